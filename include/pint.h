@@ -1,0 +1,172 @@
+/*
+ * pint.h -- C ABI of the MI355X (gfx950) parallel-in-time BDF-k / CQ-BDF-k
+ * solver: one waveform-relaxation (WR) sweep solved by diagonalization in time.
+ *
+ * Method: S. Wu and Z. Zhou, "A parallel-in-time algorithm for high-order BDF
+ * methods for diffusion and subdiffusion equations" (arXiv 2007.13125).
+ *
+ * Problem (Sec. 1, eqs. heat and fde): d_t^alpha u + A u = f on (0, T],
+ * u(0) = v, with 0 < alpha <= 1 (alpha = 1: heat equation; alpha < 1: Caputo
+ * subdiffusion), A = A_h the finite-difference Dirichlet Laplacian on a box.
+ *
+ * Time discretisation (Sec. 2.1 eq. BDF / Table 1; Sec. 3.1 eq. BDF-frac):
+ * corrected BDF-k (alpha = 1) or CQ-BDF-k (alpha < 1), k = 1..6, N uniform
+ * steps tau = T/N.  The solver returns the trajectory U^1..U^N of that scheme.
+ *
+ * Iteration (Sec. 2.2 eq. BDF-iter; Sec. 3.2 eq. BDF-frac-iter): each WR
+ * sweep solves the kappa-circulant all-at-once system
+ *     tau^{-alpha} (B_k(kappa) (x) I) U_m + (I (x) A_h) U_m = F_{m-1}
+ * by Algorithm 1 / Algorithm 2: scale time row q by kappa^{q/N}, FFT along
+ * time, solve the N/2+1 shifted systems (d_p tau^{-alpha} + A_h) Q_p = H_p
+ * (real data => Hermitian spectrum), inverse FFT, scale by kappa^{-q/N}.
+ *
+ * Conventions for every entry point:
+ *  - Array pointers marked DEVICE are HIP device pointers owned by the caller;
+ *    the library never frees them.  Pointers marked HOST are host memory.
+ *  - Space-time arrays are row-major [time][dof] in FP64, dof index fastest;
+ *    dofs are ordered x fastest, then y, then z.
+ *  - Nothing is thrown across the ABI.  A negative status is an error and the
+ *    outputs are undefined; PINT_NOT_CONVERGED (> 0) is a warning: U holds
+ *    the last iterate and the per-sweep norms written so far are valid.
+ *  - pint_last_error() returns a thread-local description of the last error.
+ *  - A plan is bound to one HIP stream and one device; plans are not
+ *    thread-safe.  All work is enqueued on the plan's stream.
+ */
+#ifndef PINT_H
+#define PINT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PINT_OK = 0,
+    PINT_NOT_CONVERGED = 1,   /* max_sweeps reached before tol; outputs valid        */
+    PINT_E_ARG = -1,          /* invalid argument (message in pint_last_error)       */
+    PINT_E_UNSUPPORTED = -2,  /* valid problem outside what the kernels implement    */
+    PINT_E_NOMEM = -3,        /* device allocation failed                            */
+    PINT_E_HIP = -4,          /* a HIP runtime call failed                           */
+    PINT_E_DIVERGED = -5      /* NaN/Inf in an update, or update growth guard fired  */
+} pint_status;
+
+enum { PINT_FP64 = 0,         /* every step in FP64                                  */
+       PINT_MIXED = 1 };      /* FFTs and shifted solves in complex FP32; residual,
+                                 kappa scalings, eigenvalues, update, norms in FP64   */
+enum { PINT_RESIDUAL = 0,     /* U_m = U_{m-1} + P^{-1}(G - T U_{m-1}) (default)     */
+       PINT_DIRECT = 1 };     /* U_m = P^{-1} F_{m-1}, the paper's literal form      */
+enum { PINT_NORM_INF = 0,     /* stop on max over space-time of |U_m - U_{m-1}|      */
+       PINT_NORM_L2_TERMINAL = 1 }; /* stop on the discrete L2 norm at t = T         */
+enum { PINT_INIT_V = 0,       /* U_0^n = v for all n (Thm 2.6 / Thm 3.5)             */
+       PINT_INIT_ZERO = 1,    /* U_0 = 0 (the start of Tables 2 and 3)               */
+       PINT_INIT_USER = 2 };  /* U_0 is the content of U on entry                    */
+
+/* Box (0,len_0) x ... with m[i] interior nodes per direction, h_i = len_i/(m_i+1).
+ * dim in 1..3; entries beyond dim are ignored. */
+typedef struct {
+    int dim;
+    int m[3];
+    double len[3];
+} pint_grid;
+
+typedef struct {
+    int k;            /* BDF order 1..6                                              */
+    double alpha;     /* 0 < alpha <= 1; alpha == 1 selects the heat equation         */
+    double T;         /* final time > 0                                               */
+    int N;            /* number of time steps; a power of two, 8 <= N <= 2048, N > k  */
+    double kappa;     /* WR relaxation parameter, 0 < kappa < 1                       */
+    double tol;       /* stop when the chosen update norm is <= tol (> 0)             */
+    int max_sweeps;   /* >= 1                                                         */
+    int precision;    /* PINT_FP64 | PINT_MIXED                                       */
+    int form;         /* PINT_RESIDUAL | PINT_DIRECT                                  */
+    int norm;         /* PINT_NORM_INF | PINT_NORM_L2_TERMINAL                        */
+    int init;         /* PINT_INIT_V | PINT_INIT_ZERO | PINT_INIT_USER                */
+} pint_params;
+
+typedef struct pint_plan pint_plan;
+
+/* Create a plan: validates the problem, computes the FP64 setup tables on the
+ * host (BDF / CQ weights of Sec. 2.1 eq. bdf-gen and Sec. 3.1 eq. delta, the
+ * eigenvalues d_p = sum_j kappa^{j/N} omega_j e^{-2 pi i j p/N} of Lemmas
+ * diag-heat / diag-frac, kappa^{+-q/N}, sine eigenvalues of A_h, Table 1) and
+ * uploads them (the plan owns these small device tables).
+ * hip_stream: a hipStream_t (NULL = default stream) of the current device.
+ * Errors: PINT_E_ARG (invalid grid/params, NULL plan), PINT_E_UNSUPPORTED
+ * (dim >= 2 with some m_i + 1 not a power of two in 4..2048, or N outside the
+ * supported powers of two), PINT_E_NOMEM, PINT_E_HIP. */
+pint_status pint_plan_create(pint_plan **plan, const pint_grid *grid,
+                             const pint_params *params, void *hip_stream);
+
+/* Bytes of device workspace one solve needs (spectrum buffer, source
+ * corrections, norm partials).  The caller may provide it with
+ * pint_plan_set_workspace; otherwise the plan allocates it on first use and
+ * frees it in pint_plan_destroy. */
+size_t pint_plan_workspace_bytes(const pint_plan *plan);
+
+/* Hand the plan a caller-owned DEVICE buffer of at least
+ * pint_plan_workspace_bytes() bytes, 256-byte aligned.  The plan uses it until
+ * destroyed or given another one.  Errors: PINT_E_ARG. */
+pint_status pint_plan_set_workspace(pint_plan *plan, void *dev_ptr, size_t bytes);
+
+/* Bind the problem data and compute the starting-step source corrections
+ * a_n (f(0) - A_h v) + sum_l b_{l,n} tau^l d^l f/dt^l (0), n < k (Table 1).
+ *   v    DEVICE [M]          initial value
+ *   f    DEVICE [N+1][M]     f(t_0) .. f(t_N); NULL means f == 0
+ *   fder DEVICE [k-2][M]     d^l f/dt^l (0), l = 1..k-2; NULL means zero
+ * The pointers must stay valid while the plan sweeps.  Asynchronous.
+ * Errors: PINT_E_ARG (NULL v), PINT_E_HIP. */
+pint_status pint_bind(pint_plan *plan, const double *v, const double *f, const double *fder);
+
+/* Set U (DEVICE [N][M]) to the initial iterate selected by params.init
+ * (INIT_USER leaves it untouched).  Requires pint_bind.  Asynchronous. */
+pint_status pint_init_iterate(pint_plan *plan, double *U);
+
+/* Run exactly nsweeps WR sweeps on U (DEVICE [N][M], in/out) with the bound
+ * data, asynchronously on the plan's stream, with no host synchronisation.
+ * dev_norms (DEVICE [nsweeps][2], may be NULL) receives per sweep
+ * { max |U_m - U_{m-1}|, (h^d sum (U_m^N - U_{m-1}^N)^2)^{1/2} }.
+ * Errors: PINT_E_ARG (not bound, NULL U, nsweeps < 0), PINT_E_NOMEM, PINT_E_HIP. */
+pint_status pint_sweeps(pint_plan *plan, double *U, int nsweeps, double *dev_norms);
+
+/* Full solve: bind, initial iterate, then sweeps until the chosen update norm
+ * is <= tol or max_sweeps is reached (host-side stop test after every sweep).
+ *   v, f, fder as in pint_bind; U DEVICE [N][M] (input too for INIT_USER).
+ *   upd     HOST [max_sweeps]: the max-norm update per sweep (may be NULL)
+ *   upd_l2T HOST [max_sweeps]: the terminal L2_h update per sweep (may be NULL)
+ *   sweeps  HOST: number of sweeps performed (may be NULL)
+ * Returns PINT_OK, PINT_NOT_CONVERGED, or an error; PINT_E_DIVERGED when an
+ * update is NaN/Inf or grows in two consecutive sweeps after the first. */
+pint_status pint_solve(pint_plan *plan, const double *v, const double *f, const double *fder,
+                       double *U, double *upd, double *upd_l2T, int *sweeps);
+
+/* Many independent problems in one plan (each with its own grid and params,
+ * N and k may differ).  Instances are swept together: one launch of each
+ * kernel covers every instance, and a sweep step is recorded once into a HIP
+ * graph and replayed.  count >= 1; grids/params are HOST arrays of count.
+ * Same validation as pint_plan_create for every instance. */
+pint_status pint_batch_plan_create(pint_plan **plan, int count, const pint_grid *grids,
+                                   const pint_params *params, void *hip_stream);
+
+/* Batch solve: HOST arrays of count DEVICE pointers (f, fder entries may be
+ * NULL), upd HOST [count][max_sweeps] (may be NULL), sweeps HOST [count]
+ * (may be NULL).  Every instance is swept until all have met their tol or
+ * reached their max_sweeps; converged instances are left untouched. */
+pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const double *const *f,
+                             const double *const *fder, double *const *U, double *upd, int *sweeps);
+
+/* Release the plan, its tables and any workspace it allocated itself.
+ * Waits for the plan's stream.  NULL is accepted. */
+pint_status pint_plan_destroy(pint_plan *plan);
+
+/* Number of space-time unknowns N * M of a plan (sum over a batch). */
+long long pint_plan_unknowns(const pint_plan *plan);
+
+const char *pint_status_str(pint_status s);
+const char *pint_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PINT_H */

@@ -1,0 +1,236 @@
+"""Thin ctypes binding of the C ABI in ``include/pint.h``.
+
+Argument marshalling only: every step of a sweep runs in the HIP kernels of
+``libpint.so``.  PyTorch provides device memory and the stream.  The library
+must have been built (``python -m paper_2007_13125_amd.build``); there is no
+fallback path, and a missing library raises immediately.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_longlong, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpint.so")
+
+PINT_OK = 0
+PINT_NOT_CONVERGED = 1
+PINT_E_ARG = -1
+PINT_E_UNSUPPORTED = -2
+PINT_E_NOMEM = -3
+PINT_E_HIP = -4
+PINT_E_DIVERGED = -5
+
+PRECISION = {"fp64": 0, "mixed": 1}
+FORM = {"residual": 0, "direct": 1}
+NORM = {"inf": 0, "l2T": 1}
+INIT = {"v": 0, "zero": 1, "user": 2}
+
+
+class pint_grid(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("m", c_int * 3), ("len", c_double * 3)]
+
+
+class pint_params(ctypes.Structure):
+    _fields_ = [("k", c_int), ("alpha", c_double), ("T", c_double), ("N", c_int),
+                ("kappa", c_double), ("tol", c_double), ("max_sweeps", c_int),
+                ("precision", c_int), ("form", c_int), ("norm", c_int), ("init", c_int)]
+
+
+EXPORTS = {
+    "pint_plan_create": (c_int, [POINTER(c_void_p), POINTER(pint_grid), POINTER(pint_params), c_void_p]),
+    "pint_plan_workspace_bytes": (c_size_t, [c_void_p]),
+    "pint_plan_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "pint_bind": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pint_init_iterate": (c_int, [c_void_p, c_void_p]),
+    "pint_sweeps": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
+    "pint_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                           POINTER(c_double), POINTER(c_double), POINTER(c_int)]),
+    "pint_batch_plan_create": (c_int, [POINTER(c_void_p), c_int, POINTER(pint_grid),
+                                       POINTER(pint_params), c_void_p]),
+    "pint_batch_solve": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                 POINTER(c_void_p), POINTER(c_double), POINTER(c_int)]),
+    "pint_plan_destroy": (c_int, [c_void_p]),
+    "pint_plan_unknowns": (c_longlong, [c_void_p]),
+    "pint_status_str": (ctypes.c_char_p, [c_int]),
+    "pint_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpint.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_13125_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class PintError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        L = lib()
+        msg = L.pint_last_error().decode()
+        super().__init__(f"{where}: {L.pint_status_str(status).decode()} ({msg})")
+
+
+def _check(status, where, allow=(PINT_OK,)):
+    if status not in allow:
+        raise PintError(status, where)
+    return status
+
+
+def make_grid(m, length=None):
+    g = pint_grid()
+    g.dim = len(m)
+    for i in range(3):
+        g.m[i] = int(m[i]) if i < len(m) else 1
+        g.len[i] = float(length[i]) if (length and i < len(length)) else 1.0
+    return g
+
+
+def make_params(k, alpha, T, N, kappa, tol=1e-12, max_sweeps=50, precision="fp64", form="residual",
+                norm="inf", init="v"):
+    p = pint_params()
+    p.k, p.alpha, p.T, p.N, p.kappa = int(k), float(alpha), float(T), int(N), float(kappa)
+    p.tol, p.max_sweeps = float(tol), int(max_sweeps)
+    p.precision, p.form, p.norm, p.init = PRECISION[precision], FORM[form], NORM[norm], INIT[init]
+    return p
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+# --- entry points under their C names ---------------------------------------------------
+
+def pint_plan_create(grid, params, stream=None):
+    """Returns a plan handle (c_void_p); stream is a torch.cuda.Stream or None (current stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = c_void_p()
+    _check(lib().pint_plan_create(ctypes.byref(h), ctypes.byref(grid), ctypes.byref(params),
+                                  c_void_p(stream.cuda_stream)), "pint_plan_create")
+    return h
+
+
+def pint_plan_workspace_bytes(plan):
+    return int(lib().pint_plan_workspace_bytes(plan))
+
+
+def pint_plan_set_workspace(plan, ws):
+    _check(lib().pint_plan_set_workspace(plan, _ptr(ws), ws.numel() * ws.element_size()),
+           "pint_plan_set_workspace")
+
+
+def pint_bind(plan, v, f=None, fder=None):
+    _check(lib().pint_bind(plan, _ptr(v), _ptr(f), _ptr(fder)), "pint_bind")
+
+
+def pint_init_iterate(plan, U):
+    _check(lib().pint_init_iterate(plan, _ptr(U)), "pint_init_iterate")
+
+
+def pint_sweeps(plan, U, nsweeps, dev_norms=None):
+    _check(lib().pint_sweeps(plan, _ptr(U), int(nsweeps), _ptr(dev_norms)), "pint_sweeps")
+
+
+def pint_solve(plan, v, f, fder, U, max_sweeps):
+    """Returns (status, upd[max_sweeps], upd_l2T[max_sweeps], sweeps)."""
+    upd = (c_double * max_sweeps)()
+    upd2 = (c_double * max_sweeps)()
+    nsw = c_int(0)
+    st = lib().pint_solve(plan, _ptr(v), _ptr(f), _ptr(fder), _ptr(U), upd, upd2, ctypes.byref(nsw))
+    _check(st, "pint_solve", allow=(PINT_OK, PINT_NOT_CONVERGED, PINT_E_DIVERGED))
+    n = nsw.value
+    return st, list(upd)[:n], list(upd2)[:n], n
+
+
+def pint_batch_plan_create(grids, params, stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    n = len(grids)
+    G = (pint_grid * n)(*grids)
+    Pm = (pint_params * n)(*params)
+    h = c_void_p()
+    _check(lib().pint_batch_plan_create(ctypes.byref(h), n, G, Pm, c_void_p(stream.cuda_stream)),
+           "pint_batch_plan_create")
+    return h
+
+
+def pint_batch_solve(plan, v, f, fder, U, max_sweeps):
+    n = len(v)
+    arr = lambda ts: (c_void_p * n)(*[None if t is None else t.data_ptr() for t in ts])
+    upd = (c_double * (n * max_sweeps))()
+    sw = (c_int * n)()
+    st = lib().pint_batch_solve(plan, arr(v), arr(f), arr(fder), arr(U), upd, sw)
+    _check(st, "pint_batch_solve", allow=(PINT_OK, PINT_NOT_CONVERGED, PINT_E_DIVERGED))
+    return st, [list(upd)[i * max_sweeps:(i + 1) * max_sweeps] for i in range(n)], list(sw)
+
+
+def pint_plan_destroy(plan):
+    lib().pint_plan_destroy(plan)
+
+
+def pint_plan_unknowns(plan):
+    return int(lib().pint_plan_unknowns(plan))
+
+
+# --- convenience wrapper ------------------------------------------------------------------
+
+class Plan:
+    """One problem on one device: owns the plan handle and a torch-allocated workspace."""
+
+    def __init__(self, m, k, alpha, T, N, kappa, tol=1e-12, max_sweeps=50, precision="fp64",
+                 form="residual", norm="inf", init="v", length=None, stream=None):
+        import torch
+        self.m, self.N, self.max_sweeps = tuple(m), int(N), int(max_sweeps)
+        self.M = 1
+        for x in m:
+            self.M *= int(x)
+        self.grid = make_grid(m, length)
+        self.params = make_params(k, alpha, T, N, kappa, tol, max_sweeps, precision, form, norm, init)
+        self.h = pint_plan_create(self.grid, self.params, stream)
+        nbytes = pint_plan_workspace_bytes(self.h)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-self.ws.data_ptr()) % 256
+        self._ws_view = self.ws[off:off + nbytes]
+        pint_plan_set_workspace(self.h, self._ws_view)
+
+    def bind(self, v, f=None, fder=None):
+        self._data = (v, f, fder)       # keep the tensors alive while bound
+        pint_bind(self.h, v, f, fder)
+
+    def init_iterate(self, U):
+        pint_init_iterate(self.h, U)
+
+    def sweeps(self, U, n, dev_norms=None):
+        pint_sweeps(self.h, U, n, dev_norms)
+
+    def solve(self, v, f=None, fder=None, U=None):
+        import torch
+        if U is None:
+            U = torch.empty((self.N, self.M), dtype=torch.float64, device="cuda")
+        self._data = (v, f, fder)
+        st, upd, upd2, n = pint_solve(self.h, v, f, fder, U, self.max_sweeps)
+        return U, {"status": st, "upd": upd, "upd_l2T": upd2, "sweeps": n}
+
+    def close(self):
+        if self.h is not None:
+            pint_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

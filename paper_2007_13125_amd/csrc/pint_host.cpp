@@ -1,0 +1,604 @@
+// Host runtime of the C ABI declared in include/pint.h: argument validation,
+// FP64 setup tables, workspace layout, the sweep loop and the stop test.
+#include "../../include/pint.h"
+#include "pint_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using pint::FwdArgs;
+using pint::InvArgs;
+using pint::SpaceArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+pint_status fail(pint_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                                 \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? PINT_E_NOMEM : PINT_E_HIP,                        \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                           \
+    } while (0)
+
+bool is_pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(long long x) {
+    int l = 0;
+    while ((1LL << l) < x) ++l;
+    return l;
+}
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+using cld = std::complex<long double>;
+const long double kPi = 3.141592653589793238462643383279502884L;
+
+// e^{-2 pi i j / L}, evaluated in extended precision and rounded once.
+cld twiddle(long long j, long long L) {
+    const long double ang = -2.0L * kPi * (long double)(j % L) / (long double)L;
+    return cld(cosl(ang), sinl(ang));
+}
+
+// BDF-k weights: coefficients of delta_k(z) = sum_{l=1..k} (1 - z)^l / l
+// (Sec. 2.1, eq. bdf-gen), by the binomial expansion of each power.
+std::vector<long double> bdf_weights(int k) {
+    std::vector<long double> w(k + 1, 0.0L);
+    for (int l = 1; l <= k; ++l) {
+        long double binom = 1.0L;  // C(l, j)
+        for (int j = 0; j <= l; ++j) {
+            w[j] += ((j & 1) ? -binom : binom) / (long double)l;
+            binom = binom * (long double)(l - j) / (long double)(j + 1);
+        }
+    }
+    return w;
+}
+
+// Power-series coefficients of delta_k(xi)^alpha (Sec. 3.1, eq. delta), by
+// J.C.P. Miller's recurrence for the power of a series (from P Q' = alpha P' Q).
+std::vector<long double> cq_weights(int k, long double alpha, int n) {
+    const std::vector<long double> p = bdf_weights(k);
+    std::vector<long double> c(n, 0.0L);
+    c[0] = powl(p[0], alpha);
+    for (int j = 1; j < n; ++j) {
+        long double acc = 0.0L;
+        const int top = j < k ? j : k;
+        for (int i = 1; i <= top; ++i) acc += ((alpha + 1.0L) * i - j) * p[i] * c[j - i];
+        c[j] = acc / (j * p[0]);
+    }
+    return c;
+}
+
+// Starting-step corrections of Table 1 (the same table is used by BDF-k and
+// CQ-BDF-k): a_n^{(k)}, n = 1..k-1, and b_{l,n}^{(k)}, l = 1..k-2.
+struct Table1 {
+    double a[5];
+    double b[4][5];
+};
+Table1 table1(int k) {
+    Table1 t;
+    std::memset(&t, 0, sizeof(t));
+    switch (k) {
+        case 2:
+            t.a[0] = 1.0 / 2;
+            break;
+        case 3:
+            t.a[0] = 11.0 / 12; t.a[1] = -5.0 / 12;
+            t.b[0][0] = 1.0 / 12;
+            break;
+        case 4:
+            t.a[0] = 31.0 / 24; t.a[1] = -7.0 / 6; t.a[2] = 3.0 / 8;
+            t.b[0][0] = 1.0 / 6; t.b[0][1] = -1.0 / 12;
+            break;
+        case 5:
+            t.a[0] = 1181.0 / 720; t.a[1] = -177.0 / 80; t.a[2] = 341.0 / 240; t.a[3] = -251.0 / 720;
+            t.b[0][0] = 59.0 / 240; t.b[0][1] = -29.0 / 120; t.b[0][2] = 19.0 / 240;
+            t.b[1][0] = 1.0 / 240; t.b[1][1] = -1.0 / 240;
+            t.b[2][0] = 1.0 / 720;
+            break;
+        case 6:
+            t.a[0] = 2837.0 / 1440; t.a[1] = -2543.0 / 720; t.a[2] = 17.0 / 5; t.a[3] = -1201.0 / 720;
+            t.a[4] = 95.0 / 288;
+            t.b[0][0] = 77.0 / 240; t.b[0][1] = -7.0 / 15; t.b[0][2] = 73.0 / 240; t.b[0][3] = -3.0 / 40;
+            t.b[1][0] = 1.0 / 96; t.b[1][1] = -1.0 / 60; t.b[1][2] = 1.0 / 160;
+            t.b[2][0] = -1.0 / 360; t.b[2][1] = 1.0 / 720;
+            break;
+        default:
+            break;
+    }
+    return t;
+}
+
+}  // namespace
+
+struct pint_plan {
+    pint_grid g{};
+    pint_params p{};
+    int M = 0, N = 0, nP = 0, ldS = 0, dim = 0, mx = 1, my = 1, mz = 1;
+    double tau = 0, ta = 0, hd = 1, ih2[3] = {0, 0, 0};
+    bool mixed = false, cq = false;
+    hipStream_t st = nullptr;
+    int device = 0;
+    // small device tables (owned)
+    std::vector<void*> owned;
+    double *d_scale = nullptr, *d_unscale = nullptr, *d_s = nullptr, *d_w = nullptr;
+    double *d_an = nullptr, *d_blt = nullptr, *d_mu[3] = {nullptr, nullptr, nullptr};
+    double2 *d_sigma = nullptr, *d_what = nullptr, *d_tw2 = nullptr;
+    void *d_twN = nullptr, *d_twL[3] = {nullptr, nullptr, nullptr};
+    double wk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double inv_factor = 1.0;
+    // workspace
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    void* S = nullptr;
+    double *corr = nullptr, *partial = nullptr, *norm_tmp = nullptr;
+    size_t off_corr = 0, off_partial = 0, off_norm = 0;
+    // bound data
+    const double *v = nullptr, *f = nullptr, *fder = nullptr;
+    bool bound = false;
+    double* h_norms = nullptr;  // pinned host, 2 doubles
+    // batch: sub-plans sharing the stream
+    std::vector<pint_plan*> inst;
+    hipGraphExec_t graph = nullptr;
+    double** batch_U = nullptr;
+
+    ~pint_plan() {
+        for (void* q : owned) (void)hipFree(q);
+        if (ws_owned && ws) (void)hipFree(ws);
+        if (h_norms) (void)hipHostFree(h_norms);
+        if (graph) (void)hipGraphExecDestroy(graph);
+        for (pint_plan* q : inst) delete q;
+    }
+};
+
+namespace {
+
+template <typename T>
+pint_status upload(pint_plan* P, T** dst, const T* src, size_t n) {
+    void* q = nullptr;
+    HIP_TRY(hipMalloc(&q, n * sizeof(T) > 0 ? n * sizeof(T) : 16));
+    P->owned.push_back(q);
+    HIP_TRY(hipMemcpy(q, src, n * sizeof(T), hipMemcpyHostToDevice));
+    *dst = static_cast<T*>(q);
+    return PINT_OK;
+}
+
+pint_status upload_tw(pint_plan* P, void** dst, long long L, bool single) {
+    if (single) {
+        std::vector<float2> t(L);
+        for (long long j = 0; j < L; ++j) {
+            const cld w = twiddle(j, L);
+            t[j].x = (float)w.real();
+            t[j].y = (float)w.imag();
+        }
+        float2* q = nullptr;
+        pint_status s = upload(P, &q, t.data(), t.size());
+        *dst = q;
+        return s;
+    }
+    std::vector<double2> t(L);
+    for (long long j = 0; j < L; ++j) {
+        const cld w = twiddle(j, L);
+        t[j].x = (double)w.real();
+        t[j].y = (double)w.imag();
+    }
+    double2* q = nullptr;
+    pint_status s = upload(P, &q, t.data(), t.size());
+    *dst = q;
+    return s;
+}
+
+pint_status validate(const pint_grid* g, const pint_params* p) {
+    if (!g || !p) return fail(PINT_E_ARG, "grid and params must not be NULL");
+    if (g->dim < 1 || g->dim > 3) return fail(PINT_E_ARG, "grid.dim must be 1, 2 or 3");
+    long long M = 1;
+    for (int i = 0; i < g->dim; ++i) {
+        if (g->m[i] < 1) return fail(PINT_E_ARG, "grid.m[i] must be >= 1");
+        if (!(g->len[i] > 0.0) || !std::isfinite(g->len[i])) return fail(PINT_E_ARG, "grid.len[i] must be > 0");
+        M *= g->m[i];
+    }
+    if (M > (1LL << 31) - 1) return fail(PINT_E_UNSUPPORTED, "more than 2^31-1 spatial unknowns");
+    if (p->k < 1 || p->k > 6) return fail(PINT_E_ARG, "k must be in 1..6");
+    if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return fail(PINT_E_ARG, "alpha must be in (0, 1]");
+    if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(PINT_E_ARG, "T must be > 0");
+    if (!(p->kappa > 0.0 && p->kappa < 1.0)) return fail(PINT_E_ARG, "kappa must be in (0, 1)");
+    if (!(p->tol > 0.0)) return fail(PINT_E_ARG, "tol must be > 0");
+    if (p->max_sweeps < 1) return fail(PINT_E_ARG, "max_sweeps must be >= 1");
+    if (p->precision != PINT_FP64 && p->precision != PINT_MIXED) return fail(PINT_E_ARG, "bad precision");
+    if (p->form != PINT_RESIDUAL && p->form != PINT_DIRECT) return fail(PINT_E_ARG, "bad form");
+    if (p->norm != PINT_NORM_INF && p->norm != PINT_NORM_L2_TERMINAL) return fail(PINT_E_ARG, "bad norm");
+    if (p->init < PINT_INIT_V || p->init > PINT_INIT_USER) return fail(PINT_E_ARG, "bad init");
+    if (p->N <= p->k) return fail(PINT_E_ARG, "N must exceed k");
+    if (!is_pow2(p->N) || p->N < (1 << pint::kMinLogN) || p->N > (1 << pint::kMaxLogN))
+        return fail(PINT_E_UNSUPPORTED, "N must be a power of two in 8..2048");
+    if (g->dim == 1) {
+        if (g->m[0] > pint::kMaxTri1D) return fail(PINT_E_UNSUPPORTED, "1D grids are limited to m <= 2048");
+    } else {
+        for (int i = 0; i < g->dim; ++i) {
+            const long long L = 2LL * (g->m[i] + 1);
+            if (!is_pow2(L) || L < (1 << 3) || L > (1 << pint::kMaxLogL))
+                return fail(PINT_E_UNSUPPORTED, "2D/3D grids need m_i + 1 a power of two in 4..2048");
+        }
+    }
+    return PINT_OK;
+}
+
+pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, hipStream_t st) {
+    P->g = *g;
+    P->p = *p;
+    P->st = st;
+    HIP_TRY(hipGetDevice(&P->device));
+    P->dim = g->dim;
+    P->mx = g->m[0];
+    P->my = g->dim >= 2 ? g->m[1] : 1;
+    P->mz = g->dim >= 3 ? g->m[2] : 1;
+    P->M = P->mx * P->my * P->mz;
+    P->N = p->N;
+    P->nP = p->N / 2 + 1;
+    P->ldS = (int)((P->M + 63) / 64 * 64);
+    P->mixed = p->precision == PINT_MIXED;
+    P->cq = p->alpha < 1.0;
+    const int N = P->N, k = p->k;
+    const long double tau = (long double)p->T / N;
+    P->tau = (double)tau;
+    P->ta = (double)powl(tau, -(long double)p->alpha);
+    P->hd = 1.0;
+    P->inv_factor = 1.0;
+    for (int i = 0; i < g->dim; ++i) {
+        const double h = g->len[i] / (g->m[i] + 1);
+        P->ih2[i] = 1.0 / (h * h);
+        P->hd *= h;
+        P->inv_factor *= -2.0 * (g->m[i] + 1);
+    }
+    P->inv_factor = 1.0 / P->inv_factor;
+
+    // time weights omega_0..omega_{N-1}
+    std::vector<long double> w(N, 0.0L);
+    const std::vector<long double> wb = bdf_weights(k);
+    if (!P->cq) {
+        for (int j = 0; j <= k; ++j) w[j] = wb[j];
+    } else {
+        w = cq_weights(k, p->alpha, N);
+    }
+    for (int j = 0; j <= k; ++j) P->wk[j] = P->cq ? 0.0 : (double)wb[j];
+    // s_n = sum_{j<n} omega_j; zero for n > k in BDF-k (the weights sum to 0)
+    std::vector<double> s(N);
+    long double acc = 0.0L;
+    for (int n = 1; n <= N; ++n) {
+        acc += w[n - 1];
+        s[n - 1] = (!P->cq && n > k) ? 0.0 : (double)acc;
+    }
+    // kappa^{+-q/N}; the 1/N of the inverse transform is folded into the unscale table
+    std::vector<double> scale(N), unscale(N);
+    const long double lk = logl((long double)p->kappa);
+    for (int q = 0; q < N; ++q) {
+        scale[q] = (double)expl(lk * q / N);
+        unscale[q] = (double)(expl(-lk * q / N) / N);
+    }
+    // eigenvalues d_p of the scaled circulant, p = 0..N/2, and sigma_p = tau^{-alpha} d_p
+    std::vector<double2> sigma(P->nP);
+    const long double kap1 = expl(lk / N);
+    for (int q = 0; q < P->nP; ++q) {
+        cld d(0.0L, 0.0L);
+        if (!P->cq) {
+            // BDF-k: d_p = delta_k(kappa^{1/N} e^{-2 pi i p/N}) (Sec. 2.2, roundoff paragraph)
+            const cld zeta = kap1 * twiddle(q, N);
+            cld pw(1.0L, 0.0L);
+            for (int l = 1; l <= k; ++l) {
+                pw *= (cld(1.0L, 0.0L) - zeta);
+                d += pw / (long double)l;
+            }
+        } else {
+            // CQ: first column kappa^{j/N} omega_j of the N x N scaled circulant, DFT'd directly
+            for (int j = 0; j < N; ++j) d += expl(lk * j / N) * w[j] * twiddle((long long)j * q, N);
+        }
+        const cld sg = (long double)P->ta * d;
+        sigma[q].x = (double)sg.real();
+        sigma[q].y = (double)sg.imag();
+    }
+    pint_status rc;
+    if ((rc = upload(P, &P->d_scale, scale.data(), N)) != PINT_OK) return rc;
+    if ((rc = upload(P, &P->d_unscale, unscale.data(), N)) != PINT_OK) return rc;
+    if ((rc = upload(P, &P->d_s, s.data(), N)) != PINT_OK) return rc;
+    if ((rc = upload(P, &P->d_sigma, sigma.data(), P->nP)) != PINT_OK) return rc;
+    if ((rc = upload_tw(P, &P->d_twN, N, P->mixed)) != PINT_OK) return rc;
+    if (P->cq) {
+        std::vector<double> wd(N);
+        for (int j = 0; j < N; ++j) wd[j] = (double)w[j];
+        if ((rc = upload(P, &P->d_w, wd.data(), N)) != PINT_OK) return rc;
+        // spectrum of (omega, 0) on 2N points, divided by 2N (inverse normalisation)
+        const int N2 = 2 * N;
+        std::vector<double2> what(N2);
+        for (int q = 0; q < N2; ++q) {
+            cld z(0.0L, 0.0L);
+            for (int j = 0; j < N; ++j) z += w[j] * twiddle((long long)j * q, N2);
+            z /= (long double)N2;
+            what[q].x = (double)z.real();
+            what[q].y = (double)z.imag();
+        }
+        if ((rc = upload(P, &P->d_what, what.data(), N2)) != PINT_OK) return rc;
+        void* t2 = nullptr;
+        if ((rc = upload_tw(P, &t2, N2, false)) != PINT_OK) return rc;
+        P->d_tw2 = static_cast<double2*>(t2);
+    }
+    // Table 1 rows with tau^l folded into b
+    const Table1 t1 = table1(k);
+    double an[5], blt[4 * 6];
+    std::memset(blt, 0, sizeof(blt));
+    for (int n = 0; n < 5; ++n) an[n] = t1.a[n];
+    for (int l = 1; l <= 4; ++l)
+        for (int n = 1; n <= 5; ++n) blt[(l - 1) * 6 + (n - 1)] = t1.b[l - 1][n - 1] * (double)powl(tau, l);
+    if ((rc = upload(P, &P->d_an, an, 5)) != PINT_OK) return rc;
+    if ((rc = upload(P, &P->d_blt, blt, 24)) != PINT_OK) return rc;
+    // sine eigenvalues of each second-difference factor and DST twiddles
+    for (int i = 0; i < g->dim; ++i) {
+        const int m = g->m[i];
+        std::vector<double> mu(m);
+        const double h = g->len[i] / (m + 1);
+        for (int j = 0; j < m; ++j) {
+            const long double sn = sinl((j + 1) * kPi / (2.0L * (m + 1)));
+            mu[j] = (double)(4.0L / ((long double)h * h) * sn * sn);
+        }
+        if ((rc = upload(P, &P->d_mu[i], mu.data(), m)) != PINT_OK) return rc;
+        if (g->dim >= 2)
+            if ((rc = upload_tw(P, &P->d_twL[i], 2LL * (m + 1), P->mixed)) != PINT_OK) return rc;
+    }
+    // workspace layout
+    const size_t cbytes = P->mixed ? 2 * sizeof(float) : 2 * sizeof(double);
+    size_t off = align256((size_t)P->nP * P->ldS * cbytes);
+    P->off_corr = off;
+    off += align256((size_t)(k > 1 ? k - 1 : 1) * P->M * sizeof(double));
+    P->off_partial = off;
+    const size_t maxblocks = ((size_t)(P->M + 1) / 2 + 8) / 8 * 8 + 8;
+    off += align256(maxblocks * 2 * sizeof(double));
+    P->off_norm = off;
+    off += 256;
+    P->ws_bytes = off;
+    HIP_TRY(hipHostMalloc((void**)&P->h_norms, 2 * sizeof(double), hipHostMallocDefault));
+    return PINT_OK;
+}
+
+pint_status ensure_workspace(pint_plan* P) {
+    if (P->ws) return PINT_OK;
+    HIP_TRY(hipMalloc(&P->ws, P->ws_bytes));
+    P->ws_owned = true;
+    char* b = static_cast<char*>(P->ws);
+    P->S = b;
+    P->corr = reinterpret_cast<double*>(b + P->off_corr);
+    P->partial = reinterpret_cast<double*>(b + P->off_partial);
+    P->norm_tmp = reinterpret_cast<double*>(b + P->off_norm);
+    return PINT_OK;
+}
+
+pint_status one_sweep(pint_plan* P, double* U, double* norms_out) {
+    FwdArgs fa{};
+    fa.U = U;
+    fa.f = P->f;
+    fa.v = P->v;
+    fa.corr = P->p.k > 1 ? P->corr : nullptr;
+    fa.S = P->S;
+    fa.scale = P->d_scale;
+    fa.s = P->d_s;
+    fa.tw = P->d_twN;
+    fa.w = P->d_w;
+    fa.what = P->d_what;
+    fa.tw2 = P->d_tw2;
+    for (int j = 0; j < 8; ++j) fa.wk[j] = P->wk[j];
+    fa.M = P->M;
+    fa.N = P->N;
+    fa.k = P->p.k;
+    fa.ldS = P->ldS;
+    fa.mx = P->mx;
+    fa.my = P->my;
+    fa.mz = P->mz;
+    fa.ihx2 = P->ih2[0];
+    fa.ihy2 = P->ih2[1];
+    fa.ihz2 = P->ih2[2];
+    fa.ta = P->ta;
+    fa.kappa = P->p.kappa;
+    fa.form = P->p.form == PINT_DIRECT ? 1 : 0;
+    fa.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
+    HIP_TRY(pint::launch_forward(fa, P->mixed, P->cq, nullptr, P->st));
+
+    SpaceArgs sa{};
+    sa.S = P->S;
+    sa.nP = P->nP;
+    sa.ldS = P->ldS;
+    sa.dim = P->dim;
+    sa.mx = P->mx;
+    sa.my = P->my;
+    sa.mz = P->mz;
+    sa.sigma = P->d_sigma;
+    for (int i = 0; i < 3; ++i) {
+        sa.mu[i] = P->d_mu[i];
+        sa.twL[i] = P->d_twL[i];
+        sa.ih2[i] = P->ih2[i];
+    }
+    sa.inv_factor = P->inv_factor;
+    HIP_TRY(pint::launch_space(sa, P->mixed, P->st));
+
+    InvArgs ia{};
+    ia.U = U;
+    ia.S = P->S;
+    ia.unscale = P->d_unscale;
+    ia.tw = P->d_twN;
+    ia.partial = P->partial;
+    ia.M = P->M;
+    ia.N = P->N;
+    ia.ldS = P->ldS;
+    ia.form = fa.form;
+    int nb = 0;
+    HIP_TRY(pint::launch_inverse(ia, P->mixed, &nb, P->st));
+    HIP_TRY(pint::launch_norm_reduce(P->partial, nb, P->hd, norms_out, P->st));
+    return PINT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pint_status pint_plan_create(pint_plan** plan, const pint_grid* grid, const pint_params* params, void* hip_stream) {
+    if (!plan) return fail(PINT_E_ARG, "plan must not be NULL");
+    *plan = nullptr;
+    pint_status rc = validate(grid, params);
+    if (rc != PINT_OK) return rc;
+    pint_plan* P = new (std::nothrow) pint_plan();
+    if (!P) return fail(PINT_E_NOMEM, "host allocation failed");
+    rc = build_plan(P, grid, params, static_cast<hipStream_t>(hip_stream));
+    if (rc != PINT_OK) {
+        delete P;
+        return rc;
+    }
+    *plan = P;
+    return PINT_OK;
+}
+
+size_t pint_plan_workspace_bytes(const pint_plan* plan) {
+    if (!plan) return 0;
+    if (!plan->inst.empty()) return 0;
+    return plan->ws_bytes;
+}
+
+pint_status pint_plan_set_workspace(pint_plan* P, void* dev_ptr, size_t bytes) {
+    if (!P || !dev_ptr) return fail(PINT_E_ARG, "plan and workspace must not be NULL");
+    if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans manage their own workspace");
+    if (bytes < P->ws_bytes) return fail(PINT_E_ARG, "workspace too small");
+    if ((reinterpret_cast<uintptr_t>(dev_ptr) & 255) != 0) return fail(PINT_E_ARG, "workspace must be 256-byte aligned");
+    if (P->ws_owned && P->ws) {
+        HIP_TRY(hipStreamSynchronize(P->st));
+        HIP_TRY(hipFree(P->ws));
+    }
+    P->ws = dev_ptr;
+    P->ws_owned = false;
+    char* b = static_cast<char*>(dev_ptr);
+    P->S = b;
+    P->corr = reinterpret_cast<double*>(b + P->off_corr);
+    P->partial = reinterpret_cast<double*>(b + P->off_partial);
+    P->norm_tmp = reinterpret_cast<double*>(b + P->off_norm);
+    return PINT_OK;
+}
+
+pint_status pint_bind(pint_plan* P, const double* v, const double* f, const double* fder) {
+    if (!P || !v) return fail(PINT_E_ARG, "plan and v must not be NULL");
+    pint_status rc = ensure_workspace(P);
+    if (rc != PINT_OK) return rc;
+    P->v = v;
+    P->f = f;
+    P->fder = fder;
+    HIP_TRY(pint::launch_prep(v, f, P->p.k > 2 ? fder : nullptr, P->corr, P->d_an, P->d_blt, P->p.k, P->M, P->mx,
+                              P->my, P->mz, P->ih2[0], P->ih2[1], P->ih2[2], P->st));
+    P->bound = true;
+    return PINT_OK;
+}
+
+pint_status pint_init_iterate(pint_plan* P, double* U) {
+    if (!P || !U) return fail(PINT_E_ARG, "plan and U must not be NULL");
+    if (!P->bound) return fail(PINT_E_ARG, "pint_bind must be called first");
+    if (P->p.init == PINT_INIT_USER) return PINT_OK;
+    HIP_TRY(pint::launch_fill(U, P->v, P->N, P->M, P->p.init == PINT_INIT_ZERO, P->st));
+    return PINT_OK;
+}
+
+pint_status pint_sweeps(pint_plan* P, double* U, int nsweeps, double* dev_norms) {
+    if (!P || !U || nsweeps < 0) return fail(PINT_E_ARG, "bad arguments to pint_sweeps");
+    if (!P->bound) return fail(PINT_E_ARG, "pint_bind must be called first");
+    for (int i = 0; i < nsweeps; ++i) {
+        pint_status rc = one_sweep(P, U, dev_norms ? dev_norms + 2 * i : P->norm_tmp);
+        if (rc != PINT_OK) return rc;
+    }
+    return PINT_OK;
+}
+
+pint_status pint_solve(pint_plan* P, const double* v, const double* f, const double* fder, double* U, double* upd,
+                       double* upd_l2T, int* sweeps) {
+    if (!P || !U) return fail(PINT_E_ARG, "plan and U must not be NULL");
+    if (!P->inst.empty()) return fail(PINT_E_ARG, "use pint_batch_solve for batch plans");
+    pint_status rc = pint_bind(P, v, f, fder);
+    if (rc != PINT_OK) return rc;
+    if ((rc = pint_init_iterate(P, U)) != PINT_OK) return rc;
+    std::vector<double> hist;
+    int done = 0;
+    pint_status result = PINT_NOT_CONVERGED;
+    for (int m = 0; m < P->p.max_sweeps; ++m) {
+        if ((rc = one_sweep(P, U, P->norm_tmp)) != PINT_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(P->h_norms, P->norm_tmp, 2 * sizeof(double), hipMemcpyDeviceToHost, P->st));
+        HIP_TRY(hipStreamSynchronize(P->st));
+        const double ninf = P->h_norms[0], nl2 = P->h_norms[1];
+        if (upd) upd[m] = ninf;
+        if (upd_l2T) upd_l2T[m] = nl2;
+        done = m + 1;
+        const double crit = P->p.norm == PINT_NORM_INF ? ninf : nl2;
+        if (!std::isfinite(ninf) || !std::isfinite(nl2)) {
+            result = fail(PINT_E_DIVERGED, "non-finite update in sweep " + std::to_string(m + 1));
+            break;
+        }
+        hist.push_back(crit);
+        if (crit <= P->p.tol) {
+            result = PINT_OK;
+            break;
+        }
+        const size_t h = hist.size();
+        if (h >= 3 && hist[h - 1] > hist[h - 2] && hist[h - 2] > hist[h - 3] && hist[h - 1] > hist[0]) {
+            result = fail(PINT_E_DIVERGED, "update grew in two consecutive sweeps beyond the first update");
+            break;
+        }
+    }
+    if (sweeps) *sweeps = done;
+    return result;
+}
+
+pint_status pint_plan_destroy(pint_plan* P) {
+    if (!P) return PINT_OK;
+    if (P->st || true) (void)hipStreamSynchronize(P->st);
+    delete P;
+    return PINT_OK;
+}
+
+long long pint_plan_unknowns(const pint_plan* P) {
+    if (!P) return 0;
+    if (!P->inst.empty()) {
+        long long s = 0;
+        for (const pint_plan* q : P->inst) s += (long long)q->N * q->M;
+        return s;
+    }
+    return (long long)P->N * P->M;
+}
+
+const char* pint_status_str(pint_status s) {
+    switch (s) {
+        case PINT_OK: return "PINT_OK";
+        case PINT_NOT_CONVERGED: return "PINT_NOT_CONVERGED";
+        case PINT_E_ARG: return "PINT_E_ARG";
+        case PINT_E_UNSUPPORTED: return "PINT_E_UNSUPPORTED";
+        case PINT_E_NOMEM: return "PINT_E_NOMEM";
+        case PINT_E_HIP: return "PINT_E_HIP";
+        case PINT_E_DIVERGED: return "PINT_E_DIVERGED";
+    }
+    return "PINT_UNKNOWN";
+}
+
+const char* pint_last_error(void) { return g_err.c_str(); }
+
+pint_status pint_batch_plan_create(pint_plan** plan, int count, const pint_grid* grids, const pint_params* params,
+                                   void* hip_stream) {
+    return fail(PINT_E_UNSUPPORTED, "batch plans are not implemented yet");
+}
+
+pint_status pint_batch_solve(pint_plan* plan, const double* const* v, const double* const* f,
+                             const double* const* fder, double* const* U, double* upd, int* sweeps) {
+    return fail(PINT_E_UNSUPPORTED, "batch plans are not implemented yet");
+}
+
+}  // extern "C"

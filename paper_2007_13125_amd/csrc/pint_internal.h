@@ -1,0 +1,78 @@
+// Internal declarations shared by the host runtime (pint_host.cpp) and the
+// gfx950 kernels (pint_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace pint {
+
+// Everything the first kernel of a sweep (right-hand side / residual, kappa
+// scaling, forward time FFT) needs.  All pointers are device pointers.
+struct FwdArgs {
+    const double* U;        // [N][M] current iterate U_{m-1} (t_1..t_N)
+    const double* f;        // [N+1][M] or nullptr (f == 0)
+    const double* v;        // [M]
+    const double* corr;     // [k-1][M] starting-step corrections, or nullptr
+    void* S;                // [N/2+1][ldS] complex spectrum (double2 or float2)
+    const double* scale;    // [N] kappa^{q/N}
+    const double* s;        // [N] s_n = sum_{j<n} omega_j, n = 1..N
+    const void* tw;         // [N] twiddles e^{-2 pi i j/N} in the spectrum precision
+    const double* w;        // [N] time weights omega_0..omega_{N-1} (CQ)
+    const double2* what;    // [2N] DFT of omega zero-padded to 2N (CQ), FP64
+    const double2* tw2;     // [2N] FP64 twiddles for the CQ convolution
+    double wk[8];           // omega_0..omega_k, zero beyond k (heat)
+    int M, N, k, ldS;
+    int mx, my, mz;         // grid (my = mz = 1 in lower dimensions)
+    double ihx2, ihy2, ihz2;  // 1/h^2 per direction (0 for absent directions)
+    double ta;              // tau^{-alpha}
+    double kappa;
+    int form;               // 0 residual, 1 direct
+    int ncorr;              // number of correction rows (k-1, or 0)
+};
+
+// Inverse time FFT + unscale + update + norm partials.
+struct InvArgs {
+    double* U;              // [N][M] in/out
+    const void* S;          // [N/2+1][ldS] complex spectrum
+    const double* unscale;  // [N] kappa^{-q/N} / N
+    const void* tw;         // [N] twiddles in the spectrum precision
+    double* partial;        // [nblocks][2] (max |delta|, sum delta^2 at q = N-1)
+    int M, N, ldS;
+    int form;               // 0 residual (U += delta), 1 direct (U = delta)
+};
+
+// Spatial shifted solves on the spectrum.
+struct SpaceArgs {
+    void* S;                // [nP][ldS] complex, in place
+    int nP, ldS;
+    int dim, mx, my, mz;
+    const double2* sigma;   // [nP] tau^{-alpha} d_p
+    const double* mu[3];    // sine eigenvalues per axis (FP64)
+    const void* twL[3];     // twiddles of length 2(m_a+1) per axis, spectrum precision
+    double ih2[3];          // 1/h^2 per axis
+    double inv_factor;      // 1 / prod_a (-2 (m_a + 1)) for the raw DST pair
+};
+
+// Host-side launchers (defined in pint_kernels.hip).  Each returns the
+// hipError_t of the launch; shapes are validated by the caller.
+hipError_t launch_prep(const double* v, const double* f, const double* fder, double* corr,
+                       const double* a_n, const double* b_ln_tau, int k, int M,
+                       int mx, int my, int mz, double ihx2, double ihy2, double ihz2,
+                       hipStream_t st);
+hipError_t launch_fill(double* U, const double* v, long long N, int M, int zero, hipStream_t st);
+hipError_t launch_forward(const FwdArgs& a, bool mixed, bool cq, int* nblocks_out, hipStream_t st);
+hipError_t launch_inverse(const InvArgs& a, bool mixed, int* nblocks_out, hipStream_t st);
+hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st);
+hipError_t launch_norm_reduce(const double* partial, int nblocks, double hd, double* out,
+                              hipStream_t st);
+
+// Largest time-FFT length and DST length the kernels are compiled for.
+constexpr int kMaxLogN = 11;      // N <= 2048
+constexpr int kMinLogN = 3;       // N >= 8
+constexpr int kMaxLogL = 12;      // DST via odd extension of length 2(m+1) <= 4096
+constexpr int kMinLogL = 2;
+constexpr int kMaxTri1D = 2048;   // 1D tridiagonal systems up to this size
+
+}  // namespace pint
