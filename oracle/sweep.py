@@ -39,13 +39,19 @@ from .cq import time_weights
 from .sequential import _as_sparse, source_terms
 
 
+def _phase(N, sign):
+    """Dense matrix exp(sign 2 pi i p q / N); p q is reduced mod N before scaling
+    (exact, by periodicity) so the phase is accurate for large N."""
+    q = np.arange(N)
+    return np.exp(sign * 2j * np.pi * (np.outer(q, q) % N) / N)
+
+
 def eigenvalues(k, alpha, N, kappa):
     """d_p, p = 0..N-1: eigenvalues of the scaled circulant (dense DFT of its first column)."""
     w = time_weights(k, alpha, N)
     j = np.arange(N)
     c = kappa ** (j / N) * w
-    Vh = np.exp(-2j * np.pi * np.outer(j, j) / N)
-    return Vh @ c
+    return _phase(N, -1) @ c
 
 
 class Problem:
@@ -65,8 +71,8 @@ class Problem:
         self.G = self.fbar + ta * np.outer(self.s, self.v)
         q = np.arange(N)
         self.scale = kappa ** (q / N)                               # Lambda^{-1} diagonal
-        self.Vinv = np.exp(-2j * np.pi * np.outer(q, q) / N) / N
-        self.V = np.exp(2j * np.pi * np.outer(q, q) / N)
+        self.Vinv = _phase(N, -1) / N
+        self.V = _phase(N, +1)
         self.d = eigenvalues(k, self.alpha, N, kappa)
 
     # -- the kappa-circulant operator and its pieces ------------------------
