@@ -352,7 +352,7 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
             mu[j] = (double)(4.0L / ((long double)h * h) * sn * sn);
         }
         if ((rc = upload(P, &P->d_mu[i], mu.data(), m)) != PINT_OK) return rc;
-        if (g->dim >= 2)
+        if (is_pow2(2LL * (m + 1)) && 2LL * (m + 1) <= (1LL << pint::kMaxLogL))
             if ((rc = upload_tw(P, &P->d_twL[i], 2LL * (m + 1), P->mixed)) != PINT_OK) return rc;
     }
     // workspace layout

@@ -552,7 +552,9 @@ __global__ __launch_bounds__(NT) void k_tri1d(SpaceArgs a) {
 // x)_k = -2i sum_t x_t sin(pi t k/(m+1)), k = 1..m, L = 2(m+1).  ROWS rows per
 // workgroup, layout [ROWS][L] in LDS.  Applying it twice multiplies by
 // -2(m+1), which the divide pass folds in.
-template <typename R, int LOGL, int ROWS, int NT>
+// With SOLVE (1D problems), the transformed row of frequency p is divided by
+// (sigma_p + mu_x) times the raw-transform factor and transformed back.
+template <typename R, int LOGL, int ROWS, int NT, bool SOLVE>
 __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) {
     using T = cx<R>;
     constexpr int L = 1 << LOGL;
@@ -580,6 +582,26 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
     }
     __syncthreads();
     lds_fft<R, LOGL, ROWS, NT, false, false, L>(sm, reinterpret_cast<const T*>(a.twL[0]));
+    if constexpr (SOLVE) {
+        for (int idx = threadIdx.x; idx < ROWS * (m + 2); idx += NT) {
+            const int b = idx / (m + 2), t = idx % (m + 2);
+            const long long g = g0 + b;
+            if (t == 0 || t == m + 1 || g >= nlines) {
+                sm[b * L + t] = zero;
+                if (t > 0 && t <= m) sm[b * L + L - t] = zero;
+                continue;
+            }
+            const double2 sg = a.sigma[g / lpp];
+            const double dre = sg.x + a.mu[0][t - 1];
+            const double inv = a.inv_factor / (dre * dre + sg.y * sg.y);
+            const T c = mk<T>((R)(dre * inv), (R)(-sg.y * inv));
+            const T z = cmul(sm[b * L + t], c);
+            sm[b * L + t] = z;
+            sm[b * L + L - t] = mk<T>(-z.x, -z.y);
+        }
+        __syncthreads();
+        lds_fft<R, LOGL, ROWS, NT, false, false, L>(sm, reinterpret_cast<const T*>(a.twL[0]));
+    }
     for (int idx = threadIdx.x; idx < ROWS * m; idx += NT) {
         const int b = idx / m, t = idx % m + 1;
         const long long g = g0 + b;
@@ -798,12 +820,12 @@ hipError_t tri1d_dispatch(const SpaceArgs& a, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
-template <typename R, int LOGL>
+template <typename R, int LOGL, bool SOLVE>
 hipError_t rows_one(const SpaceArgs& a, hipStream_t st) {
     constexpr int ROWS = rows_per_block<R>(LOGL);
     const long long nlines = (long long)a.nP * a.my * a.mz;
     const long long grid = (nlines + ROWS - 1) / ROWS;
-    hipLaunchKernelGGL((k_dst_rows<R, LOGL, ROWS, kNT>), dim3((unsigned)grid), dim3(kNT), 0, st, a, nlines);
+    hipLaunchKernelGGL((k_dst_rows<R, LOGL, ROWS, kNT, SOLVE>), dim3((unsigned)grid), dim3(kNT), 0, st, a, nlines);
     return hipGetLastError();
 }
 
@@ -818,19 +840,20 @@ hipError_t cols_one(const SpaceArgs& a, int axis, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename R, bool SOLVE = false>
 hipError_t rows_dispatch(const SpaceArgs& a, hipStream_t st) {
     switch (__builtin_ctz((unsigned)(2 * (a.mx + 1)))) {
-        case 3: return rows_one<R, 3>(a, st);
-        case 4: return rows_one<R, 4>(a, st);
-        case 5: return rows_one<R, 5>(a, st);
-        case 6: return rows_one<R, 6>(a, st);
-        case 7: return rows_one<R, 7>(a, st);
-        case 8: return rows_one<R, 8>(a, st);
-        case 9: return rows_one<R, 9>(a, st);
-        case 10: return rows_one<R, 10>(a, st);
-        case 11: return rows_one<R, 11>(a, st);
-        case 12: return rows_one<R, 12>(a, st);
+        case 2: return rows_one<R, 2, SOLVE>(a, st);
+        case 3: return rows_one<R, 3, SOLVE>(a, st);
+        case 4: return rows_one<R, 4, SOLVE>(a, st);
+        case 5: return rows_one<R, 5, SOLVE>(a, st);
+        case 6: return rows_one<R, 6, SOLVE>(a, st);
+        case 7: return rows_one<R, 7, SOLVE>(a, st);
+        case 8: return rows_one<R, 8, SOLVE>(a, st);
+        case 9: return rows_one<R, 9, SOLVE>(a, st);
+        case 10: return rows_one<R, 10, SOLVE>(a, st);
+        case 11: return rows_one<R, 11, SOLVE>(a, st);
+        case 12: return rows_one<R, 12, SOLVE>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -856,7 +879,13 @@ hipError_t cols_dispatch(const SpaceArgs& a, int axis, hipStream_t st) {
 template <typename R>
 hipError_t space_dispatch(const SpaceArgs& a, hipStream_t st) {
     hipError_t e;
-    if (a.dim == 1) return tri1d_dispatch<R>(a, st);
+    if (a.dim == 1) {
+        // m + 1 a power of two: sine transform, divide, inverse (exact per mode);
+        // otherwise the PCR/Thomas tridiagonal solver.
+        const unsigned L = 2u * (unsigned)(a.mx + 1);
+        if ((L & (L - 1)) == 0 && L <= (1u << kMaxLogL)) return rows_dispatch<R, true>(a, st);
+        return tri1d_dispatch<R>(a, st);
+    }
     if (a.dim == 2) {
         if ((e = rows_dispatch<R>(a, st)) != hipSuccess) return e;
         if ((e = cols_dispatch<R, true>(a, 1, st)) != hipSuccess) return e;

@@ -52,6 +52,10 @@ class Workload:
     fder: Optional[np.ndarray]  # [k-2, M] or None
     tol: float = 1e-12
     length: tuple = field(default=None)
+    # sine-series coefficients of the data when it is a finite sine series:
+    # {"v": c_v, "f": c_f} with c[i, j, ...] the coefficient of
+    # sin((i+1) pi x) sin((j+1) pi y) ...; f(x, t) = cos(2 pi t) * series(c_f)
+    modes: Optional[dict] = None
 
     @property
     def dim(self):
@@ -129,7 +133,7 @@ def heat2d(seed=2, m=(255, 255), N=512, k=4, T=1.0, kappa=1e-5, modes=16, tol=1e
     cf = rng.standard_normal(nm) * _decay(nm)
     v = _sine_field(m, cv)
     f, fder = _cos_profile_derivs(N, T, k, _sine_field(m, cf))
-    return Workload("heat2d", m, k, 1.0, T, N, kappa, v, f, fder, tol)
+    return Workload("heat2d", m, k, 1.0, T, N, kappa, v, f, fder, tol, modes={"v": cv, "f": cf})
 
 
 def subdiff2d(seed=3, m=(511, 511), N=1024, k=3, alpha=0.5, T=1.0, kappa=1e-4, tol=1e-12):
@@ -149,7 +153,7 @@ def heat3d(seed=5, m=(127, 127, 127), N=256, k=6, T=1.0, kappa=1e-6, modes=8, to
     cf = rng.standard_normal(nm) * _decay(nm)
     v = _sine_field(m, cv)
     f, fder = _cos_profile_derivs(N, T, k, _sine_field(m, cf))
-    return Workload("heat3d", m, k, 1.0, T, N, kappa, v, f, fder, tol)
+    return Workload("heat3d", m, k, 1.0, T, N, kappa, v, f, fder, tol, modes={"v": cv, "f": cf})
 
 
 def batch_instance(i, seed=4, m_range=(63, 1023), N_choices=(32, 64, 128, 256, 512, 1024)):

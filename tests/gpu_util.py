@@ -65,3 +65,38 @@ def oracle_iterates(w, sweeps, form="residual", init="v"):
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_modal(w, dofs):
+    """Sequential oracle in sine-mode space for data that is a finite sine series.
+
+    The sampled sines are exact eigenvectors of A_h (pinned by the eigenfunction
+    test of the oracle), so each mode evolves by the scalar scheme with
+    mu = sum_a (4/h_a^2) sin^2((i_a+1) pi h_a/2); the trajectory is assembled at
+    the requested dofs only.  Returns [N, len(dofs)]."""
+    import scipy.sparse as sp
+
+    from oracle.grid import sine_eigenvalues
+    from paper_2007_13125_amd.workloads import _cos_profile_derivs
+
+    g = Grid(w.m)
+    cv, cf = w.modes["v"], w.modes["f"]
+    shape = cv.shape
+    mus = [sine_eigenvalues(g.m[a], g.h[a])[:shape[a]] for a in range(g.dim)]
+    grids = np.meshgrid(*mus, indexing="ij")
+    mu = sum(grids).reshape(-1)
+    f, fder = _cos_profile_derivs(w.N, w.T, w.k, cf.reshape(-1))
+    C = sequential(sp.diags(mu), w.k, w.alpha, w.T, w.N, cv.reshape(-1), f, fder)
+    # basis values at the sampled dofs (x fastest ordering)
+    dofs = np.asarray(dofs)
+    coords = []
+    rem = dofs.copy()
+    for a in range(g.dim):
+        coords.append(rem % g.m[a])
+        rem = rem // g.m[a]
+    phi = np.ones((C.shape[1], len(dofs)))
+    idx = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    for a in range(g.dim):
+        ia = idx[a].reshape(-1)
+        phi *= np.sin(np.pi * np.outer(ia + 1, coords[a] + 1) / (g.m[a] + 1))
+    return C @ phi

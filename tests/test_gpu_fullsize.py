@@ -1,0 +1,69 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times: 2D heat 255^2 x 512 (BDF4, kappa = 1e-5), 3D heat 127^3 x 256
+(BDF6, kappa = 1e-6), 2D subdiffusion 511^2 x 1024 (CQ-BDF3, alpha = 1/2,
+kappa = 1e-4).  The oracle evaluates sampled outputs: per sine mode for the
+heat workloads (their data are finite sine series), the sequential stepper on
+the first time levels for the subdiffusion workload (the scheme is causal),
+plus the discrete equations themselves at sampled dofs over the whole horizon."""
+import numpy as np
+import pytest
+
+from oracle.bdf import corrected_source
+from oracle.cq import time_weights
+from paper_2007_13125_amd import workloads as wl
+from tests.gpu_util import gpu_solve, oracle_modal, oracle_solution, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_heat2d_full(precision):
+    w = wl.heat2d()
+    U, info = gpu_solve(w, precision=precision, tol=1e-13, max_sweeps=12)
+    dofs = np.random.default_rng(0).choice(w.M, 4096, replace=False)
+    ref = oracle_modal(w, dofs)
+    err = rel_l2(U[:, dofs], ref)
+    print(f"heat2d {precision}: sweeps={info['sweeps']} upd={info['upd']} rel_l2={err:.2e}", flush=True)
+    assert err <= (1e-11 if precision == "fp64" else 1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_heat3d_full(precision):
+    w = wl.heat3d()
+    U, info = gpu_solve(w, precision=precision, tol=1e-13, max_sweeps=12)
+    dofs = np.random.default_rng(1).choice(w.M, 4096, replace=False)
+    ref = oracle_modal(w, dofs)
+    err = rel_l2(U[:, dofs], ref)
+    print(f"heat3d {precision}: sweeps={info['sweeps']} upd={info['upd']} rel_l2={err:.2e}", flush=True)
+    assert err <= (1e-11 if precision == "fp64" else 1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_subdiff2d_full(precision):
+    w = wl.subdiff2d()
+    U, info = gpu_solve(w, precision=precision, tol=1e-13, max_sweeps=12)
+    print(f"subdiff2d {precision}: sweeps={info['sweeps']} upd={info['upd']}", flush=True)
+    bar = 1e-11 if precision == "fp64" else 1e-10
+    # (1) the first 32 levels against the sequential oracle (causality: they do not
+    #     depend on later levels)
+    n0 = 32
+    ref = oracle_solution(w, N=n0, T=w.T * n0 / w.N)
+    err = rel_l2(U[:n0], ref)
+    assert err <= bar, err
+    # (2) the discrete CQ-BDF3 equations at sampled dofs over all N levels:
+    #     tau^-a sum_{j<n} w_j U^{n-j} + A_h U^n = fbar_n + tau^-a s_n v
+    N, M, (mx, my) = w.N, w.M, w.m
+    tau = w.T / N
+    ta = tau ** (-w.alpha)
+    rng = np.random.default_rng(2)
+    xs, ys = rng.integers(1, mx - 1, 512), rng.integers(1, my - 1, 512)
+    d = ys * mx + xs
+    h2 = (mx + 1.0) ** 2
+    AU = h2 * (4 * U[:, d] - U[:, d - 1] - U[:, d + 1] - U[:, d - mx] - U[:, d + mx])
+    Av = h2 * (4 * w.v[d] - w.v[d - 1] - w.v[d + 1] - w.v[d - mx] - w.v[d + mx])
+    om = time_weights(w.k, w.alpha, N)
+    L = np.fft.irfft(np.fft.rfft(om, 2 * N)[:, None] * np.fft.rfft(U[:, d], 2 * N, axis=0), 2 * N, axis=0)[:N]
+    G = corrected_source(w.k, tau, np.zeros((N + 1, len(d))), Av, None) + ta * np.outer(np.cumsum(om), w.v[d])
+    res = ta * L + AU - G
+    scale = np.linalg.norm(ta * L) + np.linalg.norm(AU) + np.linalg.norm(G)
+    assert np.linalg.norm(res) / scale <= bar * 10, np.linalg.norm(res) / scale
