@@ -129,6 +129,18 @@ pint_status pint_init_iterate(pint_plan *plan, double *U);
  * Errors: PINT_E_ARG (not bound, NULL U, nsweeps < 0), PINT_E_NOMEM, PINT_E_HIP. */
 pint_status pint_sweeps(pint_plan *plan, double *U, int nsweeps, double *dev_norms);
 
+/* Instrumented sweeps for measurement: runs nsweeps sweeps exactly like
+ * pint_sweeps, with a HIP event pair recorded on the plan's stream around
+ * every kernel launch, then waits for the stream.
+ *   ms    HOST [max_slots]: average device milliseconds per sweep of each launch
+ *         slot (forward time FFT, each spatial pass, inverse time FFT, norm
+ *         reduction, in launch order)
+ *   names HOST [max_slots] (may be NULL): slot names, valid until the next call
+ *         on this thread
+ * Returns the number of slots per sweep (> 0), or a negative pint_status. */
+int pint_profile_sweeps(pint_plan *plan, double *U, int nsweeps, double *ms, const char **names,
+                        int max_slots);
+
 /* Full solve: bind, initial iterate, then sweeps until the chosen update norm
  * is <= tol or max_sweeps is reached (host-side stop test after every sweep).
  *   v, f, fder as in pint_bind; U DEVICE [N][M] (input too for INIT_USER).

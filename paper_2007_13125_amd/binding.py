@@ -43,6 +43,8 @@ EXPORTS = {
     "pint_bind": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "pint_init_iterate": (c_int, [c_void_p, c_void_p]),
     "pint_sweeps": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
+    "pint_profile_sweeps": (c_int, [c_void_p, c_void_p, c_int, POINTER(c_double),
+                                    POINTER(ctypes.c_char_p), c_int]),
     "pint_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                            POINTER(c_double), POINTER(c_double), POINTER(c_int)]),
     "pint_batch_plan_create": (c_int, [POINTER(c_void_p), c_int, POINTER(pint_grid),
@@ -143,6 +145,16 @@ def pint_sweeps(plan, U, nsweeps, dev_norms=None):
     _check(lib().pint_sweeps(plan, _ptr(U), int(nsweeps), _ptr(dev_norms)), "pint_sweeps")
 
 
+def pint_profile_sweeps(plan, U, nsweeps, max_slots=8):
+    """Returns [(slot name, average ms per sweep)] measured with HIP events."""
+    ms = (c_double * max_slots)()
+    names = (ctypes.c_char_p * max_slots)()
+    n = lib().pint_profile_sweeps(plan, _ptr(U), int(nsweeps), ms, names, max_slots)
+    if n < 0:
+        raise PintError(n, "pint_profile_sweeps")
+    return [(names[i].decode(), ms[i]) for i in range(min(n, max_slots))]
+
+
 def pint_solve(plan, v, f, fder, U, max_sweeps):
     """Returns (status, upd[max_sweeps], upd_l2T[max_sweeps], sweeps)."""
     upd = (c_double * max_sweeps)()
@@ -215,6 +227,9 @@ class Plan:
 
     def sweeps(self, U, n, dev_norms=None):
         pint_sweeps(self.h, U, n, dev_norms)
+
+    def profile(self, U, n):
+        return pint_profile_sweeps(self.h, U, n)
 
     def solve(self, v, f=None, fder=None, U=None):
         import torch

@@ -382,7 +382,43 @@ pint_status ensure_workspace(pint_plan* P) {
     return PINT_OK;
 }
 
-pint_status one_sweep(pint_plan* P, double* U, double* norms_out) {
+// Optional per-launch timing: an event pair around every kernel launch of a
+// sweep, on the plan's stream.
+struct Profiler {
+    std::vector<std::string> names;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;   // one pair per launch
+    std::vector<int> slot;                               // launch -> slot index
+    int cursor = 0;                                      // slot index within the sweep
+    hipStream_t st = nullptr;
+    hipError_t begin(const char* name) {
+        if (cursor >= (int)names.size()) names.push_back(name);
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+        ev.push_back({a, b});
+        slot.push_back(cursor);
+        return hipEventRecord(a, st);
+    }
+    hipError_t end() {
+        ++cursor;
+        return hipEventRecord(ev.back().second, st);
+    }
+    ~Profiler() {
+        for (auto& e : ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+};
+
+#define PROF_BEGIN(prof, name) \
+    if (prof) HIP_TRY((prof)->begin(name))
+#define PROF_END(prof) \
+    if (prof) HIP_TRY((prof)->end())
+
+pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof = nullptr) {
+    if (prof) prof->cursor = 0;
     FwdArgs fa{};
     fa.U = U;
     fa.f = P->f;
@@ -410,7 +446,9 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out) {
     fa.kappa = P->p.kappa;
     fa.form = P->p.form == PINT_DIRECT ? 1 : 0;
     fa.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
+    PROF_BEGIN(prof, P->cq ? "forward_cq_rhs_tfft" : "forward_rhs_tfft");
     HIP_TRY(pint::launch_forward(fa, P->mixed, P->cq, nullptr, P->st));
+    PROF_END(prof);
 
     SpaceArgs sa{};
     sa.S = P->S;
@@ -427,7 +465,11 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out) {
         sa.ih2[i] = P->ih2[i];
     }
     sa.inv_factor = P->inv_factor;
-    HIP_TRY(pint::launch_space(sa, P->mixed, P->st));
+    for (int i = 0; i < pint::space_pass_count(sa); ++i) {
+        PROF_BEGIN(prof, pint::space_pass_name(sa, i));
+        HIP_TRY(pint::launch_space_pass(sa, P->mixed, i, P->st));
+        PROF_END(prof);
+    }
 
     InvArgs ia{};
     ia.U = U;
@@ -440,8 +482,12 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out) {
     ia.ldS = P->ldS;
     ia.form = fa.form;
     int nb = 0;
+    PROF_BEGIN(prof, "inverse_tfft_update");
     HIP_TRY(pint::launch_inverse(ia, P->mixed, &nb, P->st));
+    PROF_END(prof);
+    PROF_BEGIN(prof, "norm_reduce");
     HIP_TRY(pint::launch_norm_reduce(P->partial, nb, P->hd, norms_out, P->st));
+    PROF_END(prof);
     return PINT_OK;
 }
 
@@ -519,6 +565,46 @@ pint_status pint_sweeps(pint_plan* P, double* U, int nsweeps, double* dev_norms)
         if (rc != PINT_OK) return rc;
     }
     return PINT_OK;
+}
+
+int pint_profile_sweeps(pint_plan* P, double* U, int nsweeps, double* ms, const char** names, int max_slots) {
+    if (!P || !U || nsweeps < 1 || !ms || max_slots < 1) {
+        fail(PINT_E_ARG, "bad arguments to pint_profile_sweeps");
+        return PINT_E_ARG;
+    }
+    if (!P->bound) {
+        fail(PINT_E_ARG, "pint_bind must be called first");
+        return PINT_E_ARG;
+    }
+    Profiler prof;
+    prof.st = P->st;
+    for (int i = 0; i < nsweeps; ++i) {
+        pint_status rc = one_sweep(P, U, P->norm_tmp, &prof);
+        if (rc != PINT_OK) return rc;
+    }
+    hipError_t e = hipStreamSynchronize(P->st);
+    if (e != hipSuccess) {
+        fail(PINT_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+        return PINT_E_HIP;
+    }
+    const int ns = (int)prof.names.size();
+    for (int j = 0; j < max_slots; ++j) ms[j] = 0.0;
+    for (size_t i = 0; i < prof.ev.size(); ++i) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, prof.ev[i].first, prof.ev[i].second);
+        if (e != hipSuccess) {
+            fail(PINT_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+            return PINT_E_HIP;
+        }
+        if (prof.slot[i] < max_slots) ms[prof.slot[i]] += t;
+    }
+    static thread_local std::vector<std::string> keep;
+    keep = prof.names;
+    for (int j = 0; j < ns && j < max_slots; ++j) {
+        ms[j] /= nsweeps;
+        if (names) names[j] = keep[j].c_str();
+    }
+    return ns;
 }
 
 pint_status pint_solve(pint_plan* P, const double* v, const double* f, const double* fder, double* U, double* upd,

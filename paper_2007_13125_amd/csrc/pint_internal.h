@@ -65,6 +65,9 @@ hipError_t launch_fill(double* U, const double* v, long long N, int M, int zero,
 hipError_t launch_forward(const FwdArgs& a, bool mixed, bool cq, int* nblocks_out, hipStream_t st);
 hipError_t launch_inverse(const InvArgs& a, bool mixed, int* nblocks_out, hipStream_t st);
 hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st);
+int space_pass_count(const SpaceArgs& a);
+const char* space_pass_name(const SpaceArgs& a, int pass);
+hipError_t launch_space_pass(const SpaceArgs& a, bool mixed, int pass, hipStream_t st);
 hipError_t launch_norm_reduce(const double* partial, int nblocks, double hd, double* out,
                               hipStream_t st);
 

@@ -876,26 +876,33 @@ hipError_t cols_dispatch(const SpaceArgs& a, int axis, hipStream_t st) {
     }
 }
 
+// The spatial solve is a short sequence of passes over the spectrum:
+//   1D: one pass (sine transform + divide + inverse, or PCR/Thomas);
+//   2D: DST-x rows, DST-y + divide + inverse DST-y, DST-x rows;
+//   3D: DST-x, DST-y, DST-z + divide + inverse, DST-y, DST-x.
+int pass_count(const SpaceArgs& a) { return a.dim == 1 ? 1 : (a.dim == 2 ? 3 : 5); }
+
+bool dst1d(const SpaceArgs& a) {
+    const unsigned L = 2u * (unsigned)(a.mx + 1);
+    return (L & (L - 1)) == 0 && L <= (1u << kMaxLogL);
+}
+
+const char* pass_name(const SpaceArgs& a, int i) {
+    if (a.dim == 1) return dst1d(a) ? "dst_x_solve" : "tridiag_pcr_thomas";
+    if (a.dim == 2) return i == 1 ? "dst_y_solve" : "dst_x";
+    static const char* n3[5] = {"dst_x", "dst_y", "dst_z_solve", "dst_y", "dst_x"};
+    return n3[i];
+}
+
 template <typename R>
-hipError_t space_dispatch(const SpaceArgs& a, hipStream_t st) {
-    hipError_t e;
-    if (a.dim == 1) {
-        // m + 1 a power of two: sine transform, divide, inverse (exact per mode);
-        // otherwise the PCR/Thomas tridiagonal solver.
-        const unsigned L = 2u * (unsigned)(a.mx + 1);
-        if ((L & (L - 1)) == 0 && L <= (1u << kMaxLogL)) return rows_dispatch<R, true>(a, st);
-        return tri1d_dispatch<R>(a, st);
+hipError_t space_pass(const SpaceArgs& a, int i, hipStream_t st) {
+    if (a.dim == 1) return dst1d(a) ? rows_dispatch<R, true>(a, st) : tri1d_dispatch<R>(a, st);
+    if (a.dim == 2) return i == 1 ? cols_dispatch<R, true>(a, 1, st) : rows_dispatch<R>(a, st);
+    switch (i) {
+        case 1: case 3: return cols_dispatch<R, false>(a, 1, st);
+        case 2: return cols_dispatch<R, true>(a, 2, st);
+        default: return rows_dispatch<R>(a, st);
     }
-    if (a.dim == 2) {
-        if ((e = rows_dispatch<R>(a, st)) != hipSuccess) return e;
-        if ((e = cols_dispatch<R, true>(a, 1, st)) != hipSuccess) return e;
-        return rows_dispatch<R>(a, st);
-    }
-    if ((e = rows_dispatch<R>(a, st)) != hipSuccess) return e;
-    if ((e = cols_dispatch<R, false>(a, 1, st)) != hipSuccess) return e;
-    if ((e = cols_dispatch<R, true>(a, 2, st)) != hipSuccess) return e;
-    if ((e = cols_dispatch<R, false>(a, 1, st)) != hipSuccess) return e;
-    return rows_dispatch<R>(a, st);
 }
 
 }  // namespace
@@ -923,8 +930,20 @@ hipError_t launch_inverse(const InvArgs& a, bool mixed, int* nb, hipStream_t st)
     return mixed ? inv_dispatch<float>(a, nb, st) : inv_dispatch<double>(a, nb, st);
 }
 
+int space_pass_count(const SpaceArgs& a) { return pass_count(a); }
+
+const char* space_pass_name(const SpaceArgs& a, int pass) { return pass_name(a, pass); }
+
+hipError_t launch_space_pass(const SpaceArgs& a, bool mixed, int pass, hipStream_t st) {
+    return mixed ? space_pass<float>(a, pass, st) : space_pass<double>(a, pass, st);
+}
+
 hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st) {
-    return mixed ? space_dispatch<float>(a, st) : space_dispatch<double>(a, st);
+    for (int i = 0; i < pass_count(a); ++i) {
+        const hipError_t e = launch_space_pass(a, mixed, i, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_norm_reduce(const double* partial, int nb, double hd, double* out, hipStream_t st) {
