@@ -47,89 +47,128 @@ template <bool INV, typename T> __device__ __forceinline__ T twmul(T a, T w) {
     return INV ? cmulc(a, w) : cmul(a, w);
 }
 
-// Natural-order 4-point DFT in place; forward uses e^{-2 pi i rs/4}.
-template <bool INV, typename T> __device__ __forceinline__ void dft4(T& v0, T& v1, T& v2, T& v3) {
-    const T t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = csub(v1, v3);
-    const T mit3 = mk<T>(t3.y, -t3.x);  // -i * t3
-    v0 = cadd(t0, t2);
-    v2 = csub(t0, t2);
-    if (!INV) {
-        v1 = cadd(t1, mit3);
-        v3 = csub(t1, mit3);
-    } else {
-        v1 = csub(t1, mit3);
-        v3 = cadd(t1, mit3);
+// e^{-2 pi i j/16}, j = 0..15 (real and imaginary parts), for the
+// constant twiddles inside the in-register radix-8 and radix-16 DFTs.
+__device__ __constant__ double kW16re[16] = {
+    1.0, 0.92387953251128674, 0.70710678118654757, 0.38268343236508978,
+    0.0, -0.38268343236508978, -0.70710678118654757, -0.92387953251128674,
+    -1.0, -0.92387953251128674, -0.70710678118654757, -0.38268343236508978,
+    0.0, 0.38268343236508978, 0.70710678118654757, 0.92387953251128674};
+__device__ __constant__ double kW16im[16] = {
+    0.0, -0.38268343236508978, -0.70710678118654757, -0.92387953251128674,
+    -1.0, -0.92387953251128674, -0.70710678118654757, -0.38268343236508978,
+    0.0, 0.38268343236508978, 0.70710678118654757, 0.92387953251128674,
+    1.0, 0.92387953251128674, 0.70710678118654757, 0.38268343236508978};
+
+// Natural-order R-point DFT of v[0..R) in registers (R = 2, 4, 8, 16), by
+// recursive decimation in time; forward uses e^{-2 pi i rs/R}, INV e^{+...}.
+template <int R, bool INV, typename T> struct SmallDft {
+    __device__ __forceinline__ static void run(T* v) {
+        constexpr int H = R / 2;
+        T e[H], o[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        SmallDft<H, INV, T>::run(e);
+        SmallDft<H, INV, T>::run(o);
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            using E = decltype(T::x);
+            T t = o[k];
+            if (k != 0) {
+                const int j = k * (16 / R);
+                const E wr = (E)kW16re[j], wi = INV ? -(E)kW16im[j] : (E)kW16im[j];
+                if (2 * k == H) {            // +-i
+                    t = INV ? mk<T>(-t.y, t.x) : mk<T>(t.y, -t.x);
+                } else {
+                    t = mk<T>(t.x * wr - t.y * wi, t.x * wi + t.y * wr);
+                }
+            }
+            v[k] = cadd(e[k], t);
+            v[k + H] = csub(e[k], t);
+        }
+    }
+};
+template <bool INV, typename T> struct SmallDft<1, INV, T> {
+    __device__ __forceinline__ static void run(T*) {}
+};
+
+// Radix schedule of a 2^LOGL transform: the fewest stages of radix <= 16,
+// with the factors of two spread evenly over them (512 = 8 x 8 x 8,
+// 1024 = 16 x 8 x 8, 32 = 8 x 4, ...).
+constexpr int stage_count(int logl) { return (logl + 3) / 4; }
+constexpr int stage_radix(int logl, int st) {
+    return 1 << (logl / stage_count(logl) + (st < logl % stage_count(logl) ? 1 : 0));
+}
+
+// One Stockham stage of radix RAD and span Ns: butterfly j (with k = j mod Ns)
+// reads x[j + r L/RAD], multiplies by w^{r k L/(RAD Ns)}, takes the RAD-point
+// DFT and writes position (j - k) RAD + k + r Ns.  Inputs of all butterflies
+// are read into registers before a barrier, so the stage works in place.
+template <typename R, int LOGL, int RAD, int B, int NT, bool INV, bool BFAST, int BSTR>
+__device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw, int Ns) {
+    using T = cx<R>;
+    constexpr int L = 1 << LOGL;
+    constexpr int Q = L / RAD;
+    constexpr int TOT = Q * B;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    auto at = [](int t, int b) { return BFAST ? t * B + b : b * BSTR + t; };
+    T v[PER][RAD];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = tid + i * NT;
+        if ((TOT % NT) == 0 || idx < TOT) {
+            const int j = BFAST ? idx / B : idx % Q;
+            const int b = BFAST ? idx % B : idx / Q;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) v[i][r] = s[at(j + r * Q, b)];
+            const int k = j & (Ns - 1);
+            if (Ns > 1) {
+                const int e = k * (Q / Ns);
+#pragma unroll
+                for (int r = 1; r < RAD; ++r) v[i][r] = twmul<INV>(v[i][r], tw[r * e]);
+            }
+            SmallDft<RAD, INV, T>::run(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = tid + i * NT;
+        if ((TOT % NT) == 0 || idx < TOT) {
+            const int j = BFAST ? idx / B : idx % Q;
+            const int b = BFAST ? idx % B : idx / Q;
+            const int k = j & (Ns - 1);
+            const int base = (j - k) * RAD + k;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) s[at(base + r * Ns, b)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename R, int LOGL, int ST, int B, int NT, bool INV, bool BFAST, int BSTR>
+__device__ __forceinline__ void fft_stages(cx<R>* s, const cx<R>* __restrict__ tw, int Ns) {
+    if constexpr (ST < stage_count(LOGL)) {
+        constexpr int RAD = stage_radix(LOGL, ST);
+        fft_stage<R, LOGL, RAD, B, NT, INV, BFAST, BSTR>(s, tw, Ns);
+        fft_stages<R, LOGL, ST + 1, B, NT, INV, BFAST, BSTR>(s, tw, Ns * RAD);
     }
 }
 
 // Batched in-place complex FFT of length L = 2^LOGL on B sequences held in LDS.
 // Element t of sequence b sits at s[t*B + b] when BFAST, else at s[b*BSTR + t].
-// Stockham auto-sort formulation: radix-4 stages with span Ns = 1, 4, 16, ...,
-// then one radix-2 stage when LOGL is odd; each radix-4 stage reads its
-// butterfly inputs into registers, synchronises, and writes the outputs to
-// their sorted positions, so no second buffer is needed.
+// Stockham auto-sort formulation with radix-16/8 stages (radix-4/2 for the
+// remainder), in-register sub-DFTs, and one LDS round trip per stage.
 // Forward: X_k = sum_t x_t e^{-2 pi i t k/L}; INV uses e^{+...} and no 1/L.
 // tw[j] = e^{-2 pi i j/L}, j < L (global, read through the caches).
 // Every thread of the block must call it; it ends with a barrier.
 template <typename R, int LOGL, int B, int NT, bool INV, bool BFAST, int BSTR>
 __device__ void lds_fft(cx<R>* s, const cx<R>* __restrict__ tw) {
-    using T = cx<R>;
-    constexpr int L = 1 << LOGL;
-    constexpr int Q = L / 4;
-    constexpr int TOT4 = Q * B;
-    constexpr int PER4 = (TOT4 + NT - 1) / NT;
-    const int tid = threadIdx.x;
-    auto at = [](int t, int b) { return BFAST ? t * B + b : b * BSTR + t; };
-    int Ns = 1;
-#pragma unroll 1
-    for (int st = 0; st < LOGL / 2; ++st) {
-        T v[PER4][4];
-#pragma unroll
-        for (int i = 0; i < PER4; ++i) {
-            const int idx = tid + i * NT;
-            if ((TOT4 % NT) == 0 || idx < TOT4) {
-                const int j = BFAST ? idx / B : idx % Q;
-                const int b = BFAST ? idx % B : idx / Q;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[i][r] = s[at(j + r * Q, b)];
-                const int k = j & (Ns - 1);
-                const int e = k * (Q / Ns);
-                v[i][1] = twmul<INV>(v[i][1], tw[e]);
-                v[i][2] = twmul<INV>(v[i][2], tw[2 * e]);
-                v[i][3] = twmul<INV>(v[i][3], tw[3 * e]);
-                dft4<INV>(v[i][0], v[i][1], v[i][2], v[i][3]);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < PER4; ++i) {
-            const int idx = tid + i * NT;
-            if ((TOT4 % NT) == 0 || idx < TOT4) {
-                const int j = BFAST ? idx / B : idx % Q;
-                const int b = BFAST ? idx % B : idx / Q;
-                const int k = j & (Ns - 1);
-                const int base = ((j - k) << 2) + k;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) s[at(base + r * Ns, b)] = v[i][r];
-            }
-        }
-        __syncthreads();
-        Ns <<= 2;
-    }
-    if constexpr ((LOGL & 1) != 0) {
-        // Last stage, span L/2: butterfly j reads and writes positions j, j + L/2.
-        constexpr int H = L / 2;
-        constexpr int TOT2 = H * B;
-        for (int idx = tid; idx < TOT2; idx += NT) {
-            const int j = BFAST ? idx / B : idx % H;
-            const int b = BFAST ? idx % B : idx / H;
-            const T v0 = s[at(j, b)];
-            const T v1 = twmul<INV>(s[at(j + H, b)], tw[j]);
-            s[at(j, b)] = cadd(v0, v1);
-            s[at(j + H, b)] = csub(v0, v1);
-        }
-        __syncthreads();
-    }
+    fft_stages<R, LOGL, 0, B, NT, INV, BFAST, BSTR>(s, tw, 1);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip.  Give
@@ -140,6 +179,18 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
     return (bid & 7) * per + (bid >> 3);
 }
 
+// Tile order for kernels with a y-stencil: inside each XCD's contiguous range
+// of tiles, walk down columns (R tiles per grid row) so that the tiles holding
+// a tile's y-neighbours are fetched by workgroups running at the same time on
+// the same XCD, and the neighbour loads hit in its L2.
+__device__ __forceinline__ int xcd_tile_columns(int bid, int nblocks, int R) {
+    const int per = nblocks >> 3;
+    const int s = bid >> 3, base = (bid & 7) * per;
+    const int rows = R > 0 ? per / R : 0;
+    if (rows > 1 && s < rows * R) return base + (s % rows) * R + s / rows;
+    return base + s;
+}
+
 __device__ __forceinline__ double nanmax(double a, double b) {
     if (a != a) return a;
     if (b != b) return b;
@@ -148,50 +199,57 @@ __device__ __forceinline__ double nanmax(double a, double b) {
 
 // Hermitian split of the packed-pair spectrum Z = FFT(a + i b):
 // A_p = (Z_p + conj Z_{N-p})/2,  B_p = (Z_p - conj Z_{N-p})/(2i).
+// Lane (p, e) produces dof d0 + e of row p, so consecutive lanes store
+// consecutive complex values (one contiguous W-value segment per row).
 template <typename R, int N, int B, int NT>
 __device__ __forceinline__ void store_half_spectrum(const cx<R>* sm, cx<R>* S, int ldS, int d0, int M) {
     constexpr int NP = N / 2 + 1;
-    for (int idx = threadIdx.x; idx < NP * B; idx += NT) {
-        const int b = idx % B, p = idx / B;
+    constexpr int W = 2 * B;
+    for (int idx = threadIdx.x; idx < NP * W; idx += NT) {
+        const int e = idx % W, p = idx / W;
+        const int b = e >> 1;
         const cx<R> zp = sm[p * B + b];
         const cx<R> zn = sm[((N - p) & (N - 1)) * B + b];
         const R h = R(0.5);
-        const cx<R> A = mk<cx<R>>((zp.x + zn.x) * h, (zp.y - zn.y) * h);
-        const cx<R> Bv = mk<cx<R>>((zp.y + zn.y) * h, (zn.x - zp.x) * h);
-        const int e = d0 + 2 * b;
-        cx<R>* row = S + (size_t)p * ldS;
-        if (e < M) row[e] = A;
-        if (e + 1 < M) row[e + 1] = Bv;
+        const cx<R> out = (e & 1) ? mk<cx<R>>((zp.y + zn.y) * h, (zn.x - zp.x) * h)
+                                  : mk<cx<R>>((zp.x + zn.x) * h, (zp.y - zn.y) * h);
+        if (d0 + e < M) S[(size_t)p * ldS + d0 + e] = out;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Forward kernel, BDF-k (alpha = 1).  One workgroup per tile of W consecutive
-// dofs and all N time rows.  Thread (dl, ch) owns dof d0+dl and a contiguous
-// chunk of rows, so the k+1-tap time stencil runs on a register window.
+// dofs and all N time rows.
 //   residual: r_n = f_n + corr_n + tau^{-1} s_n v - tau^{-1} sum_{j<n} w_j U^{n-j} - A_h U^n
 //   direct:   F_n = f_n + corr_n + tau^{-1} s_n v + kappa tau^{-1} sum_{j=n..k} w_j U^{N+n-j}
 // (eqs. BDF-k-matrix and BDF-k-F with the kappa sum over j = n..k).
+// Phase A issues every global load of the tile at once: the U tile goes to LDS
+// (FP64), while the source terms and the stencil neighbours outside the tile
+// (y, z, and x at the tile edges) are folded into one register per element.
+// Phase B adds the parts read from LDS (time stencil, centre, x neighbours
+// inside the tile) and scales by kappa^{q/N}.  The FFT buffer then reuses the
+// LDS of the U tile.
 template <typename R, int LOGN, int W, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_heat(FwdArgs a) {
     constexpr int N = 1 << LOGN;
     constexpr int B = W / 2;
-    constexpr int NCH = NT / W;
-    constexpr int RPC = N / NCH;
-    static_assert(NCH >= 1 && RPC >= 1 && NCH * RPC == N, "tile shape");
-    __shared__ cx<R> sm[N * B];
-    R* smr = reinterpret_cast<R*>(sm);
+    constexpr int PER = N * W / NT;
+    static_assert(PER * NT == N * W, "tile shape");
+    __shared__ double su[N * W];
+    cx<R>* sm = reinterpret_cast<cx<R>*>(su);
+    R* smr = reinterpret_cast<R*>(su);
 
     const int ntiles = (a.M + W - 1) / W;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = a.my > 1 ? xcd_tile_columns(blockIdx.x, gridDim.x, (a.mx + W - 1) / W)
+                              : xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
     const int d0 = tile * W;
     const int tid = threadIdx.x;
-    const int dl = tid % W, ch = tid / W;
+    const int dl = tid % W;            // the dof of every element this thread owns
     const int d = d0 + dl;
     const bool valid = d < a.M;
-    const int q0 = ch * RPC;
     const size_t M = a.M;
+    const bool resid = a.form == 0;
 
     int x = 0, y = 0, z = 0;
     if (valid) {
@@ -203,54 +261,72 @@ __global__ __launch_bounds__(NT) void k_fwd_heat(FwdArgs a) {
     const bool hxm = x > 0, hxp = x < a.mx - 1;
     const bool hym = y > 0, hyp = y < a.my - 1;
     const bool hzm = z > 0, hzp = z < a.mz - 1;
+    const bool exm = hxm && dl == 0, exp_ = hxp && dl == W - 1;   // x neighbours outside the tile
     const size_t sy = (size_t)a.mx, sz = (size_t)a.mx * a.my;
-    const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
-    const double vv = valid ? a.v[d] : 0.0;
-    const bool resid = a.form == 0;
+    const double vt = valid ? a.ta * a.v[d] : 0.0;
 
-    double win[7];
-    win[0] = 0.0;
+    double g[PER];
 #pragma unroll
-    for (int j = 1; j < 7; ++j) {
-        const int l = q0 + 1 - j;
-        win[j] = (resid && valid && l >= 1 && j <= a.k) ? a.U[(size_t)(l - 1) * M + d] : 0.0;
+    for (int i = 0; i < PER; ++i) {
+        const int q = (tid + i * NT) / W;
+        const size_t o = (size_t)q * M + d;
+        double u = 0.0, acc = 0.0;
+        if (valid) {
+            u = a.U[o];
+            acc = vt * a.s[q];
+            if (a.f) acc += a.f[o + M];
+            if (resid) {
+                double nb = 0.0;
+                if (exm) nb += a.ihx2 * a.U[o - 1];
+                if (exp_) nb += a.ihx2 * a.U[o + 1];
+                if (hym) nb += a.ihy2 * a.U[o - sy];
+                if (hyp) nb += a.ihy2 * a.U[o + sy];
+                if (hzm) nb += a.ihz2 * a.U[o - sz];
+                if (hzp) nb += a.ihz2 * a.U[o + sz];
+                acc += nb;
+            }
+        }
+        su[q * W + dl] = u;
+        g[i] = acc;
     }
-    for (int q = q0; q < q0 + RPC; ++q) {
+    if (valid && a.ncorr > 0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = (tid + i * NT) / W;
+            if (q < a.ncorr) g[i] += a.corr[(size_t)q * M + d];
+        }
+    }
+    __syncthreads();
+
+    const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
+    const bool ixm = hxm && dl > 0, ixp = hxp && dl < W - 1;     // x neighbours inside the tile
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = (tid + i * NT) / W;
         const int n = q + 1;
         double r = 0.0;
         if (valid) {
-            const size_t o = (size_t)q * M + d;
-            double g = a.ta * a.s[q] * vv;
-            if (a.f) g += a.f[o + M];
-            if (n - 1 < a.ncorr) g += a.corr[(size_t)(n - 1) * M + d];
+            r = g[i];
             if (resid) {
-                const double u = a.U[o];
-                win[0] = u;
-                double ts = 0.0;
-#pragma unroll
-                for (int j = 0; j < 7; ++j) ts += a.wk[j] * win[j];
+                const double u = su[q * W + dl];
+                double ts = a.wk[0] * u;
+                for (int j = 1; j <= a.k && j <= q; ++j) ts += a.wk[j] * su[(q - j) * W + dl];
                 double au = diag * u;
-                if (hxm) au -= a.ihx2 * a.U[o - 1];
-                if (hxp) au -= a.ihx2 * a.U[o + 1];
-                if (hym) au -= a.ihy2 * a.U[o - sy];
-                if (hyp) au -= a.ihy2 * a.U[o + sy];
-                if (hzm) au -= a.ihz2 * a.U[o - sz];
-                if (hzp) au -= a.ihz2 * a.U[o + sz];
-                r = g - a.ta * ts - au;
-            } else {
-                r = g;
-                if (n <= a.k) {
-                    double acc = 0.0;
-                    for (int j = n; j <= a.k; ++j) acc += a.wk[j] * a.U[(size_t)(a.N + n - j - 1) * M + d];
-                    r += a.kappa * a.ta * acc;
-                }
+                if (ixm) au -= a.ihx2 * su[q * W + dl - 1];
+                if (ixp) au -= a.ihx2 * su[q * W + dl + 1];
+                r -= a.ta * ts + au;
+            } else if (n <= a.k) {
+                double acc = 0.0;
+                for (int j = n; j <= a.k; ++j) acc += a.wk[j] * su[(a.N + n - j - 1) * W + dl];
+                r += a.kappa * a.ta * acc;
             }
             r *= a.scale[q];
         }
-        smr[q * W + dl] = (R)r;
-#pragma unroll
-        for (int j = 6; j > 0; --j) win[j] = win[j - 1];
+        g[i] = r;
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) smr[tid + i * NT] = (R)g[i];
     __syncthreads();
     lds_fft<R, LOGN, B, NT, false, true, 0>(sm, reinterpret_cast<const cx<R>*>(a.tw));
     store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<cx<R>*>(a.S), a.ldS, d0, a.M);
@@ -331,15 +407,17 @@ __global__ __launch_bounds__(NT) void k_fwd_cq(FwdArgs a) {
 // ---------------------------------------------------------------------------
 // Inverse kernel: rebuild the packed-pair spectrum Z_p = A_p + i B_p for all
 // p from the retained half (conjugate symmetry), inverse FFT in LDS, scale row
-// q by kappa^{-q/N}/N (FP64), update U and accumulate the update norms.
+// q by kappa^{-q/N}/N (FP64), update U and accumulate the update norms.  The
+// U tile is fetched into registers together with the spectrum, so both
+// streams of loads are in flight at once.
 template <typename R, int LOGN, int W, int NT>
 __global__ __launch_bounds__(NT) void k_inv(InvArgs a) {
     constexpr int N = 1 << LOGN;
     constexpr int B = W / 2;
     constexpr int NP = N / 2 + 1;
-    constexpr int NCH = NT / W;
-    constexpr int RPC = N / NCH;
-    static_assert(NCH * RPC == N, "tile shape");
+    constexpr int PER = N * W / NT;
+    constexpr int PERS = (NP * B + NT - 1) / NT;
+    static_assert(PER * NT == N * W, "tile shape");
     __shared__ cx<R> sm[N * B];
     __shared__ double red[2][NT / 64];
     R* smr = reinterpret_cast<R*>(sm);
@@ -355,38 +433,59 @@ __global__ __launch_bounds__(NT) void k_inv(InvArgs a) {
         return;
     }
     const int d0 = tile * W;
+    const int dl = tid % W;
+    const int d = d0 + dl;
+    const bool valid = d < a.M;
+    const size_t M = a.M;
     const cx<R>* S = reinterpret_cast<const cx<R>*>(a.S);
-    for (int idx = tid; idx < NP * B; idx += NT) {
-        const int b = idx % B, p = idx / B;
-        const int e = d0 + 2 * b;
-        const cx<R>* row = S + (size_t)p * a.ldS;
-        cx<R> A = mk<cx<R>>(0, 0), Bv = mk<cx<R>>(0, 0);
-        if (e < a.M) A = row[e];
-        if (e + 1 < a.M) Bv = row[e + 1];
-        if (p == 0 || p == N / 2) {
-            A.y = 0;
-            Bv.y = 0;
+
+    cx<R> sa[PERS], sb[PERS];
+#pragma unroll
+    for (int i = 0; i < PERS; ++i) {
+        const int idx = tid + i * NT;
+        sa[i] = mk<cx<R>>(0, 0);
+        sb[i] = mk<cx<R>>(0, 0);
+        if (idx < NP * B) {
+            const int b = idx % B, p = idx / B;
+            const int e = d0 + 2 * b;
+            const cx<R>* row = S + (size_t)p * a.ldS;
+            if (e < a.M) sa[i] = row[e];
+            if (e + 1 < a.M) sb[i] = row[e + 1];
         }
-        sm[p * B + b] = mk<cx<R>>(A.x - Bv.y, A.y + Bv.x);
-        if (p > 0 && p < N / 2) sm[(N - p) * B + b] = mk<cx<R>>(A.x + Bv.y, Bv.x - A.y);
+    }
+    double u[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = (tid + i * NT) / W;
+        u[i] = valid ? a.U[(size_t)q * M + d] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < PERS; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < NP * B) {
+            const int b = idx % B, p = idx / B;
+            cx<R> A = sa[i], Bv = sb[i];
+            if (p == 0 || p == N / 2) {
+                A.y = 0;
+                Bv.y = 0;
+            }
+            sm[p * B + b] = mk<cx<R>>(A.x - Bv.y, A.y + Bv.x);
+            if (p > 0 && p < N / 2) sm[(N - p) * B + b] = mk<cx<R>>(A.x + Bv.y, Bv.x - A.y);
+        }
     }
     __syncthreads();
     lds_fft<R, LOGN, B, NT, true, true, 0>(sm, reinterpret_cast<const cx<R>*>(a.tw));
 
-    const int dl = tid % W, ch = tid / W;
-    const int d = d0 + dl;
-    const bool valid = d < a.M;
-    const size_t M = a.M;
     double mx = 0.0, s2 = 0.0;
     bool bad = false;
     if (valid) {
-        for (int q = ch * RPC; q < (ch + 1) * RPC; ++q) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = (tid + i * NT) / W;
             const double delta = (double)smr[q * W + dl] * a.unscale[q];
-            const size_t o = (size_t)q * M + d;
-            const double old = a.U[o];
-            const double un = a.form == 0 ? old + delta : delta;
-            const double upd = un - old;
-            a.U[o] = un;
+            const double un = a.form == 0 ? u[i] + delta : delta;
+            const double upd = un - u[i];
+            a.U[(size_t)q * M + d] = un;
             const double au = fabs(upd);
             bad |= !(au <= 1.0e300);
             mx = au > mx ? au : mx;
@@ -564,21 +663,32 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
     const long long g0 = (long long)blockIdx.x * ROWS;
     T* S = reinterpret_cast<T*>(a.S);
     const T zero = mk<T>((R)0, (R)0);
-    for (int idx = threadIdx.x; idx < ROWS * L; idx += NT) {
-        const int b = idx / L, t = idx % L;
-        const long long g = g0 + b;
-        T val = zero;
-        if (g < nlines) {
-            const long long p = g / lpp, rr = g % lpp;
-            const T* row = S + p * a.ldS + rr * m;
-            if (t >= 1 && t <= m) {
-                val = row[t - 1];
-            } else if (t >= m + 2) {
-                const T w = row[L - t - 1];
-                val = mk<T>(-w.x, -w.y);
-            }
+    // every element of the ROWS x m block is loaded once (all loads in flight),
+    // then written to its two odd-extension positions t and L - t
+    constexpr int PER = (ROWS * (L / 2 - 1) + NT - 1) / NT;
+    T val[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x + i * NT;
+        val[i] = zero;
+        if (idx < ROWS * m) {
+            const int b = idx / m, t = idx % m;
+            const long long g = g0 + b;
+            if (g < nlines) val[i] = S[(g / lpp) * a.ldS + (g % lpp) * m + t];
         }
-        sm[b * L + t] = val;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x + i * NT;
+        if (idx < ROWS * m) {
+            const int b = idx / m, t = idx % m + 1;
+            sm[b * L + t] = val[i];
+            sm[b * L + L - t] = mk<T>(-val[i].x, -val[i].y);
+        }
+    }
+    if (threadIdx.x < 2 * ROWS) {
+        const int b = threadIdx.x >> 1;
+        sm[b * L + ((threadIdx.x & 1) ? m + 1 : 0)] = zero;
     }
     __syncthreads();
     lds_fft<R, LOGL, ROWS, NT, false, false, L>(sm, reinterpret_cast<const T*>(a.twL[0]));
@@ -634,18 +744,31 @@ __global__ __launch_bounds__(NT) void k_dst_cols(SpaceArgs a, int axis) {
     const long long base = (long long)p * a.ldS + x0 + (axis == 1 ? (long long)o * a.mx * a.my : (long long)o * a.mx);
     T* S = reinterpret_cast<T*>(a.S);
     const T zero = mk<T>((R)0, (R)0);
-    for (int idx = threadIdx.x; idx < L * W; idx += NT) {
-        const int t = idx / W, w = idx % W;
-        T val = zero;
-        if (x0 + w < a.mx) {
-            if (t >= 1 && t <= m) {
-                val = S[base + (t - 1) * st + w];
-            } else if (t >= m + 2) {
-                const T u = S[base + (L - t - 1) * st + w];
-                val = mk<T>(-u.x, -u.y);
-            }
+    // one load per element of the m x W block (rows of W contiguous values), all
+    // in flight, then written to positions t and L - t of the odd extension
+    constexpr int PER = ((L / 2 - 1) * W + NT - 1) / NT;
+    T val[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x + i * NT;
+        val[i] = zero;
+        if (idx < m * W) {
+            const int t = idx / W, w = idx % W;
+            if (x0 + w < a.mx) val[i] = S[base + t * st + w];
         }
-        sm[t * W + w] = val;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x + i * NT;
+        if (idx < m * W) {
+            const int t = idx / W + 1, w = idx % W;
+            sm[t * W + w] = val[i];
+            sm[(L - t) * W + w] = mk<T>(-val[i].x, -val[i].y);
+        }
+    }
+    if (threadIdx.x < 2 * W) {
+        const int w = threadIdx.x % W;
+        sm[((threadIdx.x < W) ? 0 : m + 1) * W + w] = zero;
     }
     __syncthreads();
     const T* tw = reinterpret_cast<const T*>(a.twL[axis]);
@@ -711,8 +834,20 @@ __global__ void k_fill(double* __restrict__ U, const double* __restrict__ v, lon
 
 // ---------------------------------------------------------------------------
 // Tile widths: the LDS tile of the time FFT holds N x W values of type R.
+// The forward kernel stages the FP64 U tile (N x W doubles) in LDS.
+#ifndef PINT_TIME_TILE_BYTES
+#define PINT_TIME_TILE_BYTES 65536
+#endif
 template <typename R> constexpr int time_tile(int logn) {
-    const int w = 65536 / ((1 << logn) * (int)sizeof(R));
+    const int w = PINT_TIME_TILE_BYTES / ((1 << logn) * 8);
+    return w > 64 ? 64 : (w < 2 ? 2 : w);
+}
+// The forward kernel's LDS holds the FP64 U tile, later reused as the FFT buffer.
+#ifndef PINT_FWD_TILE_BYTES
+#define PINT_FWD_TILE_BYTES 32768
+#endif
+constexpr int fwd_tile(int logn) {
+    const int w = PINT_FWD_TILE_BYTES / ((1 << logn) * 8);
     return w > 64 ? 64 : (w < 2 ? 2 : w);
 }
 constexpr int cq_tile(int logn) {
@@ -732,6 +867,7 @@ template <typename R> constexpr int cols_per_block(int logl) {
 }
 
 constexpr int kNT = 256;
+#define N_OF(logn) (1 << (logn))
 constexpr int kNTcq = 512;  // the length-2N FP64 convolution FFT needs more lanes per tile
 
 template <typename R, int LOGN>
@@ -743,11 +879,12 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
         if (nb) *nb = grid;
         hipLaunchKernelGGL((k_fwd_cq<R, LOGN, W, kNTcq>), dim3(grid), dim3(kNTcq), 0, st, a);
     } else {
-        constexpr int W = time_tile<R>(LOGN);
+        constexpr int W = fwd_tile(LOGN);
+        constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
         const int ntiles = (a.M + W - 1) / W;
         const int grid = ((ntiles + 7) / 8) * 8;
         if (nb) *nb = grid;
-        hipLaunchKernelGGL((k_fwd_heat<R, LOGN, W, kNT>), dim3(grid), dim3(kNT), 0, st, a);
+        hipLaunchKernelGGL((k_fwd_heat<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a);
     }
     return hipGetLastError();
 }
