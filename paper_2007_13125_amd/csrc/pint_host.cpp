@@ -126,6 +126,7 @@ struct pint_plan {
     pint_grid g{};
     pint_params p{};
     int M = 0, N = 0, nP = 0, ldS = 0, dim = 0, mx = 1, my = 1, mz = 1;
+    int mxp = 16, Mp = 16;  // padded spectrum rows (multiple of 16 slots) and slots per plane
     double tau = 0, ta = 0, hd = 1, ih2[3] = {0, 0, 0};
     bool mixed = false, cq = false;
     hipStream_t st = nullptr;
@@ -209,7 +210,7 @@ pint_status validate(const pint_grid* g, const pint_params* p) {
         if (!(g->len[i] > 0.0) || !std::isfinite(g->len[i])) return fail(PINT_E_ARG, "grid.len[i] must be > 0");
         M *= g->m[i];
     }
-    if (M > (1LL << 31) - 1) return fail(PINT_E_UNSUPPORTED, "more than 2^31-1 spatial unknowns");
+    if (M > (1LL << 30)) return fail(PINT_E_UNSUPPORTED, "more than 2^30 spatial unknowns");
     if (p->k < 1 || p->k > 6) return fail(PINT_E_ARG, "k must be in 1..6");
     if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return fail(PINT_E_ARG, "alpha must be in (0, 1]");
     if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(PINT_E_ARG, "T must be > 0");
@@ -247,7 +248,9 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     P->M = P->mx * P->my * P->mz;
     P->N = p->N;
     P->nP = p->N / 2 + 1;
-    P->ldS = (int)((P->M + 63) / 64 * 64);
+    P->mxp = (P->mx + 15) / 16 * 16;
+    P->Mp = P->mxp * P->my * P->mz;
+    P->ldS = (int)((P->Mp + 63) / 64 * 64);
     P->mixed = p->precision == PINT_MIXED;
     P->cq = p->alpha < 1.0;
     const int N = P->N, k = p->k;
@@ -361,7 +364,7 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     P->off_corr = off;
     off += align256((size_t)(k > 1 ? k - 1 : 1) * P->M * sizeof(double));
     P->off_partial = off;
-    const size_t maxblocks = ((size_t)(P->M + 1) / 2 + 8) / 8 * 8 + 8;
+    const size_t maxblocks = ((size_t)(P->Mp + 1) / 2 + 8) / 8 * 8 + 8;
     off += align256(maxblocks * 2 * sizeof(double));
     P->off_norm = off;
     off += 256;
@@ -436,6 +439,8 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof
     fa.N = P->N;
     fa.k = P->p.k;
     fa.ldS = P->ldS;
+    fa.mxp = P->mxp;
+    fa.Mp = P->Mp;
     fa.mx = P->mx;
     fa.my = P->my;
     fa.mz = P->mz;
@@ -454,6 +459,7 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof
     sa.S = P->S;
     sa.nP = P->nP;
     sa.ldS = P->ldS;
+    sa.mxp = P->mxp;
     sa.dim = P->dim;
     sa.mx = P->mx;
     sa.my = P->my;
@@ -480,6 +486,9 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof
     ia.M = P->M;
     ia.N = P->N;
     ia.ldS = P->ldS;
+    ia.mx = P->mx;
+    ia.mxp = P->mxp;
+    ia.Mp = P->Mp;
     ia.form = fa.form;
     int nb = 0;
     PROF_BEGIN(prof, "inverse_tfft_update");

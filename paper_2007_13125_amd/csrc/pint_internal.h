@@ -8,6 +8,11 @@
 
 namespace pint {
 
+// Spectrum layout: every frequency plane stores the grid with its x-rows
+// padded to mxp = mx rounded up to a multiple of 16 slots (so rows start on a
+// 128-byte boundary); slot P of a plane holds dof (P / mxp) * mx + P % mxp when
+// P % mxp < mx, and zero otherwise.  Planes are ldS >= Mp = mxp * my * mz apart.
+
 // Everything the first kernel of a sweep (right-hand side / residual, kappa
 // scaling, forward time FFT) needs.  All pointers are device pointers.
 struct FwdArgs {
@@ -24,6 +29,7 @@ struct FwdArgs {
     const double2* tw2;     // [2N] FP64 twiddles for the CQ convolution
     double wk[8];           // omega_0..omega_k, zero beyond k (heat)
     int M, N, k, ldS;
+    int mxp, Mp;            // spectrum layout: rows of mxp >= mx slots, Mp slots per plane
     int mx, my, mz;         // grid (my = mz = 1 in lower dimensions)
     double ihx2, ihy2, ihz2;  // 1/h^2 per direction (0 for absent directions)
     double ta;              // tau^{-alpha}
@@ -40,6 +46,7 @@ struct InvArgs {
     const void* tw;         // [N] twiddles in the spectrum precision
     double* partial;        // [nblocks][2] (max |delta|, sum delta^2 at q = N-1)
     int M, N, ldS;
+    int mx, mxp, Mp;        // grid row length and the padded spectrum layout
     int form;               // 0 residual (U += delta), 1 direct (U = delta)
 };
 
@@ -47,6 +54,7 @@ struct InvArgs {
 struct SpaceArgs {
     void* S;                // [nP][ldS] complex, in place
     int nP, ldS;
+    int mxp;                // slots per spectrum row (grid rows padded to a multiple of 16)
     int dim, mx, my, mz;
     const double2* sigma;   // [nP] tau^{-alpha} d_p
     const double* mu[3];    // sine eigenvalues per axis (FP64)

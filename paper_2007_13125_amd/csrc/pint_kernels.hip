@@ -14,6 +14,7 @@
 // Spectra are [N/2+1][ldS] complex in FP64 or (mixed mode) FP32, dof fastest.
 #include "pint_internal.h"
 
+#include <algorithm>
 #include <cstdint>
 
 namespace pint {
@@ -107,7 +108,36 @@ constexpr int stage_radix(int logl, int st) {
 // reads x[j + r L/RAD], multiplies by w^{r k L/(RAD Ns)}, takes the RAD-point
 // DFT and writes position (j - k) RAD + k + r Ns.  Inputs of all butterflies
 // are read into registers before a barrier, so the stage works in place.
-template <typename R, int LOGL, int RAD, int B, int NT, bool INV, bool BFAST, int BSTR>
+// Twiddles w^r, r = 1..RAD-1, of one butterfly from the table entries for
+// w^e, w^{2e}, w^{4e}, w^{8e} (log2 RAD loads instead of RAD - 1); every other
+// power is a product of at most three of them.
+template <int RAD, bool INV, typename T>
+__device__ __forceinline__ void apply_twiddles(T* v, const T* __restrict__ tw, int e) {
+    T p[4];
+#pragma unroll
+    for (int i = 0; (1 << i) < RAD; ++i) p[i] = tw[(1 << i) * e];
+#pragma unroll
+    for (int r = 1; r < RAD; ++r) {
+        T w = mk<T>(1, 0);
+        bool first = true;
+#pragma unroll
+        for (int i = 0; (1 << i) < RAD; ++i)
+            if (r & (1 << i)) {
+                w = first ? p[i] : cmul(w, p[i]);
+                first = false;
+            }
+        v[r] = twmul<INV>(v[r], w);
+    }
+}
+
+// One Stockham stage of radix RAD and span Ns: butterfly j (with k = j mod Ns)
+// reads x[j + r L/RAD], multiplies by w^{r k L/(RAD Ns)}, takes the RAD-point
+// DFT and writes position (j - k) RAD + k + r Ns.  Inputs of all butterflies
+// are read into registers before a barrier, so the stage works in place.
+// Sequence layouts: BFAST s[t*B + b]; otherwise s[b*BSTR + t + (t >> PADSH)]
+// (one padding slot per 2^PADSH elements keeps the strided writes of the first
+// stage off a single LDS bank group; PADSH = 0 means no padding).
+template <typename R, int LOGL, int RAD, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH>
 __device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw, int Ns) {
     using T = cx<R>;
     constexpr int L = 1 << LOGL;
@@ -115,7 +145,7 @@ __device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw
     constexpr int TOT = Q * B;
     constexpr int PER = (TOT + NT - 1) / NT;
     const int tid = threadIdx.x;
-    auto at = [](int t, int b) { return BFAST ? t * B + b : b * BSTR + t; };
+    auto at = [](int t, int b) { return BFAST ? t * B + b : b * BSTR + t + (PADSH ? (t >> PADSH) : 0); };
     T v[PER][RAD];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -126,11 +156,7 @@ __device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw
 #pragma unroll
             for (int r = 0; r < RAD; ++r) v[i][r] = s[at(j + r * Q, b)];
             const int k = j & (Ns - 1);
-            if (Ns > 1) {
-                const int e = k * (Q / Ns);
-#pragma unroll
-                for (int r = 1; r < RAD; ++r) v[i][r] = twmul<INV>(v[i][r], tw[r * e]);
-            }
+            if (Ns > 1) apply_twiddles<RAD, INV>(v[i], tw, k * (Q / Ns));
             SmallDft<RAD, INV, T>::run(v[i]);
         }
     }
@@ -150,12 +176,12 @@ __device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw
     __syncthreads();
 }
 
-template <typename R, int LOGL, int ST, int B, int NT, bool INV, bool BFAST, int BSTR>
+template <typename R, int LOGL, int ST, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH>
 __device__ __forceinline__ void fft_stages(cx<R>* s, const cx<R>* __restrict__ tw, int Ns) {
     if constexpr (ST < stage_count(LOGL)) {
         constexpr int RAD = stage_radix(LOGL, ST);
-        fft_stage<R, LOGL, RAD, B, NT, INV, BFAST, BSTR>(s, tw, Ns);
-        fft_stages<R, LOGL, ST + 1, B, NT, INV, BFAST, BSTR>(s, tw, Ns * RAD);
+        fft_stage<R, LOGL, RAD, B, NT, INV, BFAST, BSTR, PADSH>(s, tw, Ns);
+        fft_stages<R, LOGL, ST + 1, B, NT, INV, BFAST, BSTR, PADSH>(s, tw, Ns * RAD);
     }
 }
 
@@ -166,9 +192,16 @@ __device__ __forceinline__ void fft_stages(cx<R>* s, const cx<R>* __restrict__ t
 // Forward: X_k = sum_t x_t e^{-2 pi i t k/L}; INV uses e^{+...} and no 1/L.
 // tw[j] = e^{-2 pi i j/L}, j < L (global, read through the caches).
 // Every thread of the block must call it; it ends with a barrier.
-template <typename R, int LOGL, int B, int NT, bool INV, bool BFAST, int BSTR>
+template <typename R, int LOGL, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH = 0>
 __device__ void lds_fft(cx<R>* s, const cx<R>* __restrict__ tw) {
-    fft_stages<R, LOGL, 0, B, NT, INV, BFAST, BSTR>(s, tw, 1);
+    fft_stages<R, LOGL, 0, B, NT, INV, BFAST, BSTR, PADSH>(s, tw, 1);
+}
+
+// Padding shift for sequences stored element-contiguously: one slot per
+// first-stage radix group.
+constexpr int pad_shift(int logl) {
+    const int r = stage_radix(logl, 0);
+    return r == 16 ? 4 : (r == 8 ? 3 : (r == 4 ? 2 : 1));
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip.  Give
@@ -189,6 +222,13 @@ __device__ __forceinline__ int xcd_tile_columns(int bid, int nblocks, int R) {
     const int rows = R > 0 ? per / R : 0;
     if (rows > 1 && s < rows * R) return base + (s % rows) * R + s / rows;
     return base + s;
+}
+
+// dof index of padded spectrum slot P, or -1 for a padding slot
+__device__ __forceinline__ int slot_dof(int P, int mx, int mxp, int Mp) {
+    if (P >= Mp) return -1;
+    const int x = P % mxp;
+    return x < mx ? (P / mxp) * mx + x : -1;
 }
 
 __device__ __forceinline__ double nanmax(double a, double b) {
@@ -239,15 +279,15 @@ __global__ __launch_bounds__(NT) void k_fwd_heat(FwdArgs a) {
     cx<R>* sm = reinterpret_cast<cx<R>*>(su);
     R* smr = reinterpret_cast<R*>(su);
 
-    const int ntiles = (a.M + W - 1) / W;
-    const int tile = a.my > 1 ? xcd_tile_columns(blockIdx.x, gridDim.x, (a.mx + W - 1) / W)
-                              : xcd_tile(blockIdx.x, gridDim.x);
+    const int ntiles = (a.Mp + W - 1) / W;
+    const int tile = (a.my > 1 && a.mxp >= W) ? xcd_tile_columns(blockIdx.x, gridDim.x, a.mxp / W)
+                                              : xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
-    const int d0 = tile * W;
+    const int d0 = tile * W;           // first spectrum slot of the tile
     const int tid = threadIdx.x;
-    const int dl = tid % W;            // the dof of every element this thread owns
-    const int d = d0 + dl;
-    const bool valid = d < a.M;
+    const int dl = tid % W;            // the slot of every element this thread owns
+    const int d = slot_dof(d0 + dl, a.mx, a.mxp, a.Mp);
+    const bool valid = d >= 0;
     const size_t M = a.M;
     const bool resid = a.form == 0;
 
@@ -329,7 +369,7 @@ __global__ __launch_bounds__(NT) void k_fwd_heat(FwdArgs a) {
     for (int i = 0; i < PER; ++i) smr[tid + i * NT] = (R)g[i];
     __syncthreads();
     lds_fft<R, LOGN, B, NT, false, true, 0>(sm, reinterpret_cast<const cx<R>*>(a.tw));
-    store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<cx<R>*>(a.S), a.ldS, d0, a.M);
+    store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<cx<R>*>(a.S), a.ldS, d0, a.Mp);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_fwd_cq(FwdArgs a) {
     __shared__ double2 cb[N2 * B];
     double* cbr = reinterpret_cast<double*>(cb);
 
-    const int ntiles = (a.M + W - 1) / W;
+    const int ntiles = (a.Mp + W - 1) / W;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
     const int d0 = tile * W;
@@ -356,8 +396,8 @@ __global__ __launch_bounds__(NT) void k_fwd_cq(FwdArgs a) {
     const size_t M = a.M;
 
     for (int idx = tid; idx < N * W; idx += NT) {
-        const int q = idx / W, dl = idx % W, d = d0 + dl;
-        cbr[idx] = d < a.M ? a.U[(size_t)q * M + d] : 0.0;
+        const int q = idx / W, d = slot_dof(d0 + idx % W, a.mx, a.mxp, a.Mp);
+        cbr[idx] = d >= 0 ? a.U[(size_t)q * M + d] : 0.0;
     }
     for (int idx = N * W + tid; idx < N2 * W; idx += NT) cbr[idx] = 0.0;
     __syncthreads();
@@ -373,10 +413,10 @@ __global__ __launch_bounds__(NT) void k_fwd_cq(FwdArgs a) {
     cx<R>* sm = reinterpret_cast<cx<R>*>(cb + (resid ? N * B : 0));
     R* smr = reinterpret_cast<R*>(sm);
     for (int idx = tid; idx < N * W; idx += NT) {
-        const int q = idx / W, dl = idx % W, d = d0 + dl;
+        const int q = idx / W, dl = idx % W, d = slot_dof(d0 + dl, a.mx, a.mxp, a.Mp);
         const int n = q + 1;
         double r = 0.0;
-        if (d < a.M) {
+        if (d >= 0) {
             const size_t o = (size_t)q * M + d;
             double g = a.ta * a.s[q] * a.v[d];
             if (a.f) g += a.f[o + M];
@@ -401,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_fwd_cq(FwdArgs a) {
     }
     __syncthreads();
     lds_fft<R, LOGN, B, NT, false, true, 0>(sm, reinterpret_cast<const cx<R>*>(a.tw));
-    store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<cx<R>*>(a.S), a.ldS, d0, a.M);
+    store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<cx<R>*>(a.S), a.ldS, d0, a.Mp);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,7 +463,7 @@ __global__ __launch_bounds__(NT) void k_inv(InvArgs a) {
     R* smr = reinterpret_cast<R*>(sm);
     const int tid = threadIdx.x;
 
-    const int ntiles = (a.M + W - 1) / W;
+    const int ntiles = (a.Mp + W - 1) / W;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) {
         if (tid == 0) {
@@ -434,8 +474,8 @@ __global__ __launch_bounds__(NT) void k_inv(InvArgs a) {
     }
     const int d0 = tile * W;
     const int dl = tid % W;
-    const int d = d0 + dl;
-    const bool valid = d < a.M;
+    const int d = slot_dof(d0 + dl, a.mx, a.mxp, a.Mp);
+    const bool valid = d >= 0;
     const size_t M = a.M;
     const cx<R>* S = reinterpret_cast<const cx<R>*>(a.S);
 
@@ -449,8 +489,8 @@ __global__ __launch_bounds__(NT) void k_inv(InvArgs a) {
             const int b = idx % B, p = idx / B;
             const int e = d0 + 2 * b;
             const cx<R>* row = S + (size_t)p * a.ldS;
-            if (e < a.M) sa[i] = row[e];
-            if (e + 1 < a.M) sb[i] = row[e + 1];
+            if (e < a.Mp) sa[i] = row[e];
+            if (e + 1 < a.Mp) sb[i] = row[e + 1];
         }
     }
     double u[PER];
@@ -657,68 +697,82 @@ template <typename R, int LOGL, int ROWS, int NT, bool SOLVE>
 __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) {
     using T = cx<R>;
     constexpr int L = 1 << LOGL;
-    __shared__ T sm[ROWS * L];
+    constexpr int PS = pad_shift(LOGL);
+    constexpr int LP = L + (L >> PS);            // padded sequence stride
+    __shared__ T sm[ROWS * LP];
+    auto ix = [](int b, int t) { return b * LP + t + (t >> PS); };
     const int m = a.mx;
     const int lpp = a.my * a.mz;
-    const long long g0 = (long long)blockIdx.x * ROWS;
     T* S = reinterpret_cast<T*>(a.S);
     const T zero = mk<T>((R)0, (R)0);
-    // every element of the ROWS x m block is loaded once (all loads in flight),
-    // then written to its two odd-extension positions t and L - t
+    const long long ngroups = (nlines + ROWS - 1) / ROWS;
+    // Persistent workgroups: each walks groups of ROWS rows, and the loads of
+    // its next group are issued (into registers) before the transform of the
+    // current one, so memory traffic overlaps the LDS work.
     constexpr int PER = (ROWS * (L / 2 - 1) + NT - 1) / NT;
     T val[PER];
+    auto fetch = [&](long long grp) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int idx = threadIdx.x + i * NT;
-        val[i] = zero;
-        if (idx < ROWS * m) {
-            const int b = idx / m, t = idx % m;
-            const long long g = g0 + b;
-            if (g < nlines) val[i] = S[(g / lpp) * a.ldS + (g % lpp) * m + t];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int idx = threadIdx.x + i * NT;
-        if (idx < ROWS * m) {
-            const int b = idx / m, t = idx % m + 1;
-            sm[b * L + t] = val[i];
-            sm[b * L + L - t] = mk<T>(-val[i].x, -val[i].y);
-        }
-    }
-    if (threadIdx.x < 2 * ROWS) {
-        const int b = threadIdx.x >> 1;
-        sm[b * L + ((threadIdx.x & 1) ? m + 1 : 0)] = zero;
-    }
-    __syncthreads();
-    lds_fft<R, LOGL, ROWS, NT, false, false, L>(sm, reinterpret_cast<const T*>(a.twL[0]));
-    if constexpr (SOLVE) {
-        for (int idx = threadIdx.x; idx < ROWS * (m + 2); idx += NT) {
-            const int b = idx / (m + 2), t = idx % (m + 2);
-            const long long g = g0 + b;
-            if (t == 0 || t == m + 1 || g >= nlines) {
-                sm[b * L + t] = zero;
-                if (t > 0 && t <= m) sm[b * L + L - t] = zero;
-                continue;
+        for (int i = 0; i < PER; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            val[i] = zero;
+            if (idx < ROWS * m) {
+                const int b = idx / m, t = idx % m;
+                const long long g = grp * ROWS + b;
+                if (g < nlines) val[i] = S[(g / lpp) * a.ldS + (g % lpp) * a.mxp + t];
             }
-            const double2 sg = a.sigma[g / lpp];
-            const double dre = sg.x + a.mu[0][t - 1];
-            const double inv = a.inv_factor / (dre * dre + sg.y * sg.y);
-            const T c = mk<T>((R)(dre * inv), (R)(-sg.y * inv));
-            const T z = cmul(sm[b * L + t], c);
-            sm[b * L + t] = z;
-            sm[b * L + L - t] = mk<T>(-z.x, -z.y);
+        }
+    };
+    long long grp = blockIdx.x;
+    if (grp < ngroups) fetch(grp);
+    for (; grp < ngroups; grp += gridDim.x) {
+        const long long g0 = grp * ROWS;
+        // odd extension: x_t at t and -x_t at L - t, zeros at 0 and m + 1
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            if (idx < ROWS * m) {
+                const int b = idx / m, t = idx % m + 1;
+                sm[ix(b, t)] = val[i];
+                sm[ix(b, L - t)] = mk<T>(-val[i].x, -val[i].y);
+            }
+        }
+        if (threadIdx.x < 2 * ROWS) {
+            const int b = threadIdx.x >> 1;
+            sm[ix(b, (threadIdx.x & 1) ? m + 1 : 0)] = zero;
         }
         __syncthreads();
-        lds_fft<R, LOGL, ROWS, NT, false, false, L>(sm, reinterpret_cast<const T*>(a.twL[0]));
-    }
-    for (int idx = threadIdx.x; idx < ROWS * m; idx += NT) {
-        const int b = idx / m, t = idx % m + 1;
-        const long long g = g0 + b;
-        if (g < nlines) {
-            const long long p = g / lpp, rr = g % lpp;
-            S[p * a.ldS + rr * m + t - 1] = sm[b * L + t];
+        if (grp + gridDim.x < ngroups) fetch(grp + gridDim.x);
+        lds_fft<R, LOGL, ROWS, NT, false, false, LP, PS>(sm, reinterpret_cast<const T*>(a.twL[0]));
+        if constexpr (SOLVE) {
+            for (int idx = threadIdx.x; idx < ROWS * (m + 2); idx += NT) {
+                const int b = idx / (m + 2), t = idx % (m + 2);
+                const long long g = g0 + b;
+                if (t == 0 || t == m + 1 || g >= nlines) {
+                    sm[ix(b, t)] = zero;
+                    if (t > 0 && t <= m) sm[ix(b, L - t)] = zero;
+                    continue;
+                }
+                const double2 sg = a.sigma[g / lpp];
+                const double dre = sg.x + a.mu[0][t - 1];
+                const double inv = a.inv_factor / (dre * dre + sg.y * sg.y);
+                const T c = mk<T>((R)(dre * inv), (R)(-sg.y * inv));
+                const T z = cmul(sm[ix(b, t)], c);
+                sm[ix(b, t)] = z;
+                sm[ix(b, L - t)] = mk<T>(-z.x, -z.y);
+            }
+            __syncthreads();
+            lds_fft<R, LOGL, ROWS, NT, false, false, LP, PS>(sm, reinterpret_cast<const T*>(a.twL[0]));
         }
+        for (int idx = threadIdx.x; idx < ROWS * m; idx += NT) {
+            const int b = idx / m, t = idx % m + 1;
+            const long long g = g0 + b;
+            if (g < nlines) {
+                const long long p = g / lpp, rr = g % lpp;
+                S[p * a.ldS + rr * a.mxp + t - 1] = sm[ix(b, t)];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -732,73 +786,91 @@ __global__ __launch_bounds__(NT) void k_dst_cols(SpaceArgs a, int axis) {
     constexpr int L = 1 << LOGL;
     __shared__ T sm[L * W];
     const int m = axis == 1 ? a.my : a.mz;
-    const long long st = axis == 1 ? (long long)a.mx : (long long)a.mx * a.my;
+    const long long st = axis == 1 ? (long long)a.mxp : (long long)a.mxp * a.my;
     const int other = axis == 1 ? a.mz : a.my;
     const int nxg = (a.mx + W - 1) / W;
-    const int gid = blockIdx.x;
-    const int xg = gid % nxg;
-    const int rest = gid / nxg;
-    const int o = rest % other;
-    const int p = rest / other;
-    const int x0 = xg * W;
-    const long long base = (long long)p * a.ldS + x0 + (axis == 1 ? (long long)o * a.mx * a.my : (long long)o * a.mx);
+    const long long ngroups = (long long)a.nP * other * nxg;
     T* S = reinterpret_cast<T*>(a.S);
     const T zero = mk<T>((R)0, (R)0);
-    // one load per element of the m x W block (rows of W contiguous values), all
-    // in flight, then written to positions t and L - t of the odd extension
+    const T* tw = reinterpret_cast<const T*>(a.twL[axis]);
+    struct Grp {
+        int p, o, x0;
+        long long base;
+    };
+    auto decode = [&](long long gid) {
+        Grp g;
+        const int xg = (int)(gid % nxg);
+        const long long rest = gid / nxg;
+        g.o = (int)(rest % other);
+        g.p = (int)(rest / other);
+        g.x0 = xg * W;
+        g.base = (long long)g.p * a.ldS + g.x0 +
+                 (axis == 1 ? (long long)g.o * a.mxp * a.my : (long long)g.o * a.mxp);
+        return g;
+    };
+    // Persistent workgroups with the next group's loads (rows of W contiguous
+    // values) issued before the current group's transforms.
     constexpr int PER = ((L / 2 - 1) * W + NT - 1) / NT;
     T val[PER];
+    auto fetch = [&](const Grp& g) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int idx = threadIdx.x + i * NT;
-        val[i] = zero;
-        if (idx < m * W) {
-            const int t = idx / W, w = idx % W;
-            if (x0 + w < a.mx) val[i] = S[base + t * st + w];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int idx = threadIdx.x + i * NT;
-        if (idx < m * W) {
-            const int t = idx / W + 1, w = idx % W;
-            sm[t * W + w] = val[i];
-            sm[(L - t) * W + w] = mk<T>(-val[i].x, -val[i].y);
-        }
-    }
-    if (threadIdx.x < 2 * W) {
-        const int w = threadIdx.x % W;
-        sm[((threadIdx.x < W) ? 0 : m + 1) * W + w] = zero;
-    }
-    __syncthreads();
-    const T* tw = reinterpret_cast<const T*>(a.twL[axis]);
-    lds_fft<R, LOGL, W, NT, false, true, 0>(sm, tw);
-    if constexpr (SOLVE) {
-        const double2 sg = a.sigma[p];
-        for (int idx = threadIdx.x; idx < (m + 2) * W; idx += NT) {
-            const int t = idx / W, w = idx % W;
-            if (t == 0 || t == m + 1) {
-                sm[t * W + w] = zero;
-            } else if (x0 + w >= a.mx) {
-                sm[t * W + w] = zero;
-                sm[(L - t) * W + w] = zero;
-            } else {
-                double dre = sg.x + a.mu[0][x0 + w] + a.mu[axis][t - 1];
-                if (axis == 2) dre += a.mu[1][o];
-                const double dim_ = sg.y;
-                const double inv = a.inv_factor / (dre * dre + dim_ * dim_);
-                const T c = mk<T>((R)(dre * inv), (R)(-dim_ * inv));
-                const T z = cmul(sm[t * W + w], c);
-                sm[t * W + w] = z;
-                sm[(L - t) * W + w] = mk<T>(-z.x, -z.y);
+        for (int i = 0; i < PER; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            val[i] = zero;
+            if (idx < m * W) {
+                const int t = idx / W, w = idx % W;
+                if (g.x0 + w < a.mx) val[i] = S[g.base + t * st + w];
             }
         }
+    };
+    long long gid = blockIdx.x;
+    if (gid < ngroups) fetch(decode(gid));
+    for (; gid < ngroups; gid += gridDim.x) {
+        const Grp g = decode(gid);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            if (idx < m * W) {
+                const int t = idx / W + 1, w = idx % W;
+                sm[t * W + w] = val[i];
+                sm[(L - t) * W + w] = mk<T>(-val[i].x, -val[i].y);
+            }
+        }
+        if (threadIdx.x < 2 * W) {
+            const int w = threadIdx.x % W;
+            sm[((threadIdx.x < W) ? 0 : m + 1) * W + w] = zero;
+        }
         __syncthreads();
+        if (gid + gridDim.x < ngroups) fetch(decode(gid + gridDim.x));
         lds_fft<R, LOGL, W, NT, false, true, 0>(sm, tw);
-    }
-    for (int idx = threadIdx.x; idx < m * W; idx += NT) {
-        const int t = idx / W + 1, w = idx % W;
-        if (x0 + w < a.mx) S[base + (t - 1) * st + w] = sm[t * W + w];
+        if constexpr (SOLVE) {
+            const double2 sg = a.sigma[g.p];
+            for (int idx = threadIdx.x; idx < (m + 2) * W; idx += NT) {
+                const int t = idx / W, w = idx % W;
+                if (t == 0 || t == m + 1) {
+                    sm[t * W + w] = zero;
+                } else if (g.x0 + w >= a.mx) {
+                    sm[t * W + w] = zero;
+                    sm[(L - t) * W + w] = zero;
+                } else {
+                    double dre = sg.x + a.mu[0][g.x0 + w] + a.mu[axis][t - 1];
+                    if (axis == 2) dre += a.mu[1][g.o];
+                    const double dim_ = sg.y;
+                    const double inv = a.inv_factor / (dre * dre + dim_ * dim_);
+                    const T c = mk<T>((R)(dre * inv), (R)(-dim_ * inv));
+                    const T z = cmul(sm[t * W + w], c);
+                    sm[t * W + w] = z;
+                    sm[(L - t) * W + w] = mk<T>(-z.x, -z.y);
+                }
+            }
+            __syncthreads();
+            lds_fft<R, LOGL, W, NT, false, true, 0>(sm, tw);
+        }
+        for (int idx = threadIdx.x; idx < m * W; idx += NT) {
+            const int t = idx / W + 1, w = idx % W;
+            if (g.x0 + w < a.mx) S[g.base + (t - 1) * st + w] = sm[t * W + w];
+        }
+        __syncthreads();
     }
 }
 
@@ -867,6 +939,21 @@ template <typename R> constexpr int cols_per_block(int logl) {
 }
 
 constexpr int kNT = 256;
+
+// Workgroups that fit on the whole device at once for a kernel (persistent
+// launches); cached per kernel.
+int persistent_blocks(const void* fn, int nt) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, nt, 0) != hipSuccess || per <= 0) per = 1;
+    return cus * per;
+}
 #define N_OF(logn) (1 << (logn))
 constexpr int kNTcq = 512;  // the length-2N FP64 convolution FFT needs more lanes per tile
 
@@ -874,14 +961,14 @@ template <typename R, int LOGN>
 hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
     if (cq) {
         constexpr int W = cq_tile(LOGN);
-        const int ntiles = (a.M + W - 1) / W;
+        const int ntiles = (a.Mp + W - 1) / W;
         const int grid = ((ntiles + 7) / 8) * 8;
         if (nb) *nb = grid;
         hipLaunchKernelGGL((k_fwd_cq<R, LOGN, W, kNTcq>), dim3(grid), dim3(kNTcq), 0, st, a);
     } else {
         constexpr int W = fwd_tile(LOGN);
         constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
-        const int ntiles = (a.M + W - 1) / W;
+        const int ntiles = (a.Mp + W - 1) / W;
         const int grid = ((ntiles + 7) / 8) * 8;
         if (nb) *nb = grid;
         hipLaunchKernelGGL((k_fwd_heat<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a);
@@ -892,7 +979,7 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
 template <typename R, int LOGN>
 hipError_t inv_one(const InvArgs& a, int* nb, hipStream_t st) {
     constexpr int W = time_tile<R>(LOGN);
-    const int ntiles = (a.M + W - 1) / W;
+    const int ntiles = (a.Mp + W - 1) / W;
     const int grid = ((ntiles + 7) / 8) * 8;
     if (nb) *nb = grid;
     hipLaunchKernelGGL((k_inv<R, LOGN, W, kNT>), dim3(grid), dim3(kNT), 0, st, a);
@@ -961,7 +1048,9 @@ template <typename R, int LOGL, bool SOLVE>
 hipError_t rows_one(const SpaceArgs& a, hipStream_t st) {
     constexpr int ROWS = rows_per_block<R>(LOGL);
     const long long nlines = (long long)a.nP * a.my * a.mz;
-    const long long grid = (nlines + ROWS - 1) / ROWS;
+    const long long groups = (nlines + ROWS - 1) / ROWS;
+    const long long grid = std::min<long long>(groups, persistent_blocks(reinterpret_cast<const void*>(
+                                                           &k_dst_rows<R, LOGL, ROWS, kNT, SOLVE>), kNT));
     hipLaunchKernelGGL((k_dst_rows<R, LOGL, ROWS, kNT, SOLVE>), dim3((unsigned)grid), dim3(kNT), 0, st, a, nlines);
     return hipGetLastError();
 }
@@ -972,7 +1061,9 @@ hipError_t cols_one(const SpaceArgs& a, int axis, hipStream_t st) {
     // tiles above 64 KB of LDS get 512 lanes so the FFT stages stay in registers
     constexpr int NT = ((1 << LOGL) * W * (int)sizeof(cx<R>) > 65536) ? 512 : kNT;
     const int other = axis == 1 ? a.mz : a.my;
-    const long long grid = (long long)a.nP * other * ((a.mx + W - 1) / W);
+    const long long groups = (long long)a.nP * other * ((a.mx + W - 1) / W);
+    const long long grid = std::min<long long>(
+        groups, persistent_blocks(reinterpret_cast<const void*>(&k_dst_cols<R, LOGL, W, NT, SOLVE>), NT));
     hipLaunchKernelGGL((k_dst_cols<R, LOGL, W, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, axis);
     return hipGetLastError();
 }
