@@ -42,6 +42,22 @@ def kernel_bytes(name, N, M, mixed, has_f):
     return 2 * S                                                    # spatial pass: spectrum in and out
 
 
+def measured_traffic(precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record, or None when the kernel source changed since it was taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "heat2d_255x255_N512_bdf4_traffic.json")
+    try:
+        rec = json.load(open(rec_path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        k = rec["kernels"][precision][kernel]
+        return k["read"] + k["write"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_precision(w, precision, steps, warmup):
     import torch
 
@@ -182,7 +198,8 @@ def main():
                    "grid": list(w.m), "N": N, "k": w.k, "kappa": w.kappa, "form": "residual",
                    "unknowns": N * M},
         "roofline": {"bound": "hbm", "kernel": d["kernel"], "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("fp64", d["kernel"]), "alg_bytes": d["bytes"]},
         "kernels_ms": out["fp64"]["kernels_ms"],
         "sweep_hbm_frac": out["fp64"]["sweep_hbm_frac"],
         "mixed": {k: out["mixed"][k] for k in ("value", "ms_per_step", "kernels_ms", "sweep_hbm_frac",
