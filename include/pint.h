@@ -152,18 +152,25 @@ int pint_profile_sweeps(pint_plan *plan, double *U, int nsweeps, double *ms, con
 pint_status pint_solve(pint_plan *plan, const double *v, const double *f, const double *fder,
                        double *U, double *upd, double *upd_l2T, int *sweeps);
 
-/* Many independent problems in one plan (each with its own grid and params,
- * N and k may differ).  Instances are swept together: one launch of each
- * kernel covers every instance, and a sweep step is recorded once into a HIP
- * graph and replayed.  count >= 1; grids/params are HOST arrays of count.
- * Same validation as pint_plan_create for every instance. */
+/* Many independent problems in one plan (each instance with its own grid and
+ * params; N, k, alpha, precision may all differ).  Every instance is validated
+ * as in pint_plan_create and gets its own tables and workspace.  One sweep of
+ * all instances still iterating is recorded once into a HIP graph, forked over
+ * up to 8 streams of default priority so that small instances run
+ * concurrently, and replayed each sweep; the graph is re-recorded only when an
+ * instance stops.  count >= 1; grids/params are HOST arrays of count entries.
+ * Errors: as pint_plan_create (the message names the instance). */
 pint_status pint_batch_plan_create(pint_plan **plan, int count, const pint_grid *grids,
                                    const pint_params *params, void *hip_stream);
 
-/* Batch solve: HOST arrays of count DEVICE pointers (f, fder entries may be
- * NULL), upd HOST [count][max_sweeps] (may be NULL), sweeps HOST [count]
- * (may be NULL).  Every instance is swept until all have met their tol or
- * reached their max_sweeps; converged instances are left untouched. */
+/* Batch solve.  v, f, fder, U: HOST arrays of count DEVICE pointers with the
+ * meaning of pint_solve (f and fder entries, or the f/fder arrays themselves,
+ * may be NULL).  upd: HOST [count][S] with S the largest max_sweeps of the
+ * instances (may be NULL); sweeps: HOST [count] (may be NULL).  After each
+ * replay the per-instance norms come back in one copy; an instance stops at its
+ * own tol, max_sweeps or divergence and is left untouched afterwards.
+ * Returns PINT_OK if every instance converged, PINT_NOT_CONVERGED if one hit
+ * max_sweeps, PINT_E_DIVERGED if one diverged (the others still finish). */
 pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const double *const *f,
                              const double *const *fder, double *const *U, double *upd, int *sweeps);
 

@@ -180,13 +180,16 @@ def pint_batch_plan_create(grids, params, stream=None):
 
 
 def pint_batch_solve(plan, v, f, fder, U, max_sweeps):
+    """max_sweeps: the largest max_sweeps of the instances.  Returns
+    (status, per-instance update norms, per-instance sweep counts)."""
     n = len(v)
     arr = lambda ts: (c_void_p * n)(*[None if t is None else t.data_ptr() for t in ts])
     upd = (c_double * (n * max_sweeps))()
     sw = (c_int * n)()
     st = lib().pint_batch_solve(plan, arr(v), arr(f), arr(fder), arr(U), upd, sw)
     _check(st, "pint_batch_solve", allow=(PINT_OK, PINT_NOT_CONVERGED, PINT_E_DIVERGED))
-    return st, [list(upd)[i * max_sweeps:(i + 1) * max_sweeps] for i in range(n)], list(sw)
+    sw = list(sw)
+    return st, [list(upd)[i * max_sweeps:i * max_sweeps + sw[i]] for i in range(n)], sw
 
 
 def pint_plan_destroy(plan):

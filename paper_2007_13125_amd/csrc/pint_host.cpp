@@ -152,14 +152,20 @@ struct pint_plan {
     double* h_norms = nullptr;  // pinned host, 2 doubles
     // batch: sub-plans sharing the stream
     std::vector<pint_plan*> inst;
-    hipGraphExec_t graph = nullptr;
-    double** batch_U = nullptr;
+    std::vector<hipStream_t> lanes;   // fork streams of a batch capture (default priority)
+    hipStream_t cap = nullptr;        // stream the batch graph is recorded on and replayed on
+    std::vector<hipEvent_t> lane_ev;
+    double* d_bnorms = nullptr;       // [count][2] per-instance norms of the last sweep
+    double* h_bnorms = nullptr;       // pinned host copy
 
     ~pint_plan() {
         for (void* q : owned) (void)hipFree(q);
         if (ws_owned && ws) (void)hipFree(ws);
         if (h_norms) (void)hipHostFree(h_norms);
-        if (graph) (void)hipGraphExecDestroy(graph);
+        if (h_bnorms) (void)hipHostFree(h_bnorms);
+        for (hipEvent_t e : lane_ev) (void)hipEventDestroy(e);
+        for (hipStream_t q : lanes) (void)hipStreamDestroy(q);
+        if (cap) (void)hipStreamDestroy(cap);
         for (pint_plan* q : inst) delete q;
     }
 };
@@ -688,12 +694,168 @@ const char* pint_last_error(void) { return g_err.c_str(); }
 
 pint_status pint_batch_plan_create(pint_plan** plan, int count, const pint_grid* grids, const pint_params* params,
                                    void* hip_stream) {
-    return fail(PINT_E_UNSUPPORTED, "batch plans are not implemented yet");
+    if (!plan || count < 1 || !grids || !params) return fail(PINT_E_ARG, "bad arguments to pint_batch_plan_create");
+    *plan = nullptr;
+    for (int i = 0; i < count; ++i) {
+        pint_status rc = validate(&grids[i], &params[i]);
+        if (rc != PINT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+    }
+    pint_plan* P = new (std::nothrow) pint_plan();
+    if (!P) return fail(PINT_E_NOMEM, "host allocation failed");
+    P->st = static_cast<hipStream_t>(hip_stream);
+    auto bail = [&](pint_status rc) {
+        delete P;
+        return rc;
+    };
+    hipError_t e = hipGetDevice(&P->device);
+    if (e != hipSuccess) return bail(fail(PINT_E_HIP, hipGetErrorString(e)));
+    for (int i = 0; i < count; ++i) {
+        pint_plan* Q = new (std::nothrow) pint_plan();
+        if (!Q) return bail(fail(PINT_E_NOMEM, "host allocation failed"));
+        P->inst.push_back(Q);
+        pint_status rc = build_plan(Q, &grids[i], &params[i], P->st);
+        if (rc != PINT_OK) return bail(rc);
+    }
+    // the caller's stream may be the legacy default stream, which cannot be
+    // captured: record and replay on a stream of the plan's own
+    if ((e = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking)) != hipSuccess)
+        return bail(fail(PINT_E_HIP, hipGetErrorString(e)));
+    const int nl = count < 8 ? count : 8;
+    for (int i = 0; i < nl; ++i) {
+        hipStream_t q;
+        if ((e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking)) != hipSuccess)
+            return bail(fail(PINT_E_HIP, hipGetErrorString(e)));
+        P->lanes.push_back(q);
+    }
+    for (int i = 0; i <= nl; ++i) {
+        hipEvent_t ev;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+            return bail(fail(PINT_E_HIP, hipGetErrorString(e)));
+        P->lane_ev.push_back(ev);
+    }
+    void* q = nullptr;
+    if ((e = hipMalloc(&q, (size_t)count * 2 * sizeof(double))) != hipSuccess)
+        return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
+    P->owned.push_back(q);
+    P->d_bnorms = static_cast<double*>(q);
+    if ((e = hipHostMalloc((void**)&P->h_bnorms, (size_t)count * 2 * sizeof(double), hipHostMallocDefault)) !=
+        hipSuccess)
+        return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
+    *plan = P;
+    return PINT_OK;
 }
 
-pint_status pint_batch_solve(pint_plan* plan, const double* const* v, const double* const* f,
-                             const double* const* fder, double* const* U, double* upd, int* sweeps) {
-    return fail(PINT_E_UNSUPPORTED, "batch plans are not implemented yet");
+namespace {
+
+// Record one sweep of every active instance into a HIP graph: the instances
+// are forked over the lane streams (instance i on lane i mod lanes) and joined
+// back on the plan's stream, so independent instances may run concurrently.
+pint_status capture_batch_sweep(pint_plan* P, const std::vector<int>& active, double* const* U,
+                                hipGraphExec_t* exec) {
+    HIP_TRY(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+    hipGraph_t graph = nullptr;
+    pint_status rc = PINT_OK;
+    const int nl = (int)P->lanes.size();
+    hipError_t e = hipEventRecord(P->lane_ev[nl], P->cap);
+    for (int l = 0; l < nl && e == hipSuccess; ++l) e = hipStreamWaitEvent(P->lanes[l], P->lane_ev[nl], 0);
+    for (size_t a = 0; a < active.size() && e == hipSuccess && rc == PINT_OK; ++a) {
+        const int i = active[a];
+        pint_plan* Q = P->inst[i];
+        const hipStream_t keep = Q->st;
+        Q->st = P->lanes[i % nl];
+        rc = one_sweep(Q, U[i], P->d_bnorms + 2 * i);
+        Q->st = keep;
+    }
+    for (int l = 0; l < nl && e == hipSuccess; ++l) {
+        e = hipEventRecord(P->lane_ev[l], P->lanes[l]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P->cap, P->lane_ev[l], 0);
+    }
+    const hipError_t e2 = hipStreamEndCapture(P->cap, &graph);
+    if (rc != PINT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(PINT_E_HIP, std::string("batch capture: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(PINT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(PINT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return PINT_OK;
+}
+
+}  // namespace
+
+pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double* const* f, const double* const* fder,
+                             double* const* U, double* upd, int* sweeps) {
+    if (!P || P->inst.empty() || !v || !U) return fail(PINT_E_ARG, "bad arguments to pint_batch_solve");
+    const int count = (int)P->inst.size();
+    int max_sw = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!v[i] || !U[i]) return fail(PINT_E_ARG, "instance " + std::to_string(i) + ": NULL v or U");
+        pint_plan* Q = P->inst[i];
+        pint_status rc = pint_bind(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr);
+        if (rc != PINT_OK) return rc;
+        if ((rc = pint_init_iterate(Q, U[i])) != PINT_OK) return rc;
+        if (Q->p.max_sweeps > max_sw) max_sw = Q->p.max_sweeps;
+        if (sweeps) sweeps[i] = 0;
+    }
+    // binding and initial iterates were enqueued on the caller's stream
+    HIP_TRY(hipStreamSynchronize(P->st));
+    std::vector<int> active(count);
+    for (int i = 0; i < count; ++i) active[i] = i;
+    std::vector<std::vector<double>> hist(count);
+    pint_status result = PINT_OK;
+    hipGraphExec_t exec = nullptr;
+    bool recapture = true;
+    for (int m = 0; m < max_sw && !active.empty(); ++m) {
+        if (recapture) {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+            pint_status rc = capture_batch_sweep(P, active, U, &exec);
+            if (rc != PINT_OK) return rc;
+            recapture = false;
+        }
+        hipError_t e = hipGraphLaunch(exec, P->cap);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P->h_bnorms, P->d_bnorms, (size_t)count * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               P->cap);
+        if (e == hipSuccess) e = hipStreamSynchronize(P->cap);
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            return fail(PINT_E_HIP, std::string("batch sweep: ") + hipGetErrorString(e));
+        }
+        std::vector<int> next;
+        for (int i : active) {
+            pint_plan* Q = P->inst[i];
+            const double ninf = P->h_bnorms[2 * i], nl2 = P->h_bnorms[2 * i + 1];
+            if (upd) upd[(size_t)i * max_sw + m] = ninf;
+            if (sweeps) sweeps[i] = m + 1;
+            const double crit = Q->p.norm == PINT_NORM_INF ? ninf : nl2;
+            bool done = false;
+            if (!std::isfinite(ninf) || !std::isfinite(nl2)) {
+                result = fail(PINT_E_DIVERGED, "instance " + std::to_string(i) + ": non-finite update");
+                done = true;
+            } else {
+                hist[i].push_back(crit);
+                const size_t h = hist[i].size();
+                if (crit <= Q->p.tol) {
+                    done = true;
+                } else if (h >= 3 && hist[i][h - 1] > hist[i][h - 2] && hist[i][h - 2] > hist[i][h - 3] &&
+                           hist[i][h - 1] > hist[i][0]) {
+                    result = fail(PINT_E_DIVERGED, "instance " + std::to_string(i) + ": update grew");
+                    done = true;
+                } else if (m + 1 >= Q->p.max_sweeps) {
+                    if (result == PINT_OK) result = PINT_NOT_CONVERGED;
+                    done = true;
+                }
+            }
+            if (!done) next.push_back(i);
+        }
+        if (next.size() != active.size()) recapture = true;
+        active.swap(next);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return result;
 }
 
 }  // extern "C"

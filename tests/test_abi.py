@@ -67,3 +67,14 @@ def test_bad_enum_and_null_plan():
     assert B.lib().pint_plan_destroy(None) == B.PINT_OK
     assert B.lib().pint_plan_workspace_bytes(None) == 0
     assert B.lib().pint_status_str(B.PINT_E_DIVERGED) == b"PINT_E_DIVERGED"
+
+
+def test_batch_rejects_unsupported_instance():
+    grids = [B.make_grid((63,)), B.make_grid((100, 127))]
+    params = [B.make_params(2, 1.0, 1.0, 64, 1e-3), B.make_params(2, 1.0, 1.0, 64, 1e-3)]
+    G = (B.pint_grid * 2)(*grids)
+    Pm = (B.pint_params * 2)(*params)
+    h = ctypes.c_void_p()
+    st = B.lib().pint_batch_plan_create(ctypes.byref(h), 2, G, Pm, None)
+    assert st == B.PINT_E_UNSUPPORTED
+    assert b"instance 1" in B.lib().pint_last_error()

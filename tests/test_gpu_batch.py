@@ -1,0 +1,53 @@
+"""GPU tests of the batch entry points: many instances of different shapes,
+orders, alpha, kappa and precision swept together by one replayed HIP graph.
+Each instance must equal its own single-plan solve bit for bit (same kernels,
+same inputs, same sweep count; the single solves launch eagerly, so this also
+checks every graph replay against eager execution) and match the oracle."""
+import numpy as np
+import pytest
+
+from paper_2007_13125_amd import binding as B
+from paper_2007_13125_amd import workloads as wl
+from tests.gpu_util import gpu_solve, oracle_solution, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances():
+    ws = [wl.heat1d(seed=11, m=63, N=64, k=2, kappa=1e-3),
+          wl.heat1d(seed=12, m=100, N=32, k=5, kappa=1e-2),
+          wl.heat2d(seed=13, m=(31, 15), N=128, k=4, kappa=1e-4),
+          wl.heat2d(seed=14, m=(63, 63), N=64, k=3, kappa=1e-3),
+          wl.heat3d(seed=15, m=(7, 15, 7), N=32, k=6, kappa=1e-4),
+          wl.heat1d(seed=16, m=255, N=256, k=3, kappa=1e-3)]
+    ws[3].alpha = 0.5
+    ws[5].alpha = 0.7
+    precs = ["fp64", "mixed", "fp64", "fp64", "mixed", "fp64"]
+    return ws, precs
+
+
+def test_batch_matches_single_solves_and_oracle():
+    import torch
+    ws, precs = _instances()
+    tol = 1e-13
+    grids = [B.make_grid(w.m) for w in ws]
+    params = [B.make_params(w.k, w.alpha, w.T, w.N, w.kappa, tol=tol, max_sweeps=30, precision=p)
+              for w, p in zip(ws, precs)]
+    print("[gpu] batch of", len(ws), "instances", flush=True)
+    h = B.pint_batch_plan_create(grids, params)
+    vs = [to_dev(w.v) for w in ws]
+    fs = [to_dev(w.f) for w in ws]
+    fds = [to_dev(w.fder) for w in ws]
+    Us = [torch.empty((w.N, w.M), dtype=torch.float64, device="cuda") for w in ws]
+    st, upd, sw = B.pint_batch_solve(h, vs, fs, fds, Us, 30)
+    torch.cuda.synchronize()
+    assert st == B.PINT_OK, (st, sw)
+    B.pint_plan_destroy(h)
+    for i, (w, p) in enumerate(zip(ws, precs)):
+        single, info = gpu_solve(w, precision=p, tol=tol, max_sweeps=30)
+        got = Us[i].cpu().numpy()
+        assert info["sweeps"] == sw[i], (i, info["sweeps"], sw[i])
+        assert np.array_equal(got, single), (i, np.max(np.abs(got - single)))
+        assert np.allclose(upd[i], info["upd"], rtol=0, atol=0)
+        ref = oracle_solution(w)
+        assert rel_l2(got, ref) <= (1e-11 if p == "fp64" else 1e-10), i
