@@ -269,8 +269,14 @@ __device__ __forceinline__ void store_half_spectrum(const cx<R>* sm, cx<R>* S, i
 // Phase B adds the parts read from LDS (time stencil, centre, x neighbours
 // inside the tile) and scales by kappa^{q/N}.  The FFT buffer then reuses the
 // LDS of the U tile.
+#ifndef PINT_FWD_WAVES
+#define PINT_FWD_WAVES 4
+#endif
+#ifndef PINT_INV_WAVES
+#define PINT_INV_WAVES 1
+#endif
 template <typename R, int LOGN, int W, int NT>
-__global__ __launch_bounds__(NT) void k_fwd_heat(FwdArgs a) {
+__global__ __launch_bounds__(NT, PINT_FWD_WAVES) void k_fwd_heat(FwdArgs a) {
     constexpr int N = 1 << LOGN;
     constexpr int B = W / 2;
     constexpr int PER = N * W / NT;
@@ -305,29 +311,32 @@ __global__ __launch_bounds__(NT) void k_fwd_heat(FwdArgs a) {
     const size_t sy = (size_t)a.mx, sz = (size_t)a.mx * a.my;
     const double vt = valid ? a.ta * a.v[d] : 0.0;
 
+    // Neighbours outside the tile: branch-free loads (a missing neighbour reads
+    // the centre with weight zero), so every load of the tile is in flight at once.
+    const bool nbx = resid && valid;
+    const double cxm = (nbx && exm) ? a.ihx2 : 0.0, cxp = (nbx && exp_) ? a.ihx2 : 0.0;
+    const double cym = (nbx && hym) ? a.ihy2 : 0.0, cyp = (nbx && hyp) ? a.ihy2 : 0.0;
+    const double czm = (nbx && hzm) ? a.ihz2 : 0.0, czp = (nbx && hzp) ? a.ihz2 : 0.0;
+    const long long oxm = cxm != 0.0 ? -1 : 0, oxp = cxp != 0.0 ? 1 : 0;
+    const long long oym = cym != 0.0 ? -(long long)sy : 0, oyp = cyp != 0.0 ? (long long)sy : 0;
+    const long long ozm = czm != 0.0 ? -(long long)sz : 0, ozp = czp != 0.0 ? (long long)sz : 0;
+    const bool has3 = a.mz > 1;
+    const double* Ub = a.U + (valid ? d : 0);
+    const double* fb = a.f ? a.f + (valid ? d : 0) + M : nullptr;
     double g[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int q = (tid + i * NT) / W;
-        const size_t o = (size_t)q * M + d;
-        double u = 0.0, acc = 0.0;
-        if (valid) {
-            u = a.U[o];
-            acc = vt * a.s[q];
-            if (a.f) acc += a.f[o + M];
-            if (resid) {
-                double nb = 0.0;
-                if (exm) nb += a.ihx2 * a.U[o - 1];
-                if (exp_) nb += a.ihx2 * a.U[o + 1];
-                if (hym) nb += a.ihy2 * a.U[o - sy];
-                if (hyp) nb += a.ihy2 * a.U[o + sy];
-                if (hzm) nb += a.ihz2 * a.U[o - sz];
-                if (hzp) nb += a.ihz2 * a.U[o + sz];
-                acc += nb;
-            }
+        const double* uq = Ub + (size_t)q * M;
+        const double u = uq[0];
+        double acc = vt * a.s[q];
+        if (fb) acc += fb[(size_t)q * M];
+        if (resid) {
+            acc += cxm * uq[oxm] + cxp * uq[oxp] + cym * uq[oym] + cyp * uq[oyp];
+            if (has3) acc += czm * uq[ozm] + czp * uq[ozp];
         }
-        su[q * W + dl] = u;
-        g[i] = acc;
+        su[q * W + dl] = valid ? u : 0.0;
+        g[i] = valid ? acc : 0.0;
     }
     if (valid && a.ncorr > 0) {
 #pragma unroll
@@ -339,7 +348,11 @@ __global__ __launch_bounds__(NT) void k_fwd_heat(FwdArgs a) {
     __syncthreads();
 
     const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
-    const bool ixm = hxm && dl > 0, ixp = hxp && dl < W - 1;     // x neighbours inside the tile
+    const double cim = (hxm && dl > 0) ? a.ihx2 : 0.0, cip = (hxp && dl < W - 1) ? a.ihx2 : 0.0;
+    const int lm = dl > 0 ? dl - 1 : dl, lp = dl < W - 1 ? dl + 1 : dl;   // x neighbours inside the tile
+    double wk[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) wk[j] = a.wk[j];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int q = (tid + i * NT) / W;
@@ -349,15 +362,15 @@ __global__ __launch_bounds__(NT) void k_fwd_heat(FwdArgs a) {
             r = g[i];
             if (resid) {
                 const double u = su[q * W + dl];
-                double ts = a.wk[0] * u;
-                for (int j = 1; j <= a.k && j <= q; ++j) ts += a.wk[j] * su[(q - j) * W + dl];
-                double au = diag * u;
-                if (ixm) au -= a.ihx2 * su[q * W + dl - 1];
-                if (ixp) au -= a.ihx2 * su[q * W + dl + 1];
+                // time stencil sum_{j<n, j<=k} w_j U^{n-j}; w_j = 0 beyond k
+                double ts = wk[0] * u;
+#pragma unroll
+                for (int j = 1; j < 7; ++j) ts += (q >= j) ? wk[j] * su[(q >= j ? q - j : 0) * W + dl] : 0.0;
+                const double au = diag * u - cim * su[q * W + lm] - cip * su[q * W + lp];
                 r -= a.ta * ts + au;
             } else if (n <= a.k) {
                 double acc = 0.0;
-                for (int j = n; j <= a.k; ++j) acc += a.wk[j] * su[(a.N + n - j - 1) * W + dl];
+                for (int j = n; j <= a.k; ++j) acc += wk[j] * su[(a.N + n - j - 1) * W + dl];
                 r += a.kappa * a.ta * acc;
             }
             r *= a.scale[q];
@@ -451,7 +464,7 @@ __global__ __launch_bounds__(NT) void k_fwd_cq(FwdArgs a) {
 // U tile is fetched into registers together with the spectrum, so both
 // streams of loads are in flight at once.
 template <typename R, int LOGN, int W, int NT>
-__global__ __launch_bounds__(NT) void k_inv(InvArgs a) {
+__global__ __launch_bounds__(NT, PINT_INV_WAVES) void k_inv(InvArgs a) {
     constexpr int N = 1 << LOGN;
     constexpr int B = W / 2;
     constexpr int NP = N / 2 + 1;
@@ -706,33 +719,49 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
     T* S = reinterpret_cast<T*>(a.S);
     const T zero = mk<T>((R)0, (R)0);
     const long long ngroups = (nlines + ROWS - 1) / ROWS;
-    // Persistent workgroups: each walks groups of ROWS rows, and the loads of
-    // its next group are issued (into registers) before the transform of the
-    // current one, so memory traffic overlaps the LDS work.
-    constexpr int PER = (ROWS * (L / 2 - 1) + NT - 1) / NT;
+    // Element e of a group is (row b, position t) = (e >> LH, e & (H - 1)) with
+    // H = L/2 > m, so no integer division appears per element; the offset of
+    // each row of the group is computed once per group into LDS.
+    constexpr int H = L / 2;
+    constexpr int LH = LOGL - 1;
+    constexpr int PER = (ROWS * H + NT - 1) / NT;
+    __shared__ long long rowoff[2][ROWS];
     T val[PER];
-    auto fetch = [&](long long grp) {
+    auto offsets = [&](long long grp, int slot) {
+        if (threadIdx.x < ROWS) {
+            const long long g = grp * ROWS + threadIdx.x;
+            const unsigned gu = (unsigned)g;
+            rowoff[slot][threadIdx.x] =
+                g < nlines ? (long long)(gu / (unsigned)lpp) * a.ldS + (long long)(gu % (unsigned)lpp) * a.mxp : -1;
+        }
+    };
+    auto fetch = [&](int slot) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            const int idx = threadIdx.x + i * NT;
+            const int e = threadIdx.x + i * NT;
+            const int b = e >> LH, t = e & (H - 1);
             val[i] = zero;
-            if (idx < ROWS * m) {
-                const int b = idx / m, t = idx % m;
-                const long long g = grp * ROWS + b;
-                if (g < nlines) val[i] = S[(g / lpp) * a.ldS + (g % lpp) * a.mxp + t];
+            if ((ROWS * H) % NT == 0 || e < ROWS * H) {
+                const long long off = rowoff[slot][b];
+                if (t < m && off >= 0) val[i] = S[off + t];
             }
         }
     };
     long long grp = blockIdx.x;
-    if (grp < ngroups) fetch(grp);
-    for (; grp < ngroups; grp += gridDim.x) {
+    int slot = 0;
+    if (grp < ngroups) {
+        offsets(grp, 0);
+        __syncthreads();
+        fetch(0);
+    }
+    for (; grp < ngroups; grp += gridDim.x, slot ^= 1) {
         const long long g0 = grp * ROWS;
         // odd extension: x_t at t and -x_t at L - t, zeros at 0 and m + 1
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            const int idx = threadIdx.x + i * NT;
-            if (idx < ROWS * m) {
-                const int b = idx / m, t = idx % m + 1;
+            const int e = threadIdx.x + i * NT;
+            const int b = e >> LH, t = (e & (H - 1)) + 1;
+            if (((ROWS * H) % NT == 0 || e < ROWS * H) && t <= m) {
                 sm[ix(b, t)] = val[i];
                 sm[ix(b, L - t)] = mk<T>(-val[i].x, -val[i].y);
             }
@@ -741,19 +770,21 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
             const int b = threadIdx.x >> 1;
             sm[ix(b, (threadIdx.x & 1) ? m + 1 : 0)] = zero;
         }
+        if (grp + gridDim.x < ngroups) offsets(grp + gridDim.x, slot ^ 1);
         __syncthreads();
-        if (grp + gridDim.x < ngroups) fetch(grp + gridDim.x);
+        if (grp + gridDim.x < ngroups) fetch(slot ^ 1);
         lds_fft<R, LOGL, ROWS, NT, false, false, LP, PS>(sm, reinterpret_cast<const T*>(a.twL[0]));
         if constexpr (SOLVE) {
-            for (int idx = threadIdx.x; idx < ROWS * (m + 2); idx += NT) {
-                const int b = idx / (m + 2), t = idx % (m + 2);
+            for (int idx = threadIdx.x; idx < ROWS * L; idx += NT) {
+                const int b = idx >> LOGL, t = idx & (L - 1);
+                if (t > m + 1) continue;
                 const long long g = g0 + b;
                 if (t == 0 || t == m + 1 || g >= nlines) {
                     sm[ix(b, t)] = zero;
                     if (t > 0 && t <= m) sm[ix(b, L - t)] = zero;
                     continue;
                 }
-                const double2 sg = a.sigma[g / lpp];
+                const double2 sg = a.sigma[(unsigned)g / (unsigned)lpp];
                 const double dre = sg.x + a.mu[0][t - 1];
                 const double inv = a.inv_factor / (dre * dre + sg.y * sg.y);
                 const T c = mk<T>((R)(dre * inv), (R)(-sg.y * inv));
@@ -764,12 +795,13 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
             __syncthreads();
             lds_fft<R, LOGL, ROWS, NT, false, false, LP, PS>(sm, reinterpret_cast<const T*>(a.twL[0]));
         }
-        for (int idx = threadIdx.x; idx < ROWS * m; idx += NT) {
-            const int b = idx / m, t = idx % m + 1;
-            const long long g = g0 + b;
-            if (g < nlines) {
-                const long long p = g / lpp, rr = g % lpp;
-                S[p * a.ldS + rr * a.mxp + t - 1] = sm[ix(b, t)];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * NT;
+            const int b = e >> LH, t = (e & (H - 1)) + 1;
+            if (((ROWS * H) % NT == 0 || e < ROWS * H) && t <= m) {
+                const long long off = rowoff[slot][b];
+                if (off >= 0) S[off + t - 1] = sm[ix(b, t)];
             }
         }
         __syncthreads();
