@@ -241,19 +241,29 @@ __device__ __forceinline__ double nanmax(double a, double b) {
 // A_p = (Z_p + conj Z_{N-p})/2,  B_p = (Z_p - conj Z_{N-p})/(2i).
 // Lane (p, e) produces dof d0 + e of row p, so consecutive lanes store
 // consecutive complex values (one contiguous W-value segment per row).
-template <typename R, int N, int B, int NT>
+// The loop has a compile-time trip count (all but the last pass unconditional),
+// so the number of stores in flight is known to the compiler and later waits
+// for earlier loads need not wait for these stores.  CHECK = false when the
+// caller's tile never extends past the last slot.
+template <typename R, int N, int B, int NT, bool CHECK = true>
 __device__ __forceinline__ void store_half_spectrum(const cx<R>* sm, cx<R>* S, int ldS, int d0, int M) {
     constexpr int NP = N / 2 + 1;
     constexpr int W = 2 * B;
-    for (int idx = threadIdx.x; idx < NP * W; idx += NT) {
-        const int e = idx % W, p = idx / W;
-        const int b = e >> 1;
-        const cx<R> zp = sm[p * B + b];
-        const cx<R> zn = sm[((N - p) & (N - 1)) * B + b];
-        const R h = R(0.5);
-        const cx<R> out = (e & 1) ? mk<cx<R>>((zp.y + zn.y) * h, (zn.x - zp.x) * h)
-                                  : mk<cx<R>>((zp.x + zn.x) * h, (zp.y - zn.y) * h);
-        if (d0 + e < M) S[(size_t)p * ldS + d0 + e] = out;
+    constexpr int TOT = NP * W;
+    constexpr int IT = (TOT + NT - 1) / NT;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = threadIdx.x + it * NT;
+        if ((it + 1) * NT <= TOT || idx < TOT) {
+            const int e = idx % W, p = idx / W;
+            const int b = e >> 1;
+            const cx<R> zp = sm[p * B + b];
+            const cx<R> zn = sm[((N - p) & (N - 1)) * B + b];
+            const R h = R(0.5);
+            const cx<R> out = (e & 1) ? mk<cx<R>>((zp.y + zn.y) * h, (zn.x - zp.x) * h)
+                                      : mk<cx<R>>((zp.x + zn.x) * h, (zp.y - zn.y) * h);
+            if (!CHECK || d0 + e < M) S[(size_t)p * ldS + d0 + e] = out;
+        }
     }
 }
 
@@ -383,6 +393,188 @@ __global__ __launch_bounds__(NT, PINT_FWD_WAVES) void k_fwd_heat(FwdArgs a) {
     __syncthreads();
     lds_fft<R, LOGN, B, NT, false, true, 0>(sm, reinterpret_cast<const cx<R>*>(a.tw));
     store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<cx<R>*>(a.S), a.ldS, d0, a.Mp);
+}
+
+// ---------------------------------------------------------------------------
+// Forward kernel, BDF-k residual form on 2D and 3D grids, marching along the
+// outermost axis (y in 2D, z in 3D).  A workgroup owns the W x slots of one
+// line and walks a chunk of consecutive outer indices c.  Each lane keeps its
+// time rows of U at c-1, c and c+1 in registers, so the outer-axis stencil
+// neighbours are read from memory once (not three times), and every load of
+// position c+1 (U at c+2, f, v, x halo, 3D y neighbours) is issued before the
+// LDS phases, FFT and spectrum store of position c.  Per position the
+// arithmetic is that of k_fwd_heat (same residual, same FFT, same store).
+#ifndef PINT_MARCH_WAVES
+#define PINT_MARCH_WAVES 1
+#endif
+#ifndef PINT_MARCH_NT
+#define PINT_MARCH_NT 512
+#endif
+template <typename R, int LOGN, int W, int NT, bool IS3>
+__global__ __launch_bounds__(NT, PINT_MARCH_WAVES) void k_fwd_march(FwdArgs a, int ncol, int nchunk, int chunk) {
+    using T = cx<R>;
+    constexpr int N = 1 << LOGN;
+    constexpr int B = W / 2;
+    constexpr int PER = N * W / NT;
+    static_assert(PER * NT == N * W, "tile shape");
+    constexpr int CI = (6 * W + NT - 1) / NT < PER ? (6 * W + NT - 1) / NT : PER;   // i with q_i < 6 possible
+    constexpr int Z = 6 * W;            // six zero rows below time row 0: U^{n-j} = 0 for n - j < 1
+    __shared__ double sbuf[Z + N * W];
+    __shared__ double ssn[N], ssc[N];   // tau^{-1} s_n and kappa^{q/N}
+    __shared__ T stw[N];                // FFT twiddles, read from LDS so that the FFT never
+                                        // waits on the vector-memory counter of the prefetches
+    double* su = sbuf + Z;              // su[q W + l] = U^{q+1} at slot l of the tile
+    T* sm = reinterpret_cast<T*>(sbuf); // FFT buffer [N][B], reuses the LDS of the tile
+    R* smr = reinterpret_cast<R*>(sbuf);
+
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    if (lin >= ncol * nchunk) return;
+    const int col = lin % ncol, chk = lin / ncol;
+    const int nxt = a.mxp / W;
+    const int xt = col % nxt, yl = col / nxt;          // x tile, y line (3D)
+    const int nm = IS3 ? a.mz : a.my;                  // length of the marching axis
+    const int c0 = chk * chunk, c1 = min(nm, c0 + chunk);
+    const int tid = threadIdx.x;
+    const int dl = tid % W;
+    const int x = xt * W + dl;
+    const bool valid = x < a.mx;
+    const size_t M = a.M;
+    const long long sdof = IS3 ? (long long)a.mx * a.my : a.mx;      // dof stride along the march
+    const long long sslot = IS3 ? (long long)a.mxp * a.my : a.mxp;   // spectrum slot stride
+    const long long dbase = (valid ? x : 0) + (IS3 ? (long long)a.mx * yl : 0);
+    const long long slot0 = (long long)xt * W + (IS3 ? (long long)a.mxp * yl : 0);
+
+    for (int i = tid; i < N; i += NT) {
+        ssn[i] = a.ta * a.s[i];
+        ssc[i] = a.scale[i];
+        stw[i] = reinterpret_cast<const T*>(a.tw)[i];
+    }
+    // Coefficients fixed along the march; a missing neighbour reads the centre with weight 0.
+    const bool hxm = valid && x > 0 && dl == 0, hxp = valid && x < a.mx - 1 && dl == W - 1;
+    const double chx = (hxm || hxp) ? a.ihx2 : 0.0;
+    const long long ohx = hxm ? -1 : (hxp ? 1 : 0);
+    const double cym = (IS3 && valid && yl > 0) ? a.ihy2 : 0.0;
+    const double cyp = (IS3 && valid && yl < a.my - 1) ? a.ihy2 : 0.0;
+    const long long oym = cym != 0.0 ? -(long long)a.mx : 0, oyp = cyp != 0.0 ? (long long)a.mx : 0;
+    const double co = valid ? (IS3 ? a.ihz2 : a.ihy2) : 0.0;
+    const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
+    const double cim = (valid && x > 0 && dl > 0) ? a.ihx2 : 0.0;
+    const double cip = (valid && x < a.mx - 1 && dl < W - 1) ? a.ihx2 : 0.0;
+    const int om = dl > 0 ? -1 : 0, op = dl < W - 1 ? 1 : 0;   // x neighbours inside the tile
+    double wk[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) wk[j] = a.wk[j];
+
+    // Addresses: a uniform (scalar) base per row group i and outer index c plus
+    // one 32-bit byte offset per lane that is fixed for the whole kernel, so
+    // the loads take the scalar-base + vector-offset form and need no 64-bit
+    // address arithmetic per element (the host guarantees the offsets fit).
+    // Every load is unconditional (rows clamped to the grid, absent terms read
+    // a valid array with weight 0), so no loaded register is ever copied or
+    // merged before use and the prefetches stay in flight across the FFT.
+    constexpr int RS = NT / W;                         // time rows between row groups i and i+1
+    const int qb = tid / W;
+    const unsigned lo = (unsigned)(((long long)qb * (long long)M + dbase) * 8);
+    const unsigned lhx = (unsigned)((long long)lo + ohx * 8);
+    const unsigned lym = (unsigned)((long long)lo + oym * 8), lyp = (unsigned)((long long)lo + oyp * 8);
+    const unsigned lv = (unsigned)(dbase * 8);
+    const double cf = a.f ? 1.0 : 0.0;
+    const double* fbase = a.f ? a.f + M : a.U;         // f(t_{q+1}), or U with weight 0
+    const double* cbase = a.ncorr > 0 ? a.corr : a.U;  // correction rows, or U with weight 0
+    double ccf[CI];
+    unsigned lcr[CI];
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+        const int q = qb + i * RS;
+        ccf[i] = q < a.ncorr ? 1.0 : 0.0;
+        lcr[i] = (unsigned)(((long long)(q < a.ncorr ? q : 0) * (long long)M + dbase) * 8);
+    }
+    const size_t nU = (size_t)a.N * M;
+    const size_t nF = a.f ? (size_t)a.N * M : nU;          // f rows 1..N (fbase skips row 0)
+    const size_t nC = a.ncorr > 0 ? (size_t)a.ncorr * M : nU;
+    // buffer load of arr[e0 + lane offset]: the descriptor spans arr[e0 .. n), so an
+    // offset outside the array reads 0 instead of faulting
+    auto at = [](const double* arr, size_t n, size_t e0, unsigned off) {
+        const unsigned long long avail = (unsigned long long)(n - e0) * 8ull;
+        const int nrec = avail > 0xffffffffull ? -1 : (int)(unsigned)avail;
+        __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(arr + e0), (short)0, nrec,
+                                                                     0x00020000);
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    };
+    double A[PER], Bv[PER], C[PER], fr[PER], hx[PER], ym[PER], yp[PER], cr[CI];
+    double vv;
+    auto load_row = [&](double (&dst)[PER], int c) {   // U at outer index c (within the grid)
+#pragma unroll
+        for (int i = 0; i < PER; ++i) dst[i] = at(a.U, nU, (size_t)i * RS * M + (size_t)c * sdof, lo);
+    };
+    auto load_side = [&](int c) {                      // everything else position c needs
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const size_t e0 = (size_t)i * RS * M + (size_t)c * sdof;
+            hx[i] = at(a.U, nU, e0, lhx);
+            if (IS3) {
+                ym[i] = at(a.U, nU, e0, lym);
+                yp[i] = at(a.U, nU, e0, lyp);
+            }
+            fr[i] = at(fbase, nF, e0, lo);
+        }
+#pragma unroll
+        for (int i = 0; i < CI; ++i) cr[i] = at(cbase, nC, (size_t)c * sdof, lcr[i]);
+        vv = at(a.v, M, (size_t)c * sdof, lv);
+    };
+
+    // One position c of the march with U at c-1, c, c+1 in Um, Uc, Up; Um is
+    // refilled with U at c+2.  The three arrays rotate by renaming (the loop
+    // below is unrolled three times), never by register copies.
+    auto step = [&](int c, double (&Um)[PER], double (&Uc)[PER], double (&Up)[PER]) {
+        const double cm = c > 0 ? co : 0.0, cp = c < nm - 1 ? co : 0.0;
+        double g[PER];
+        for (int e = tid; e < Z; e += NT) sbuf[e] = 0.0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            double acc = vv * ssn[qb + i * RS] + cf * fr[i] + chx * hx[i] + cm * Um[i] + cp * Up[i];
+            if (IS3) acc += cym * ym[i] + cyp * yp[i];
+            if (i < CI) acc += ccf[i] * cr[i];
+            su[tid + i * NT] = valid ? Uc[i] : 0.0;
+            g[i] = acc;
+        }
+        // every loaded value of position c is consumed above before new loads are issued
+        __builtin_amdgcn_sched_barrier(0);
+        load_row(Um, min(c + 2, nm - 1));
+        load_side(min(c + 1, nm - 1));
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = qb + i * RS;
+            const double* sp = su + tid + i * NT;
+            const double u = sp[0];
+            // time stencil sum_{j<=k} w_j U^{n-j} over the zero-padded tile (w_j = 0 beyond k)
+            double ts = wk[0] * u;
+#pragma unroll
+            for (int j = 1; j < 7; ++j) ts += wk[j] * sp[-j * W];
+            const double au = diag * u - cim * sp[om] - cip * sp[op];
+            const double r = (g[i] - (a.ta * ts + au)) * ssc[q];
+            g[i] = valid ? r : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; ++i) smr[tid + i * NT] = (R)g[i];
+        __syncthreads();
+        lds_fft<R, LOGN, B, NT, false, true, 0>(sm, stw);
+        store_half_spectrum<R, N, B, NT, false>(sm, reinterpret_cast<T*>(a.S), a.ldS, (int)(slot0 + c * sslot), a.Mp);
+        __syncthreads();
+    };
+
+    load_row(A, max(c0 - 1, 0));
+    load_row(Bv, c0);
+    load_row(C, min(c0 + 1, nm - 1));
+    load_side(c0);
+    __syncthreads();   // ssn, ssc, stw
+    for (int c = c0; c < c1; c += 3) {
+        step(c, A, Bv, C);
+        if (c + 1 < c1) step(c + 1, Bv, C, A);
+        if (c + 2 < c1) step(c + 2, C, A, Bv);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -989,6 +1181,28 @@ int persistent_blocks(const void* fn, int nt) {
 #define N_OF(logn) (1 << (logn))
 constexpr int kNTcq = 512;  // the length-2N FP64 convolution FFT needs more lanes per tile
 
+// Marching forward launch: one workgroup per (x tile, line, chunk of the
+// outer axis), with the chunk length chosen so that the grid fills the device once.
+template <typename R, int LOGN, int W, int NT>
+hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
+    const bool is3 = a.mz > 1;
+    const void* fn = is3 ? reinterpret_cast<const void*>(&k_fwd_march<R, LOGN, W, NT, true>)
+                         : reinterpret_cast<const void*>(&k_fwd_march<R, LOGN, W, NT, false>);
+    const int ncol = (a.mxp / W) * (is3 ? a.my : 1);
+    const int nm = is3 ? a.mz : a.my;
+    const int target = persistent_blocks(fn, NT);
+    int nchunk = std::max(1, std::min(nm, (target + ncol - 1) / ncol));
+    const int chunk = (nm + nchunk - 1) / nchunk;
+    nchunk = (nm + chunk - 1) / chunk;
+    const int grid = ((ncol * nchunk + 7) / 8) * 8;
+    if (nb) *nb = grid;
+    if (is3)
+        hipLaunchKernelGGL((k_fwd_march<R, LOGN, W, NT, true>), dim3(grid), dim3(NT), 0, st, a, ncol, nchunk, chunk);
+    else
+        hipLaunchKernelGGL((k_fwd_march<R, LOGN, W, NT, false>), dim3(grid), dim3(NT), 0, st, a, ncol, nchunk, chunk);
+    return hipGetLastError();
+}
+
 template <typename R, int LOGN>
 hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
     if (cq) {
@@ -1000,6 +1214,10 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
     } else {
         constexpr int W = fwd_tile(LOGN);
         constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
+        // the marching kernel addresses with 32-bit byte offsets per lane
+        constexpr int NTM = (N_OF(LOGN) * W >= PINT_MARCH_NT) ? PINT_MARCH_NT : NT;
+        if (a.form == 0 && a.my > 1 && W <= a.mxp && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32))
+            return fwd_march<R, LOGN, W, NTM>(a, nb, st);
         const int ntiles = (a.Mp + W - 1) / W;
         const int grid = ((ntiles + 7) / 8) * 8;
         if (nb) *nb = grid;
