@@ -233,11 +233,16 @@ pint_status validate(const pint_grid* g, const pint_params* p) {
     if (g->dim == 1) {
         if (g->m[0] > pint::kMaxTri1D) return fail(PINT_E_UNSUPPORTED, "1D grids are limited to m <= 2048");
     } else {
+        long long plane = 16;   // complex FP64 slots of one spectrum plane, in bytes
         for (int i = 0; i < g->dim; ++i) {
             const long long L = 2LL * (g->m[i] + 1);
             if (!is_pow2(L) || L < (1 << 3) || L > (1 << pint::kMaxLogL))
                 return fail(PINT_E_UNSUPPORTED, "2D/3D grids need m_i + 1 a power of two in 4..2048");
+            plane *= i == 0 ? (g->m[0] + 15) / 16 * 16 : g->m[i];
         }
+        // the spatial passes address within a spectrum plane with 32-bit byte offsets
+        if (plane >= (1LL << 32) - (1LL << 24))
+            return fail(PINT_E_UNSUPPORTED, "2D/3D grids are limited to spectrum planes below 4 GiB");
     }
     return PINT_OK;
 }

@@ -48,6 +48,32 @@ template <bool INV, typename T> __device__ __forceinline__ T twmul(T a, T w) {
     return INV ? cmulc(a, w) : cmul(a, w);
 }
 
+// Raw buffer access: a scalar descriptor (base, byte extent) plus a 32-bit
+// byte offset per lane.  A load at or beyond the extent returns 0 and a store
+// there is dropped by the hardware, so lanes without work are masked by the
+// offset kNoLane instead of a branch: the number of memory instructions a
+// wave issues stays fixed, and the compiler can count the stores in flight
+// when it waits for earlier loads.
+constexpr unsigned kNoLane = 0xFFFFFFF0u;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned long long bytes) {
+    const unsigned nrec = bytes >= (unsigned long long)kNoLane ? kNoLane : (unsigned)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nrec, 0x00020000);
+}
+__device__ __forceinline__ double2 buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, double2) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ float2 buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, float2) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, float2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
 // e^{-2 pi i j/16}, j = 0..15 (real and imaginary parts), for the
 // constant twiddles inside the in-register radix-8 and radix-16 DFTs.
 __device__ __constant__ double kW16re[16] = {
@@ -190,10 +216,12 @@ __device__ __forceinline__ void fft_stages(cx<R>* s, const cx<R>* __restrict__ t
 // Stockham auto-sort formulation with radix-16/8 stages (radix-4/2 for the
 // remainder), in-register sub-DFTs, and one LDS round trip per stage.
 // Forward: X_k = sum_t x_t e^{-2 pi i t k/L}; INV uses e^{+...} and no 1/L.
-// tw[j] = e^{-2 pi i j/L}, j < L (global, read through the caches).
+// tw[j] = e^{-2 pi i j/L}; the stages only index j < L/2 (in LDS or global memory).
 // Every thread of the block must call it; it ends with a barrier.
+// Always inlined: as a call it would make the caller wait for all of its
+// outstanding loads (prefetches) at the call and spill around it.
 template <typename R, int LOGL, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH = 0>
-__device__ void lds_fft(cx<R>* s, const cx<R>* __restrict__ tw) {
+__device__ __forceinline__ void lds_fft(cx<R>* s, const cx<R>* __restrict__ tw) {
     fft_stages<R, LOGL, 0, B, NT, INV, BFAST, BSTR, PADSH>(s, tw, 1);
 }
 
@@ -421,7 +449,7 @@ __global__ __launch_bounds__(NT, PINT_MARCH_WAVES) void k_fwd_march(FwdArgs a, i
     constexpr int Z = 6 * W;            // six zero rows below time row 0: U^{n-j} = 0 for n - j < 1
     __shared__ double sbuf[Z + N * W];
     __shared__ double ssn[N], ssc[N];   // tau^{-1} s_n and kappa^{q/N}
-    __shared__ T stw[N];                // FFT twiddles, read from LDS so that the FFT never
+    __shared__ T stw[N / 2];            // FFT twiddles, read from LDS so that the FFT never
                                         // waits on the vector-memory counter of the prefetches
     double* su = sbuf + Z;              // su[q W + l] = U^{q+1} at slot l of the tile
     T* sm = reinterpret_cast<T*>(sbuf); // FFT buffer [N][B], reuses the LDS of the tile
@@ -447,7 +475,7 @@ __global__ __launch_bounds__(NT, PINT_MARCH_WAVES) void k_fwd_march(FwdArgs a, i
     for (int i = tid; i < N; i += NT) {
         ssn[i] = a.ta * a.s[i];
         ssc[i] = a.scale[i];
-        stw[i] = reinterpret_cast<const T*>(a.tw)[i];
+        if (i < N / 2) stw[i] = reinterpret_cast<const T*>(a.tw)[i];
     }
     // Coefficients fixed along the march; a missing neighbour reads the centre with weight 0.
     const bool hxm = valid && x > 0 && dl == 0, hxp = valid && x < a.mx - 1 && dl == W - 1;
@@ -664,6 +692,8 @@ __global__ __launch_bounds__(NT, PINT_INV_WAVES) void k_inv(InvArgs a) {
     constexpr int PERS = (NP * B + NT - 1) / NT;
     static_assert(PER * NT == N * W, "tile shape");
     __shared__ cx<R> sm[N * B];
+    __shared__ cx<R> stw[N / 2];    // twiddles w^j, j < N/2 (the only ones the stages use)
+    __shared__ double sun[N];       // kappa^{-q/N}/N
     __shared__ double red[2][NT / 64];
     R* smr = reinterpret_cast<R*>(sm);
     const int tid = threadIdx.x;
@@ -704,6 +734,12 @@ __global__ __launch_bounds__(NT, PINT_INV_WAVES) void k_inv(InvArgs a) {
         const int q = (tid + i * NT) / W;
         u[i] = valid ? a.U[(size_t)q * M + d] : 0.0;
     }
+    // The FFT reads its twiddles from LDS: a global twiddle load there would
+    // wait (in-order vector-memory counter) for the U tile loaded above.
+    // The scaling table too: a global load between the U stores below would
+    // make every store wait for the previous one.
+    for (int j = tid; j < N / 2; j += NT) stw[j] = reinterpret_cast<const cx<R>*>(a.tw)[j];
+    for (int j = tid; j < N; j += NT) sun[j] = a.unscale[j];
 #pragma unroll
     for (int i = 0; i < PERS; ++i) {
         const int idx = tid + i * NT;
@@ -719,7 +755,7 @@ __global__ __launch_bounds__(NT, PINT_INV_WAVES) void k_inv(InvArgs a) {
         }
     }
     __syncthreads();
-    lds_fft<R, LOGN, B, NT, true, true, 0>(sm, reinterpret_cast<const cx<R>*>(a.tw));
+    lds_fft<R, LOGN, B, NT, true, true, 0>(sm, stw);
 
     double mx = 0.0, s2 = 0.0;
     bool bad = false;
@@ -727,7 +763,7 @@ __global__ __launch_bounds__(NT, PINT_INV_WAVES) void k_inv(InvArgs a) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int q = (tid + i * NT) / W;
-            const double delta = (double)smr[q * W + dl] * a.unscale[q];
+            const double delta = (double)smr[q * W + dl] * sun[q];
             const double un = a.form == 0 ? u[i] + delta : delta;
             const double upd = un - u[i];
             a.U[(size_t)q * M + d] = un;
@@ -905,6 +941,13 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
     constexpr int PS = pad_shift(LOGL);
     constexpr int LP = L + (L >> PS);            // padded sequence stride
     __shared__ T sm[ROWS * LP];
+    // Twiddles in LDS (when two workgroups per CU still fit), so that the FFT
+    // does not wait on the vector-memory counter behind the next group's prefetch.
+    constexpr bool TWL = (ROWS * LP + L / 2) * (int)sizeof(T) <= 81920;
+    __shared__ T stw[TWL ? L / 2 : 1];
+    const T* tw = TWL ? stw : reinterpret_cast<const T*>(a.twL[0]);
+    if (TWL)
+        for (int j = threadIdx.x; j < L / 2; j += NT) stw[j] = reinterpret_cast<const T*>(a.twL[0])[j];
     auto ix = [](int b, int t) { return b * LP + t + (t >> PS); };
     const int m = a.mx;
     const int lpp = a.my * a.mz;
@@ -927,16 +970,29 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
                 g < nlines ? (long long)(gu / (unsigned)lpp) * a.ldS + (long long)(gu % (unsigned)lpp) * a.mxp : -1;
         }
     };
-    auto fetch = [&](int slot) {
+    const unsigned long long sbytes = (unsigned long long)a.nP * a.ldS * sizeof(T);
+    // offset of the first row of group grp (uniform, so the descriptor stays scalar)
+    auto first_row = [&](long long grp) {
+        const unsigned g = (unsigned)(grp * ROWS);
+        return (long long)(g / (unsigned)lpp) * a.ldS + (long long)(g % (unsigned)lpp) * a.mxp;
+    };
+    // byte offset of (row b, position t) from the group's first row o0, or kNoLane
+    auto lane_off = [&](int slot, long long o0, int b, int t, bool ok) {
+        const long long off = rowoff[slot][b];
+        return (ok && off >= 0) ? (unsigned)((off - o0 + t) * (long long)sizeof(T)) : kNoLane;
+    };
+    // A group past the end gets an empty descriptor: its loads return 0 without
+    // touching memory, so every iteration issues the same loads.
+    auto fetch = [&](int slot, long long grp) {
+        const bool live = grp < ngroups;
+        const long long o0 = live ? first_row(grp) : 0;
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + o0, live ? sbytes - (unsigned long long)o0 * sizeof(T) : 0);
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = threadIdx.x + i * NT;
-            const int b = e >> LH, t = e & (H - 1);
-            val[i] = zero;
-            if ((ROWS * H) % NT == 0 || e < ROWS * H) {
-                const long long off = rowoff[slot][b];
-                if (t < m && off >= 0) val[i] = S[off + t];
-            }
+            const bool in = (ROWS * H) % NT == 0 || e < ROWS * H;
+            const int b = in ? e >> LH : 0, t = e & (H - 1);
+            val[i] = buf_ld(rs, lane_off(slot, o0, b, t, in && t < m), zero);
         }
     };
     long long grp = blockIdx.x;
@@ -944,7 +1000,7 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
     if (grp < ngroups) {
         offsets(grp, 0);
         __syncthreads();
-        fetch(0);
+        fetch(0, grp);
     }
     for (; grp < ngroups; grp += gridDim.x, slot ^= 1) {
         const long long g0 = grp * ROWS;
@@ -962,10 +1018,10 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
             const int b = threadIdx.x >> 1;
             sm[ix(b, (threadIdx.x & 1) ? m + 1 : 0)] = zero;
         }
-        if (grp + gridDim.x < ngroups) offsets(grp + gridDim.x, slot ^ 1);
+        offsets(grp + gridDim.x, slot ^ 1);
         __syncthreads();
-        if (grp + gridDim.x < ngroups) fetch(slot ^ 1);
-        lds_fft<R, LOGL, ROWS, NT, false, false, LP, PS>(sm, reinterpret_cast<const T*>(a.twL[0]));
+        fetch(slot ^ 1, grp + gridDim.x);
+        lds_fft<R, LOGL, ROWS, NT, false, false, LP, PS>(sm, tw);
         if constexpr (SOLVE) {
             for (int idx = threadIdx.x; idx < ROWS * L; idx += NT) {
                 const int b = idx >> LOGL, t = idx & (L - 1);
@@ -985,16 +1041,16 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
                 sm[ix(b, L - t)] = mk<T>(-z.x, -z.y);
             }
             __syncthreads();
-            lds_fft<R, LOGL, ROWS, NT, false, false, LP, PS>(sm, reinterpret_cast<const T*>(a.twL[0]));
+            lds_fft<R, LOGL, ROWS, NT, false, false, LP, PS>(sm, tw);
         }
+        const long long o0 = first_row(grp);
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + o0, sbytes - (unsigned long long)o0 * sizeof(T));
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = threadIdx.x + i * NT;
-            const int b = e >> LH, t = (e & (H - 1)) + 1;
-            if (((ROWS * H) % NT == 0 || e < ROWS * H) && t <= m) {
-                const long long off = rowoff[slot][b];
-                if (off >= 0) S[off + t - 1] = sm[ix(b, t)];
-            }
+            const bool in = (ROWS * H) % NT == 0 || e < ROWS * H;
+            const int b = in ? e >> LH : 0, t = (e & (H - 1)) + 1;
+            buf_st(rs, lane_off(slot, o0, b, t - 1, in && t <= m), sm[ix(b, t)]);
         }
         __syncthreads();
     }
@@ -1008,7 +1064,14 @@ template <typename R, int LOGL, int W, int NT, bool SOLVE>
 __global__ __launch_bounds__(NT) void k_dst_cols(SpaceArgs a, int axis) {
     using T = cx<R>;
     constexpr int L = 1 << LOGL;
+    static_assert(NT % W == 0, "a lane keeps one column");
     __shared__ T sm[L * W];
+    // Twiddles (when they fit) and the eigenvalues of the transformed axis in
+    // LDS, so that neither the FFT nor the divide waits on the vector-memory
+    // counter behind the next group's prefetch.
+    constexpr bool TWL = (L * W + L / 2) * (int)sizeof(T) + (L / 2) * 8 <= 155648;
+    __shared__ T stw[TWL ? L / 2 : 1];
+    __shared__ double smu[SOLVE ? L / 2 : 1];
     const int m = axis == 1 ? a.my : a.mz;
     const long long st = axis == 1 ? (long long)a.mxp : (long long)a.mxp * a.my;
     const int other = axis == 1 ? a.mz : a.my;
@@ -1016,7 +1079,12 @@ __global__ __launch_bounds__(NT) void k_dst_cols(SpaceArgs a, int axis) {
     const long long ngroups = (long long)a.nP * other * nxg;
     T* S = reinterpret_cast<T*>(a.S);
     const T zero = mk<T>((R)0, (R)0);
-    const T* tw = reinterpret_cast<const T*>(a.twL[axis]);
+    const T* tw = TWL ? stw : reinterpret_cast<const T*>(a.twL[axis]);
+    if (TWL)
+        for (int j = threadIdx.x; j < L / 2; j += NT) stw[j] = reinterpret_cast<const T*>(a.twL[axis])[j];
+    if (SOLVE)
+        for (int j = threadIdx.x; j < m; j += NT) smu[j] = a.mu[axis][j];
+    const int wl = threadIdx.x % W;      // the column this lane loads, stores and scales
     struct Grp {
         int p, o, x0;
         long long base;
@@ -1033,66 +1101,91 @@ __global__ __launch_bounds__(NT) void k_dst_cols(SpaceArgs a, int axis) {
         return g;
     };
     // Persistent workgroups with the next group's loads (rows of W contiguous
-    // values) issued before the current group's transforms.
+    // values, and the x eigenvalue of the lane's column) issued before the
+    // current group's transforms.
     constexpr int PER = ((L / 2 - 1) * W + NT - 1) / NT;
     T val[PER];
-    auto fetch = [&](const Grp& g) {
+    double mux_next = 0.0, muo_next = 0.0;   // x eigenvalue of the lane's column, eigenvalue of the other axis
+    double2 sg_next = double2{};             // sigma_p of the group
+    const unsigned long long sbytes = (unsigned long long)a.nP * a.ldS * sizeof(T);
+    // byte offset of row t of the lane's column from the group base, or kNoLane
+    auto lane_off = [&](int t, bool ok) {
+        return ok ? (unsigned)(((long long)t * st + wl) * (long long)sizeof(T)) : kNoLane;
+    };
+    // A group past the end (live = false) gets an empty descriptor: its loads
+    // return 0 without touching memory, so every iteration issues the same loads.
+    auto fetch = [&](const Grp& g, bool live) {
+        const bool colok = live && g.x0 + wl < a.mx;
+        const long long b0 = live ? g.base : 0;
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + b0, live ? sbytes - (unsigned long long)b0 * sizeof(T) : 0);
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int idx = threadIdx.x + i * NT;
-            val[i] = zero;
-            if (idx < m * W) {
-                const int t = idx / W, w = idx % W;
-                if (g.x0 + w < a.mx) val[i] = S[g.base + t * st + w];
-            }
+            val[i] = buf_ld(rs, lane_off(idx / W, colok && idx < m * W), zero);
+        }
+        if (SOLVE) {
+            mux_next = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                      buf_rsrc(a.mu[0], (unsigned long long)a.mx * 8),
+                                                      (int)(colok ? (unsigned)(g.x0 + wl) * 8u : kNoLane), 0, 0));
+            sg_next = buf_ld(buf_rsrc(a.sigma, (unsigned long long)a.nP * 16), live ? (unsigned)g.p * 16u : kNoLane,
+                             double2{});
+            muo_next = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                      buf_rsrc(a.mu[1], (unsigned long long)a.my * 8),
+                                                      (int)(live && axis == 2 ? (unsigned)g.o * 8u : kNoLane), 0, 0));
         }
     };
     long long gid = blockIdx.x;
-    if (gid < ngroups) fetch(decode(gid));
+    if (gid < ngroups) fetch(decode(gid), true);
     for (; gid < ngroups; gid += gridDim.x) {
         const Grp g = decode(gid);
+        const double mux = mux_next, muo = muo_next;
+        const double2 sg = sg_next;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int idx = threadIdx.x + i * NT;
             if (idx < m * W) {
-                const int t = idx / W + 1, w = idx % W;
-                sm[t * W + w] = val[i];
-                sm[(L - t) * W + w] = mk<T>(-val[i].x, -val[i].y);
+                const int t = idx / W + 1;
+                sm[t * W + wl] = val[i];
+                sm[(L - t) * W + wl] = mk<T>(-val[i].x, -val[i].y);
             }
         }
-        if (threadIdx.x < 2 * W) {
-            const int w = threadIdx.x % W;
-            sm[((threadIdx.x < W) ? 0 : m + 1) * W + w] = zero;
-        }
+        if (threadIdx.x < 2 * W) sm[((threadIdx.x < W) ? 0 : m + 1) * W + wl] = zero;
         __syncthreads();
-        if (gid + gridDim.x < ngroups) fetch(decode(gid + gridDim.x));
+        fetch(decode(gid + gridDim.x), gid + gridDim.x < ngroups);
         lds_fft<R, LOGL, W, NT, false, true, 0>(sm, tw);
         if constexpr (SOLVE) {
-            const double2 sg = a.sigma[g.p];
+            const double base_re = sg.x + (axis == 2 ? muo : 0.0) + mux;
+            const bool colok = g.x0 + wl < a.mx;
             for (int idx = threadIdx.x; idx < (m + 2) * W; idx += NT) {
-                const int t = idx / W, w = idx % W;
+                const int t = idx / W;
                 if (t == 0 || t == m + 1) {
-                    sm[t * W + w] = zero;
-                } else if (g.x0 + w >= a.mx) {
-                    sm[t * W + w] = zero;
-                    sm[(L - t) * W + w] = zero;
+                    sm[t * W + wl] = zero;
+                } else if (!colok) {
+                    sm[t * W + wl] = zero;
+                    sm[(L - t) * W + wl] = zero;
                 } else {
-                    double dre = sg.x + a.mu[0][g.x0 + w] + a.mu[axis][t - 1];
-                    if (axis == 2) dre += a.mu[1][g.o];
+                    const double dre = base_re + smu[t - 1];
                     const double dim_ = sg.y;
                     const double inv = a.inv_factor / (dre * dre + dim_ * dim_);
                     const T c = mk<T>((R)(dre * inv), (R)(-dim_ * inv));
-                    const T z = cmul(sm[t * W + w], c);
-                    sm[t * W + w] = z;
-                    sm[(L - t) * W + w] = mk<T>(-z.x, -z.y);
+                    const T z = cmul(sm[t * W + wl], c);
+                    sm[t * W + wl] = z;
+                    sm[(L - t) * W + wl] = mk<T>(-z.x, -z.y);
                 }
             }
             __syncthreads();
             lds_fft<R, LOGL, W, NT, false, true, 0>(sm, tw);
         }
-        for (int idx = threadIdx.x; idx < m * W; idx += NT) {
-            const int t = idx / W + 1, w = idx % W;
-            if (g.x0 + w < a.mx) S[g.base + (t - 1) * st + w] = sm[t * W + w];
+        {
+            const bool colok = g.x0 + wl < a.mx;
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + g.base, sbytes - (unsigned long long)g.base * sizeof(T));
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int idx = threadIdx.x + i * NT;
+                const bool ok = colok && idx < m * W;
+                const int t = ok ? idx / W + 1 : 1;
+                buf_st(rs, lane_off(t - 1, ok), sm[t * W + wl]);
+            }
         }
         __syncthreads();
     }
@@ -1163,6 +1256,9 @@ template <typename R> constexpr int cols_per_block(int logl) {
 }
 
 constexpr int kNT = 256;
+#ifndef PINT_INV_NT
+#define PINT_INV_NT 512
+#endif
 
 // Workgroups that fit on the whole device at once for a kernel (persistent
 // launches); cached per kernel.
@@ -1232,7 +1328,8 @@ hipError_t inv_one(const InvArgs& a, int* nb, hipStream_t st) {
     const int ntiles = (a.Mp + W - 1) / W;
     const int grid = ((ntiles + 7) / 8) * 8;
     if (nb) *nb = grid;
-    hipLaunchKernelGGL((k_inv<R, LOGN, W, kNT>), dim3(grid), dim3(kNT), 0, st, a);
+    constexpr int NT = (N_OF(LOGN) * W >= PINT_INV_NT) ? PINT_INV_NT : kNT;
+    hipLaunchKernelGGL((k_inv<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1297,11 +1394,12 @@ hipError_t tri1d_dispatch(const SpaceArgs& a, hipStream_t st) {
 template <typename R, int LOGL, bool SOLVE>
 hipError_t rows_one(const SpaceArgs& a, hipStream_t st) {
     constexpr int ROWS = rows_per_block<R>(LOGL);
+    constexpr int NT = kNT;
     const long long nlines = (long long)a.nP * a.my * a.mz;
     const long long groups = (nlines + ROWS - 1) / ROWS;
     const long long grid = std::min<long long>(groups, persistent_blocks(reinterpret_cast<const void*>(
-                                                           &k_dst_rows<R, LOGL, ROWS, kNT, SOLVE>), kNT));
-    hipLaunchKernelGGL((k_dst_rows<R, LOGL, ROWS, kNT, SOLVE>), dim3((unsigned)grid), dim3(kNT), 0, st, a, nlines);
+                                                           &k_dst_rows<R, LOGL, ROWS, NT, SOLVE>), NT));
+    hipLaunchKernelGGL((k_dst_rows<R, LOGL, ROWS, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, nlines);
     return hipGetLastError();
 }
 
@@ -1309,7 +1407,8 @@ template <typename R, int LOGL, bool SOLVE>
 hipError_t cols_one(const SpaceArgs& a, int axis, hipStream_t st) {
     constexpr int W = cols_per_block<R>(LOGL);
     // tiles above 64 KB of LDS get 512 lanes so the FFT stages stay in registers
-    constexpr int NT = ((1 << LOGL) * W * (int)sizeof(cx<R>) > 65536) ? 512 : kNT;
+    // (FP64 tiles of 64 KB as well: measured faster with 8 waves per workgroup)
+    constexpr int NT = ((1 << LOGL) * W * (int)sizeof(cx<R>) > 65536 || sizeof(R) == 8) ? 512 : kNT;
     const int other = axis == 1 ? a.mz : a.my;
     const long long groups = (long long)a.nP * other * ((a.mx + W - 1) / W);
     const long long grid = std::min<long long>(

@@ -51,7 +51,7 @@ def test_invalid_params_rejected(change, status):
 
 @pytest.mark.parametrize("m,status", [((0,), B.PINT_E_ARG), ((4096,), B.PINT_E_UNSUPPORTED),
                                       ((100, 127), B.PINT_E_UNSUPPORTED), ((127, 1), B.PINT_E_UNSUPPORTED),
-                                      ((7, 7, 9), B.PINT_E_UNSUPPORTED)])
+                                      ((7, 7, 9), B.PINT_E_UNSUPPORTED), ((1023, 1023, 511), B.PINT_E_UNSUPPORTED)])
 def test_invalid_grids_rejected(m, status):
     st, h = _create(B.make_grid(m), B.make_params(2, 1.0, 1.0, 64, 1e-3))
     assert st == status
