@@ -438,6 +438,9 @@ __global__ __launch_bounds__(NT, PINT_FWD_WAVES) void k_fwd_heat(FwdArgs a) {
 #ifndef PINT_MARCH_NT
 #define PINT_MARCH_NT 512
 #endif
+#ifndef PINT_FWD_WIDE
+#define PINT_FWD_WIDE 1
+#endif
 template <typename R, int LOGN, int W, int NT, bool IS3>
 __global__ __launch_bounds__(NT, PINT_MARCH_WAVES) void k_fwd_march(FwdArgs a, int ncol, int nchunk, int chunk) {
     using T = cx<R>;
@@ -602,6 +605,195 @@ __global__ __launch_bounds__(NT, PINT_MARCH_WAVES) void k_fwd_march(FwdArgs a, i
         step(c, A, Bv, C);
         if (c + 1 < c1) step(c + 1, Bv, C, A);
         if (c + 2 < c1) step(c + 2, C, A, Bv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward kernel, BDF-k residual form on 2D and 3D grids: wide-tile march.
+// The same march as k_fwd_march, laid out for wider tiles (W = 16 FP64 slots,
+// whole 128-byte row segments per load, for N = 512) within the register file:
+//  - U at the previous outer index is read back from the LDS tile of the
+//    previous position (each lane reads and rewrites only its own elements),
+//    so only U at c and c+1 are held in registers;
+//  - the partial sums of Phase A go to a separate LDS buffer, which Phase B
+//    overwrites in place with the residual and the FFT then transforms, so no
+//    per-element sum stays in registers across the barrier (FP64 spectra);
+//  - the x neighbours outside the tile are loaded by the two edge lanes only
+//    (every other lane's load is masked off) and written to halo columns of
+//    the LDS tile, so Phase B applies one stencil to every slot.
+template <typename R, int LOGN, int W, int NT, bool IS3>
+__global__ __launch_bounds__(NT, 1) void k_fwd_wide(FwdArgs a, int ncol, int nchunk, int chunk) {
+    using T = cx<R>;
+    constexpr int N = 1 << LOGN;
+    constexpr int B = W / 2;
+    constexpr int PER = N * W / NT;
+    static_assert(PER * NT == N * W, "tile shape");
+    constexpr int RS = NT / W;                       // time rows between row groups i and i+1
+    constexpr int WS = W + 2;                        // LDS row: halo, W slots, halo
+    constexpr int Z = 6;                             // zero time rows below row 0
+    constexpr int CI = (6 * W + NT - 1) / NT < PER ? (6 * W + NT - 1) / NT : PER;
+    __shared__ double su[(Z + N) * WS];
+    __shared__ double sg[N * W];
+    __shared__ double ssn[N], ssc[N];                // tau^{-1} s_n and kappa^{q/N}
+    __shared__ T stw[N / 2];
+    double* u0 = su + Z * WS + 1;                    // u0[q WS + l]: slot l of time row q (l = -1, W: halo)
+    T* sm = reinterpret_cast<T*>(sg);                // FFT buffer [N][B]
+    R* smr = reinterpret_cast<R*>(sg);
+
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    if (lin >= ncol * nchunk) return;
+    const int col = lin % ncol, chk = lin / ncol;
+    const int nxt = a.mxp / W;
+    const int xt = col % nxt, yl = col / nxt;
+    const int nm = IS3 ? a.mz : a.my;
+    const int c0 = chk * chunk, c1 = min(nm, c0 + chunk);
+    const int tid = threadIdx.x;
+    const int dl = tid % W, qb = tid / W;
+    const int x0 = xt * W, x = x0 + dl;
+    const bool valid = x < a.mx;
+    const size_t M = a.M;
+    const long long sdof = IS3 ? (long long)a.mx * a.my : a.mx;
+    const long long sslot = IS3 ? (long long)a.mxp * a.my : a.mxp;
+    const long long dbase = (valid ? x : 0) + (IS3 ? (long long)a.mx * yl : 0);
+    const long long slot0 = (long long)x0 + (IS3 ? (long long)a.mxp * yl : 0);
+
+    for (int i = tid; i < N; i += NT) {
+        ssn[i] = a.ta * a.s[i];
+        ssc[i] = a.scale[i];
+        if (i < N / 2) stw[i] = reinterpret_cast<const T*>(a.tw)[i];
+    }
+    for (int j = tid; j < Z * WS; j += NT) su[j] = 0.0;
+
+    // halo loads: lane dl = 0 reads x0 - 1, lane dl = W-1 reads x0 + W; all others, and
+    // neighbours outside the grid, are masked off (they read 0 without a memory access)
+    const bool hl = dl == 0 && x0 > 0, hr = dl == W - 1 && x0 + W < a.mx;
+    const long long ohx = hl ? -1 : (hr ? 1 : 0);
+    const double cym = (IS3 && valid && yl > 0) ? a.ihy2 : 0.0;
+    const double cyp = (IS3 && valid && yl < a.my - 1) ? a.ihy2 : 0.0;
+    const long long oym = cym != 0.0 ? -(long long)a.mx : 0, oyp = cyp != 0.0 ? (long long)a.mx : 0;
+    const double co = valid ? (IS3 ? a.ihz2 : a.ihy2) : 0.0;
+    const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
+    const double cx = a.ihx2;
+    double wk[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) wk[j] = a.wk[j];
+
+    const unsigned lo = (unsigned)(((long long)qb * (long long)M + dbase) * 8);
+    const unsigned lhx = (hl || hr) ? (unsigned)((long long)lo + ohx * 8) : kNoLane;
+    const unsigned lym = (unsigned)((long long)lo + oym * 8), lyp = (unsigned)((long long)lo + oyp * 8);
+    const unsigned lv = (unsigned)(dbase * 8);
+    const double cf = a.f ? 1.0 : 0.0;
+    const double* fbase = a.f ? a.f + M : a.U;
+    const double* cbase = a.ncorr > 0 ? a.corr : a.U;
+    const size_t nU = (size_t)a.N * M;
+    const size_t nC = a.ncorr > 0 ? (size_t)a.ncorr * M : nU;
+    double ccf[CI];
+    unsigned lcr[CI];
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+        const int q = qb + i * RS;
+        ccf[i] = q < a.ncorr ? 1.0 : 0.0;
+        lcr[i] = (unsigned)(((long long)(q < a.ncorr ? q : 0) * (long long)M + dbase) * 8);
+    }
+    auto at = [](const double* arr, size_t n, size_t e0, unsigned off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                              buf_rsrc(arr + e0, (unsigned long long)(n - e0) * 8ull), (int)off, 0, 0));
+    };
+    double A[PER], Bv[PER], fr[PER], hx[PER], ym[PER], yp[PER], cr[CI];
+    double vv;
+    auto load_row = [&](double (&dst)[PER], int c) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) dst[i] = at(a.U, nU, (size_t)i * RS * M + (size_t)c * sdof, lo);
+    };
+    auto load_side = [&](int c) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const size_t e0 = (size_t)i * RS * M + (size_t)c * sdof;
+            hx[i] = at(a.U, nU, e0, lhx);
+            if (IS3) {
+                ym[i] = at(a.U, nU, e0, lym);
+                yp[i] = at(a.U, nU, e0, lyp);
+            }
+            fr[i] = at(fbase, nU, e0, lo);
+        }
+#pragma unroll
+        for (int i = 0; i < CI; ++i) cr[i] = at(cbase, nC, (size_t)c * sdof, lcr[i]);
+        vv = at(a.v, M, (size_t)c * sdof, lv);
+    };
+    // LDS index of element i of this lane: (q_i, dl) with q_i = qb + i RS
+    const int sb = qb * WS + dl;
+    constexpr int SSTEP = RS * WS;
+
+    // One position c with U at c and c+1 in Uc, Up (Uc is refilled with U at c+2).
+    auto step = [&](int c, double (&Uc)[PER], double (&Up)[PER]) {
+        const double cm = c > 0 ? co : 0.0, cp = c < nm - 1 ? co : 0.0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = qb + i * RS;
+            double* p = u0 + sb + i * SSTEP;
+            double acc = vv * ssn[q] + cf * fr[i] + cm * p[0] + cp * Up[i];   // p[0]: U at c-1
+            if (IS3) acc += cym * ym[i] + cyp * yp[i];
+            if (i < CI) acc += ccf[i] * cr[i];
+            p[0] = valid ? Uc[i] : 0.0;
+            if (dl == 0) p[-1] = hx[i];
+            if (dl == W - 1) p[1] = hx[i];
+            sg[tid + i * NT] = acc;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        load_row(Uc, min(c + 2, nm - 1));
+        load_side(min(c + 1, nm - 1));
+        __syncthreads();
+        if constexpr (sizeof(R) == 8) {
+            // LDS to LDS: a partial unroll keeps the hoisted stencil reads few
+#pragma unroll 2
+            for (int i = 0; i < PER; ++i) {
+                const int q = qb + i * RS;
+                const double* p = u0 + sb + i * SSTEP;
+                const double u = p[0];
+                double ts = wk[0] * u;
+#pragma unroll
+                for (int j = 1; j < 7; ++j) ts += wk[j] * p[-j * WS];
+                const double au = diag * u - cx * (p[-1] + p[1]);
+                const double r = (sg[tid + i * NT] - (a.ta * ts + au)) * ssc[q];
+                sg[tid + i * NT] = valid ? r : 0.0;
+            }
+            __syncthreads();
+        } else {
+            R rr[PER];
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int q = qb + i * RS;
+                const double* p = u0 + sb + i * SSTEP;
+                const double u = p[0];
+                double ts = wk[0] * u;
+#pragma unroll
+                for (int j = 1; j < 7; ++j) ts += wk[j] * p[-j * WS];
+                const double au = diag * u - cx * (p[-1] + p[1]);
+                const double r = (sg[tid + i * NT] - (a.ta * ts + au)) * ssc[q];
+                rr[i] = valid ? (R)r : (R)0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < PER; ++i) smr[tid + i * NT] = rr[i];
+            __syncthreads();
+        }
+        lds_fft<R, LOGN, B, NT, false, true, 0>(sm, stw);
+        store_half_spectrum<R, N, B, NT, false>(sm, reinterpret_cast<T*>(a.S), a.ldS, (int)(slot0 + c * sslot), a.Mp);
+        __syncthreads();
+    };
+
+    // prologue: U at c0 - 1 into the LDS tile, U at c0 and c0 + 1 and the rest of c0 into registers
+    load_row(A, max(c0 - 1, 0));
+    __syncthreads();   // tables and zero rows
+#pragma unroll
+    for (int i = 0; i < PER; ++i) u0[sb + i * SSTEP] = valid ? A[i] : 0.0;
+    load_row(A, c0);
+    load_row(Bv, min(c0 + 1, nm - 1));
+    load_side(c0);
+    __syncthreads();
+    for (int c = c0; c < c1; c += 2) {
+        step(c, A, Bv);
+        if (c + 1 < c1) step(c + 1, Bv, A);
     }
 }
 
@@ -1279,11 +1471,14 @@ constexpr int kNTcq = 512;  // the length-2N FP64 convolution FFT needs more lan
 
 // Marching forward launch: one workgroup per (x tile, line, chunk of the
 // outer axis), with the chunk length chosen so that the grid fills the device once.
-template <typename R, int LOGN, int W, int NT>
+template <typename R, int LOGN, int W, int NT, bool WIDE>
 hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
     const bool is3 = a.mz > 1;
-    const void* fn = is3 ? reinterpret_cast<const void*>(&k_fwd_march<R, LOGN, W, NT, true>)
-                         : reinterpret_cast<const void*>(&k_fwd_march<R, LOGN, W, NT, false>);
+    auto kern = [](bool three) {
+        if constexpr (WIDE) return (void)three, &k_fwd_wide<R, LOGN, W, NT, false>;   // 2D only
+        else return three ? &k_fwd_march<R, LOGN, W, NT, true> : &k_fwd_march<R, LOGN, W, NT, false>;
+    };
+    const void* fn = reinterpret_cast<const void*>(kern(is3));
     const int ncol = (a.mxp / W) * (is3 ? a.my : 1);
     const int nm = is3 ? a.mz : a.my;
     const int target = persistent_blocks(fn, NT);
@@ -1292,10 +1487,7 @@ hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
     nchunk = (nm + chunk - 1) / chunk;
     const int grid = ((ncol * nchunk + 7) / 8) * 8;
     if (nb) *nb = grid;
-    if (is3)
-        hipLaunchKernelGGL((k_fwd_march<R, LOGN, W, NT, true>), dim3(grid), dim3(NT), 0, st, a, ncol, nchunk, chunk);
-    else
-        hipLaunchKernelGGL((k_fwd_march<R, LOGN, W, NT, false>), dim3(grid), dim3(NT), 0, st, a, ncol, nchunk, chunk);
+    hipLaunchKernelGGL(kern(is3), dim3(grid), dim3(NT), 0, st, a, ncol, nchunk, chunk);
     return hipGetLastError();
 }
 
@@ -1312,8 +1504,18 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
         constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
         // the marching kernel addresses with 32-bit byte offsets per lane
         constexpr int NTM = (N_OF(LOGN) * W >= PINT_MARCH_NT) ? PINT_MARCH_NT : NT;
-        if (a.form == 0 && a.my > 1 && W <= a.mxp && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32))
-            return fwd_march<R, LOGN, W, NTM>(a, nb, st);
+        // wide tiles (2D): 16 slots (128-byte rows of FP64) for N <= 512, up to 512 lanes
+        constexpr int WW = 16;
+        constexpr int NTW = N_OF(LOGN) * WW < 512 ? N_OF(LOGN) * WW : 512;
+        constexpr bool WIDE_OK = LOGN <= 9 && PINT_FWD_WIDE;
+        if (a.form == 0 && a.my > 1) {
+            if constexpr (WIDE_OK)
+                if (a.mz == 1 && WW <= a.mxp && (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32))
+                    return fwd_march<R, LOGN, WW, NTW, true>(a, nb, st);
+            // the marching kernels address with 32-bit byte offsets per lane
+            if (W <= a.mxp && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32))
+                return fwd_march<R, LOGN, W, NTM, false>(a, nb, st);
+        }
         const int ntiles = (a.Mp + W - 1) / W;
         const int grid = ((ntiles + 7) / 8) * 8;
         if (nb) *nb = grid;
