@@ -46,7 +46,7 @@ def measured_traffic(precision, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE record, or None when the kernel source changed since it was taken."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "heat2d_255x255_N512_bdf4_traffic.json")
+    rec_path = PROFILE_STEM + "_traffic.json"
     try:
         rec = json.load(open(rec_path))
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
@@ -134,13 +134,111 @@ def cpu_baseline(seconds_hint=20.0):
                       f"(same recipe as the timed workload); {t:.1f} s; host logical CPUs {os.cpu_count()}"}
 
 
+PROFILE_STEM = os.path.join(ROOT, "profiles", "heat2d_255x255_N512_bdf4")
+KERNEL_SOURCE = "paper_2007_13125_amd/csrc/pint_kernels.hip"
+COPY_BYTES = 256 << 20
+
+
+def slot_of(kernel):
+    """Profile slot of a kernel symbol of the 2D sweep (bench workload)."""
+    if "k_fwd_" in kernel:
+        return "forward_rhs_tfft"
+    if "k_dst_rows" in kernel:
+        return "dst_x"
+    if "k_dst_cols" in kernel:
+        return "dst_y_solve"
+    if "k_inv" in kernel:
+        return "inverse_tfft_update"
+    return None
+
+
+def summarize(outdir):
+    """Write the committed profile summary (markdown) and the HBM traffic record
+    that bench.py reads, from rocprofv3 CSV output of the three runs listed in
+    the summary: <outdir>/trace (--kernel-trace --stats), <outdir>/FETCH_SIZE and
+    <outdir>/WRITE_SIZE (--pmc), each of `bench.py --steps 5 --warmup 1
+    --no-cpu-baseline --copy-calibration`."""
+    import csv
+    import glob
+    import hashlib
+    from collections import defaultdict
+
+    def rows(sub, suffix):
+        paths = glob.glob(os.path.join(outdir, sub, "**", "*" + suffix), recursive=True)
+        if not paths:
+            raise SystemExit(f"no *{suffix} under {os.path.join(outdir, sub)}")
+        return list(csv.DictReader(open(paths[0])))
+
+    def short(name):
+        return name.replace("void pint::(anonymous namespace)::", "").replace("pint::", "").split("(")[0]
+
+    stats = rows("trace", "kernel_stats.csv")
+    counters = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        per = defaultdict(list)
+        for r in rows(c, "counter_collection.csv"):
+            per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        counters[c] = per
+    # calibration: the largest device copy (the 256 MiB copy of --copy-calibration)
+    copies = [k for k in counters["FETCH_SIZE"] if "copyBuffer" in k]
+    fcal = max(max(counters["FETCH_SIZE"][k]) for k in copies)
+    wcal = max(max(counters["WRITE_SIZE"][k]) for k in copies)
+    rf, wf = COPY_BYTES / (fcal * 1024), COPY_BYTES / (wcal * 1024)
+    src = open(os.path.join(ROOT, KERNEL_SOURCE), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()
+    rec = {"workload": "heat2d 255x255 N=512 BDF4 kappa=1e-5", "source": KERNEL_SOURCE, "source_sha256": sha,
+           "calibration": {"copy_bytes": COPY_BYTES, "FETCH_SIZE_KiB": fcal, "WRITE_SIZE_KiB": wcal,
+                           "read_factor": rf, "write_factor": wf},
+           "kernels": {"fp64": {}, "mixed": {}}}
+    lines = ["# Kernel profile: 2D heat 255x255, N=512, BDF4, kappa=1e-5 (bench workload)", "",
+             f"Device: one MI355X (gfx950).  Source: `{KERNEL_SOURCE}` sha256 prefix `{sha[:16]}`.", "",
+             "Commands (run from /tmp with TMPDIR=/tmp; each writes CSV under the -d folder), then "
+             "`python bench.py --summarize <out>` writes this file and the traffic record:", "", "```"]
+    cmd = "python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --copy-calibration"
+    lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o heat2d -- {cmd}",
+              f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/FETCH_SIZE -o heat2d -- {cmd}",
+              f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/WRITE_SIZE -o heat2d -- {cmd}",
+              "```", "",
+              "bench.py runs the FP64 plan (kernels `<double,...>`) and the mixed plan (`<float,...>`), each for "
+              "warmup + timed + time-to-1e-10 sweeps.", "", "## --kernel-trace --stats", "",
+              "| kernel | calls | average us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{short(r['Name'])[:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    lines += ["", "## --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch, mean over dispatches)", "",
+              f"Calibration: a plain {COPY_BYTES >> 20} MiB device copy read FETCH_SIZE = {fcal:.0f} KiB and "
+              f"WRITE_SIZE = {wcal:.0f} KiB, so HBM read bytes = {rf:.3f} x FETCH_SIZE KiB x 1024 and write "
+              f"bytes = {wf:.3f} x WRITE_SIZE KiB x 1024.", "",
+              "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | write MB |", "|---|---|---|---|---|"]
+    for k, vals in counters["FETCH_SIZE"].items():
+        slot = slot_of(k)
+        if slot is None:
+            continue
+        fk = sum(vals) / len(vals)
+        wk = sum(counters["WRITE_SIZE"][k]) / len(counters["WRITE_SIZE"][k])
+        rd, wr = rf * fk * 1024, wf * wk * 1024
+        prec = "mixed" if "<float" in k else "fp64"
+        rec["kernels"][prec][slot] = {"read": rd, "write": wr}
+        lines.append(f"| `{short(k)}` | {fk:.4g} | {wk:.4g} | {rd / 1e6:.1f} | {wr / 1e6:.1f} |")
+    open(PROFILE_STEM + "_kernels.md", "w").write("\n".join(lines) + "\n")
+    json.dump(rec, open(PROFILE_STEM + "_traffic.json", "w"), indent=1)
+    print(f"wrote {PROFILE_STEM}_kernels.md and _traffic.json")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy 256 MiB on the device (counter calibration for profiles)")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="write the profile summary from rocprofv3 CSV output in DIR and exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sharded multi-GPU "
               f"design is described in DESIGN.md and is not built.", file=sys.stderr)
@@ -211,6 +309,12 @@ def main():
     for p in plans.values():
         p[0].close()
     print(json.dumps(res), flush=True)
+    if args.copy_calibration:
+        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
