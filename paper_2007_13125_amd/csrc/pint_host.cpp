@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,10 @@ struct pint_plan {
     double *d_an = nullptr, *d_blt = nullptr, *d_mu[3] = {nullptr, nullptr, nullptr};
     double2 *d_sigma = nullptr, *d_what = nullptr, *d_tw2 = nullptr;
     void *d_twN = nullptr, *d_twL[3] = {nullptr, nullptr, nullptr};
+    // Bluestein tables of the axes whose 2(m+1) is not a power of two
+    int logP[3] = {0, 0, 0};
+    void *d_chirp[3] = {nullptr, nullptr, nullptr}, *d_bh[3] = {nullptr, nullptr, nullptr};
+    void *d_twP[3] = {nullptr, nullptr, nullptr};
     double wk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double inv_factor = 1.0;
     // workspace
@@ -207,6 +212,67 @@ pint_status upload_tw(pint_plan* P, void** dst, long long L, bool single) {
     return s;
 }
 
+// In-place radix-2 FFT, X_k = sum_j x_j e^{-2 pi i jk/n}, n a power of two (host, long double).
+void host_fft(std::vector<cld>& x) {
+    const size_t n = x.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(x[i], x[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1)
+        for (size_t i = 0; i < n; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const cld w = twiddle((long long)(k * (n / len)), (long long)n);
+                const cld u = x[i + k], v = x[i + k + len / 2] * w;
+                x[i + k] = u + v;
+                x[i + k + len / 2] = u - v;
+            }
+}
+
+template <typename C>
+pint_status upload_cld(pint_plan* P, void** dst, const std::vector<cld>& v) {
+    std::vector<C> t(v.size());
+    for (size_t j = 0; j < v.size(); ++j) {
+        t[j].x = (decltype(t[j].x))v[j].real();
+        t[j].y = (decltype(t[j].y))v[j].imag();
+    }
+    C* q = nullptr;
+    pint_status s = upload(P, &q, t.data(), t.size());
+    *dst = q;
+    return s;
+}
+
+// Tables of the Bluestein sine transform of an axis with m interior nodes:
+// L = 2(m+1), chirp c_t = e^{-pi i t^2/L} (t < L, argument reduced mod 2L),
+// Bh = FFT_P(b)/P with b_l = conj(c_|l|) for |l| < L wrapped mod P, P >= 2L-1.
+pint_status upload_bluestein(pint_plan* P, int axis, int m) {
+    const long long L = 2LL * (m + 1);
+    int logp = 4;   // P >= 16, the smallest transform the kernels are built for
+    while ((1LL << logp) < 2 * L - 1) ++logp;
+    const long long Pn = 1LL << logp;
+    std::vector<cld> c(L), b(Pn, cld(0, 0));
+    for (long long t = 0; t < L; ++t) c[t] = twiddle((t * t) % (2 * L), 2 * L);
+    for (long long l = 0; l < L; ++l) {
+        b[l] = std::conj(c[l]);
+        if (l > 0) b[Pn - l] = std::conj(c[l]);
+    }
+    host_fft(b);
+    for (auto& z : b) z /= (long double)Pn;
+    pint_status rc;
+    if (P->mixed) {
+        if ((rc = upload_cld<float2>(P, &P->d_chirp[axis], c)) != PINT_OK) return rc;
+        if ((rc = upload_cld<float2>(P, &P->d_bh[axis], b)) != PINT_OK) return rc;
+    } else {
+        if ((rc = upload_cld<double2>(P, &P->d_chirp[axis], c)) != PINT_OK) return rc;
+        if ((rc = upload_cld<double2>(P, &P->d_bh[axis], b)) != PINT_OK) return rc;
+    }
+    if ((rc = upload_tw(P, &P->d_twP[axis], Pn, P->mixed)) != PINT_OK) return rc;
+    P->logP[axis] = logp;
+    return PINT_OK;
+}
+
 pint_status validate(const pint_grid* g, const pint_params* p) {
     if (!g || !p) return fail(PINT_E_ARG, "grid and params must not be NULL");
     if (g->dim < 1 || g->dim > 3) return fail(PINT_E_ARG, "grid.dim must be 1, 2 or 3");
@@ -235,9 +301,8 @@ pint_status validate(const pint_grid* g, const pint_params* p) {
     } else {
         long long plane = 16;   // complex FP64 slots of one spectrum plane, in bytes
         for (int i = 0; i < g->dim; ++i) {
-            const long long L = 2LL * (g->m[i] + 1);
-            if (!is_pow2(L) || L < (1 << 3) || L > (1 << pint::kMaxLogL))
-                return fail(PINT_E_UNSUPPORTED, "2D/3D grids need m_i + 1 a power of two in 4..2048");
+            if (2LL * (g->m[i] + 1) > (1 << pint::kMaxLogL))
+                return fail(PINT_E_UNSUPPORTED, "2D/3D grids are limited to m_i <= 2047");
             plane *= i == 0 ? (g->m[0] + 15) / 16 * 16 : g->m[i];
         }
         // the spatial passes address within a spectrum plane with 32-bit byte offsets
@@ -366,8 +431,12 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
             mu[j] = (double)(4.0L / ((long double)h * h) * sn * sn);
         }
         if ((rc = upload(P, &P->d_mu[i], mu.data(), m)) != PINT_OK) return rc;
-        if (is_pow2(2LL * (m + 1)) && 2LL * (m + 1) <= (1LL << pint::kMaxLogL))
-            if ((rc = upload_tw(P, &P->d_twL[i], 2LL * (m + 1), P->mixed)) != PINT_OK) return rc;
+        const long long L = 2LL * (m + 1);
+        if (is_pow2(L) && L <= (1LL << pint::kMaxLogL) && (g->dim == 1 || L >= 8)) {
+            if ((rc = upload_tw(P, &P->d_twL[i], L, P->mixed)) != PINT_OK) return rc;
+        } else if (g->dim >= 2) {
+            if ((rc = upload_bluestein(P, i, m)) != PINT_OK) return rc;
+        }
     }
     // workspace layout
     const size_t cbytes = P->mixed ? 2 * sizeof(float) : 2 * sizeof(double);
@@ -479,6 +548,10 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof
     for (int i = 0; i < 3; ++i) {
         sa.mu[i] = P->d_mu[i];
         sa.twL[i] = P->d_twL[i];
+        sa.logP[i] = P->logP[i];
+        sa.chirp[i] = P->d_chirp[i];
+        sa.bh[i] = P->d_bh[i];
+        sa.twP[i] = P->d_twP[i];
         sa.ih2[i] = P->ih2[i];
     }
     sa.inv_factor = P->inv_factor;

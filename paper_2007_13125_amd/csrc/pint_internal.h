@@ -59,6 +59,11 @@ struct SpaceArgs {
     const double2* sigma;   // [nP] tau^{-alpha} d_p
     const double* mu[3];    // sine eigenvalues per axis (FP64)
     const void* twL[3];     // twiddles of length 2(m_a+1) per axis, spectrum precision
+    // axes with 2(m_a+1) not a power of two (Bluestein), spectrum precision; logP[a] = 0 otherwise
+    int logP[3];            // P_a = 2^logP[a] >= 4(m_a+1) - 1
+    const void* chirp[3];   // [2(m_a+1)] e^{-pi i t^2/(2(m_a+1))}
+    const void* bh[3];      // [P_a] FFT_P of the conjugate chirp wrapped around 0, divided by P_a
+    const void* twP[3];     // [P_a] twiddles e^{-2 pi i j/P_a}
     double ih2[3];          // 1/h^2 per axis
     double inv_factor;      // 1 / prod_a (-2 (m_a + 1)) for the raw DST pair
 };

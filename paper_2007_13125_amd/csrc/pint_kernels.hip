@@ -1383,6 +1383,132 @@ __global__ __launch_bounds__(NT) void k_dst_cols(SpaceArgs a, int axis) {
     }
 }
 
+// Raw sine transform of any length (axes whose 2(m+1) is not a power of two),
+// by Bluestein's chirp-z identity jk = (j^2 + k^2 - (k-j)^2)/2:
+//   Y_k = sum_{t<L} y_t e^{-2 pi i t k/L} = c_k sum_t (y_t c_t) conj(c_{k-t}),
+//   c_t = e^{-pi i t^2/L},  L = 2(m+1),  y = odd extension of the line,
+// the linear convolution evaluated with power-of-two FFTs of length P >= 2L-1
+// in LDS: Y = c . IFFT_P(FFT_P(a) . Bh), a_t = y_t c_t (t < L, zero beyond),
+// Bh = FFT_P(conj c wrapped to -(L-1)..L-1)/P (a host table).  It returns the
+// same raw values Y_1..Y_m as the power-of-two path, so the scale factors agree.
+// B lines (one grid line of one frequency plane each) per workgroup, layout
+// [P][B] in LDS.  With SOLVE the transformed line is divided by sigma_p plus the
+// sine eigenvalues and transformed again (the last axis of the spatial solve).
+template <typename R, int LOGP, int B, int NT, bool SOLVE>
+__global__ __launch_bounds__(NT) void k_dst_blue(SpaceArgs a, int axis, long long nlines) {
+    using T = cx<R>;
+    constexpr int P = 1 << LOGP;
+    constexpr int MAXPER = ((P / 4) * B + NT - 1) / NT;   // m < P/4 values per line
+    __shared__ T sm[P * B];
+    const int m = axis == 0 ? a.mx : (axis == 1 ? a.my : a.mz);
+    const int L = 2 * (m + 1);
+    const long long stride = axis == 0 ? 1 : (axis == 1 ? (long long)a.mxp : (long long)a.mxp * a.my);
+    const T* cw = reinterpret_cast<const T*>(a.chirp[axis]);
+    const T* bh = reinterpret_cast<const T*>(a.bh[axis]);
+    const T* tw = reinterpret_cast<const T*>(a.twP[axis]);
+    T* S = reinterpret_cast<T*>(a.S);
+    const T zero = mk<T>((R)0, (R)0);
+    // line l: offset of its first element, frequency p and the other two grid
+    // indices (axis 0: y, z; axis 1: x, z; axis 2: x, y)
+    struct Line {
+        long long off;
+        int p, i1, i2;
+    };
+    auto line = [&](long long l) {
+        Line r;
+        if (axis == 0) {
+            const long long lpp = (long long)a.my * a.mz;
+            const long long q = l % lpp;
+            r.p = (int)(l / lpp);
+            r.i1 = (int)(q % a.my);
+            r.i2 = (int)(q / a.my);
+            r.off = (long long)r.p * a.ldS + q * a.mxp;
+        } else {
+            const long long q = l / a.mx;
+            const int o = axis == 1 ? a.mz : a.my;
+            r.i1 = (int)(l % a.mx);
+            r.i2 = (int)(q % o);
+            r.p = (int)(q / o);
+            r.off = (long long)r.p * a.ldS + r.i1 +
+                    (axis == 1 ? (long long)r.i2 * a.mxp * a.my : (long long)r.i2 * a.mxp);
+        }
+        return r;
+    };
+    T val[MAXPER];
+    // a = chirped odd extension of val (element i of this lane is (b, j) =
+    // (idx / m, idx % m), idx = tid + i NT, i.e. v_{j+1} of line b), zero elsewhere
+    auto build = [&]() {
+#pragma unroll
+        for (int i = 0; i < MAXPER; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            if (idx < m * B) {
+                const int b = idx / m, j = idx % m;
+                const T v = val[i];
+                sm[(j + 1) * B + b] = cmul(v, cw[j + 1]);
+                const T u = cmul(v, cw[L - 1 - j]);
+                sm[(L - 1 - j) * B + b] = mk<T>(-u.x, -u.y);
+            }
+        }
+        for (int idx = threadIdx.x; idx < (2 + P - L) * B; idx += NT) {
+            const int r = idx / B, b = idx % B;
+            const int t = r == 0 ? 0 : (r == 1 ? m + 1 : L + r - 2);
+            sm[t * B + b] = zero;
+        }
+        __syncthreads();
+    };
+    // FFT, multiply by Bh, inverse FFT; afterwards Y_k = c_k sm[k B + b]
+    auto convolve = [&]() {
+        lds_fft<R, LOGP, B, NT, false, true, 0>(sm, tw);
+        for (int idx = threadIdx.x; idx < P * B; idx += NT) sm[idx] = cmul(sm[idx], bh[idx / B]);
+        __syncthreads();
+        lds_fft<R, LOGP, B, NT, true, true, 0>(sm, tw);
+    };
+    for (long long g = blockIdx.x; g * B < nlines; g += gridDim.x) {
+#pragma unroll
+        for (int i = 0; i < MAXPER; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            val[i] = zero;
+            if (idx < m * B) {
+                const long long l = g * B + idx / m;
+                if (l < nlines) val[i] = S[line(l).off + (long long)(idx % m) * stride];
+            }
+        }
+        build();
+        convolve();
+        if constexpr (SOLVE) {
+#pragma unroll
+            for (int i = 0; i < MAXPER; ++i) {
+                const int idx = threadIdx.x + i * NT;
+                if (idx < m * B) {
+                    const int b = idx / m, k = idx % m + 1;
+                    const long long l = g * B + b;
+                    const Line ln = line(l < nlines ? l : 0);
+                    const double2 sg = a.sigma[ln.p];
+                    double dre = sg.x + (axis == 0 ? a.mu[0] : (axis == 1 ? a.mu[1] : a.mu[2]))[k - 1];
+                    if (axis >= 1) dre += a.mu[0][ln.i1];
+                    if (axis == 2) dre += a.mu[1][ln.i2];
+                    const double inv = a.inv_factor / (dre * dre + sg.y * sg.y);
+                    const T c = mk<T>((R)(dre * inv), (R)(-sg.y * inv));
+                    val[i] = cmul(cmul(sm[k * B + b], cw[k]), c);
+                }
+            }
+            __syncthreads();
+            build();
+            convolve();
+        }
+#pragma unroll
+        for (int i = 0; i < MAXPER; ++i) {
+            const int idx = threadIdx.x + i * NT;
+            if (idx < m * B) {
+                const int b = idx / m, k = idx % m + 1;
+                const long long l = g * B + b;
+                if (l < nlines) S[line(l).off + (long long)(k - 1) * stride] = cmul(sm[k * B + b], cw[k]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Starting-step corrections of Table 1 for rows n = 1..k-1:
 //   corr_n = a_n (f(0) - A_h v) + sum_{l=1..k-2} (b_{l,n} tau^l) d^l f/dt^l (0).
 __global__ void k_prep(const double* __restrict__ v, const double* __restrict__ f, const double* __restrict__ fder,
@@ -1673,14 +1799,55 @@ const char* pass_name(const SpaceArgs& a, int i) {
     return n3[i];
 }
 
+template <typename R, int LOGP, bool SOLVE>
+hipError_t blue_one(const SpaceArgs& a, int axis, hipStream_t st) {
+    constexpr int P = 1 << LOGP;
+    constexpr int BQ = 65536 / (P * (int)sizeof(cx<R>));
+    constexpr int B = BQ > 16 ? 16 : (BQ < 1 ? 1 : BQ);
+    constexpr int NT = kNT;
+    const long long other = axis == 0 ? (long long)a.my * a.mz : (long long)a.mx * (axis == 1 ? a.mz : a.my);
+    const long long nlines = (long long)a.nP * other;
+    const long long groups = (nlines + B - 1) / B;
+    const long long grid = std::min<long long>(
+        groups, persistent_blocks(reinterpret_cast<const void*>(&k_dst_blue<R, LOGP, B, NT, SOLVE>), NT));
+    hipLaunchKernelGGL((k_dst_blue<R, LOGP, B, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, axis, nlines);
+    return hipGetLastError();
+}
+
+template <typename R, bool SOLVE>
+hipError_t blue_dispatch(const SpaceArgs& a, int axis, hipStream_t st) {
+    switch (a.logP[axis]) {
+        case 4: return blue_one<R, 4, SOLVE>(a, axis, st);
+        case 5: return blue_one<R, 5, SOLVE>(a, axis, st);
+        case 6: return blue_one<R, 6, SOLVE>(a, axis, st);
+        case 7: return blue_one<R, 7, SOLVE>(a, axis, st);
+        case 8: return blue_one<R, 8, SOLVE>(a, axis, st);
+        case 9: return blue_one<R, 9, SOLVE>(a, axis, st);
+        case 10: return blue_one<R, 10, SOLVE>(a, axis, st);
+        case 11: return blue_one<R, 11, SOLVE>(a, axis, st);
+        case 12: return blue_one<R, 12, SOLVE>(a, axis, st);
+        case 13: return blue_one<R, 13, SOLVE>(a, axis, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// One spatial pass of a 2D/3D solve along `axis`: the power-of-two kernels
+// when 2(m+1) is a power of two, Bluestein otherwise.
+template <typename R, bool SOLVE>
+hipError_t axis_pass(const SpaceArgs& a, int axis, hipStream_t st) {
+    if (a.logP[axis] != 0) return blue_dispatch<R, SOLVE>(a, axis, st);
+    if (axis == 0) return rows_dispatch<R, SOLVE>(a, st);
+    return cols_dispatch<R, SOLVE>(a, axis, st);
+}
+
 template <typename R>
 hipError_t space_pass(const SpaceArgs& a, int i, hipStream_t st) {
     if (a.dim == 1) return dst1d(a) ? rows_dispatch<R, true>(a, st) : tri1d_dispatch<R>(a, st);
-    if (a.dim == 2) return i == 1 ? cols_dispatch<R, true>(a, 1, st) : rows_dispatch<R>(a, st);
+    if (a.dim == 2) return i == 1 ? axis_pass<R, true>(a, 1, st) : axis_pass<R, false>(a, 0, st);
     switch (i) {
-        case 1: case 3: return cols_dispatch<R, false>(a, 1, st);
-        case 2: return cols_dispatch<R, true>(a, 2, st);
-        default: return rows_dispatch<R>(a, st);
+        case 1: case 3: return axis_pass<R, false>(a, 1, st);
+        case 2: return axis_pass<R, true>(a, 2, st);
+        default: return axis_pass<R, false>(a, 0, st);
     }
 }
 

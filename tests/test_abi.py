@@ -50,8 +50,8 @@ def test_invalid_params_rejected(change, status):
 
 
 @pytest.mark.parametrize("m,status", [((0,), B.PINT_E_ARG), ((4096,), B.PINT_E_UNSUPPORTED),
-                                      ((100, 127), B.PINT_E_UNSUPPORTED), ((127, 1), B.PINT_E_UNSUPPORTED),
-                                      ((7, 7, 9), B.PINT_E_UNSUPPORTED), ((1023, 1023, 511), B.PINT_E_UNSUPPORTED)])
+                                      ((5, 0), B.PINT_E_ARG), ((2048, 15), B.PINT_E_UNSUPPORTED),
+                                      ((15, 15, 2048), B.PINT_E_UNSUPPORTED), ((1023, 1023, 511), B.PINT_E_UNSUPPORTED)])
 def test_invalid_grids_rejected(m, status):
     st, h = _create(B.make_grid(m), B.make_params(2, 1.0, 1.0, 64, 1e-3))
     assert st == status
@@ -70,7 +70,7 @@ def test_bad_enum_and_null_plan():
 
 
 def test_batch_rejects_unsupported_instance():
-    grids = [B.make_grid((63,)), B.make_grid((100, 127))]
+    grids = [B.make_grid((63,)), B.make_grid((2048, 127))]
     params = [B.make_params(2, 1.0, 1.0, 64, 1e-3), B.make_params(2, 1.0, 1.0, 64, 1e-3)]
     G = (B.pint_grid * 2)(*grids)
     Pm = (B.pint_params * 2)(*params)

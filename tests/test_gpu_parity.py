@@ -58,6 +58,12 @@ SMALL = [
     (2, (63, 15), 128, 5, 1.0, 1e-3),
     (3, (7, 15, 3), 16, 6, 1.0, 1e-4),
     (3, (7, 7, 7), 32, 2, 0.3, 1e-3),
+    # 2D/3D sizes whose sine transforms are not power-of-two FFTs (Bluestein passes)
+    (2, (20, 13), 32, 3, 1.0, 1e-3),
+    (2, (100, 67), 16, 4, 1.0, 1e-4),
+    (2, (30, 12), 64, 2, 0.5, 1e-3),
+    (2, (1, 5), 8, 1, 1.0, 0.1),
+    (3, (6, 9, 5), 16, 2, 1.0, 1e-3),
 ]
 
 
