@@ -51,3 +51,28 @@ def test_batch_matches_single_solves_and_oracle():
         assert np.allclose(upd[i], info["upd"], rtol=0, atol=0)
         ref = oracle_solution(w)
         assert rel_l2(got, ref) <= (1e-11 if p == "fp64" else 1e-10), i
+
+
+def test_batch_of_random_instances_any_grid_size():
+    # The many-instance recipe (dim, m, N, k, alpha, kappa all drawn per instance;
+    # 2D sizes are arbitrary, so most 2D instances take the Bluestein sine transforms),
+    # at sizes the oracle finishes quickly; mixed precision as in that recipe.
+    import torch
+    ws = [wl.batch_instance(i, seed=9, m_range=(5, 40), N_choices=(8, 16, 32, 64)) for i in range(10)]
+    tol = 1e-13
+    grids = [B.make_grid(w.m) for w in ws]
+    params = [B.make_params(w.k, w.alpha, w.T, w.N, w.kappa, tol=tol, max_sweeps=40, precision="mixed")
+              for w in ws]
+    print("[gpu] random batch:", [(w.m, w.N, w.k, w.alpha) for w in ws], flush=True)
+    h = B.pint_batch_plan_create(grids, params)
+    Us = [torch.empty((w.N, w.M), dtype=torch.float64, device="cuda") for w in ws]
+    st, upd, sw = B.pint_batch_solve(h, [to_dev(w.v) for w in ws], [to_dev(w.f) for w in ws],
+                                     [to_dev(w.fder) for w in ws], Us, 40)
+    torch.cuda.synchronize()
+    B.pint_plan_destroy(h)
+    assert st == B.PINT_OK, (st, sw)
+    for i, w in enumerate(ws):
+        got = Us[i].cpu().numpy()
+        single, info = gpu_solve(w, precision="mixed", tol=tol, max_sweeps=40)
+        assert np.array_equal(got, single), i
+        assert rel_l2(got, oracle_solution(w)) <= 1e-10, (i, w.m, w.N, w.k, w.alpha)
