@@ -170,7 +170,9 @@ def summarize(outdir):
         return list(csv.DictReader(open(paths[0])))
 
     def short(name):
-        return name.replace("void pint::(anonymous namespace)::", "").replace("pint::", "").split("(")[0]
+        for pre in ("void ", "pint::", "(anonymous namespace)::"):
+            name = name.replace(pre, "")
+        return name.split("(")[0]
 
     stats = rows("trace", "kernel_stats.csv")
     counters = {}
