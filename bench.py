@@ -58,7 +58,7 @@ def measured_traffic(precision, kernel):
         return None
 
 
-def run_precision(w, precision, steps, warmup):
+def run_precision(w, precision, steps, warmup, form="residual"):
     import torch
 
     from paper_2007_13125_amd.binding import Plan
@@ -66,7 +66,7 @@ def run_precision(w, precision, steps, warmup):
     v = torch.from_numpy(w.v).to(dev)
     f = torch.from_numpy(w.f).to(dev) if w.f is not None else None
     fd = torch.from_numpy(w.fder).to(dev) if w.fder is not None else None
-    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-14, max_sweeps=30, precision=precision)
+    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-14, max_sweeps=30, precision=precision, form=form)
     plan.bind(v, f, fd)
     U = torch.empty((w.N, w.M), dtype=torch.float64, device=dev)
     plan.init_iterate(U)
@@ -277,7 +277,10 @@ def main():
     plan64.init_iterate(Uref)
     plan64.sweeps(Uref, 8)
     torch.cuda.synchronize()
-    ttt = {p: time_to_tol(w, plans[p][0], plans[p][1], Uref) for p in ("fp64", "mixed")}
+    # the paper's direct form in FP64 (its roundoff floor, ~eps/kappa ~ 6e-12 here, is below 1e-10)
+    pd, dd, ms_d, prof_d = run_precision(w, "fp64", args.steps, args.warmup, form="direct")
+    plans["fp64_direct"] = (pd, dd)
+    ttt = {p: time_to_tol(w, plans[p][0], plans[p][1], Uref) for p in ("fp64", "fp64_direct", "mixed")}
 
     d = out["fp64"]["dominant"]
     res = {
@@ -305,6 +308,7 @@ def main():
         "mixed": {k: out["mixed"][k] for k in ("value", "ms_per_step", "kernels_ms", "sweep_hbm_frac",
                                                "dominant")},
         "time_to_1e-10": {p: {"sweeps": ttt[p]["sweeps"], "ms": ttt[p]["ms"]} for p in ttt},
+        "fp64_direct": {"ms_per_step": ms_d, "kernels_ms": {n: t for n, t in prof_d}},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()

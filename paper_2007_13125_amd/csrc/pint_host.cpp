@@ -150,7 +150,8 @@ struct pint_plan {
     bool ws_owned = false;
     void* S = nullptr;
     double *corr = nullptr, *partial = nullptr, *norm_tmp = nullptr;
-    size_t off_corr = 0, off_partial = 0, off_norm = 0;
+    void* Sg = nullptr;   // direct form, BDF-k: spectrum of the source part (set at bind)
+    size_t off_corr = 0, off_partial = 0, off_norm = 0, off_sg = 0;
     // bound data
     const double *v = nullptr, *f = nullptr, *fder = nullptr;
     bool bound = false;
@@ -448,6 +449,10 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     off += align256(maxblocks * 2 * sizeof(double));
     P->off_norm = off;
     off += 256;
+    if (!P->cq && p->form == PINT_DIRECT) {
+        P->off_sg = off;
+        off += align256((size_t)P->nP * P->ldS * cbytes);
+    }
     P->ws_bytes = off;
     HIP_TRY(hipHostMalloc((void**)&P->h_norms, 2 * sizeof(double), hipHostMallocDefault));
     return PINT_OK;
@@ -462,6 +467,7 @@ pint_status ensure_workspace(pint_plan* P) {
     P->corr = reinterpret_cast<double*>(b + P->off_corr);
     P->partial = reinterpret_cast<double*>(b + P->off_partial);
     P->norm_tmp = reinterpret_cast<double*>(b + P->off_norm);
+    P->Sg = P->off_sg ? static_cast<void*>(b + P->off_sg) : nullptr;
     return PINT_OK;
 }
 
@@ -500,8 +506,7 @@ struct Profiler {
 #define PROF_END(prof) \
     if (prof) HIP_TRY((prof)->end())
 
-pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof = nullptr) {
-    if (prof) prof->cursor = 0;
+FwdArgs fwd_args(const pint_plan* P, const double* U) {
     FwdArgs fa{};
     fa.U = U;
     fa.f = P->f;
@@ -531,9 +536,22 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof
     fa.kappa = P->p.kappa;
     fa.form = P->p.form == PINT_DIRECT ? 1 : 0;
     fa.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
-    PROF_BEGIN(prof, P->cq ? "forward_cq_rhs_tfft" : "forward_rhs_tfft");
-    HIP_TRY(pint::launch_forward(fa, P->mixed, P->cq, nullptr, P->st));
-    PROF_END(prof);
+    return fa;
+}
+
+pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof = nullptr) {
+    if (prof) prof->cursor = 0;
+    FwdArgs fa = fwd_args(P, U);
+    if (P->Sg) {
+        // direct form, BDF-k: stored source spectrum + the k relaxation rows
+        PROF_BEGIN(prof, "direct_rhs_spectrum");
+        HIP_TRY(pint::launch_inject(fa, P->Sg, P->mixed, P->st));
+        PROF_END(prof);
+    } else {
+        PROF_BEGIN(prof, P->cq ? "forward_cq_rhs_tfft" : "forward_rhs_tfft");
+        HIP_TRY(pint::launch_forward(fa, P->mixed, P->cq, nullptr, P->st));
+        PROF_END(prof);
+    }
 
     SpaceArgs sa{};
     sa.S = P->S;
@@ -626,6 +644,7 @@ pint_status pint_plan_set_workspace(pint_plan* P, void* dev_ptr, size_t bytes) {
     P->corr = reinterpret_cast<double*>(b + P->off_corr);
     P->partial = reinterpret_cast<double*>(b + P->off_partial);
     P->norm_tmp = reinterpret_cast<double*>(b + P->off_norm);
+    P->Sg = P->off_sg ? static_cast<void*>(b + P->off_sg) : nullptr;
     return PINT_OK;
 }
 
@@ -638,6 +657,14 @@ pint_status pint_bind(pint_plan* P, const double* v, const double* f, const doub
     P->fder = fder;
     HIP_TRY(pint::launch_prep(v, f, P->p.k > 2 ? fder : nullptr, P->corr, P->d_an, P->d_blt, P->p.k, P->M, P->mx,
                               P->my, P->mz, P->ih2[0], P->ih2[1], P->ih2[2], P->st));
+    if (P->Sg) {
+        // spectrum of kappa^{q/N} G_q, the part of the direct-form right-hand side
+        // that does not change between sweeps
+        FwdArgs fa = fwd_args(P, nullptr);
+        fa.form = 2;
+        fa.S = P->Sg;
+        HIP_TRY(pint::launch_forward(fa, P->mixed, false, nullptr, P->st));
+    }
     P->bound = true;
     return PINT_OK;
 }

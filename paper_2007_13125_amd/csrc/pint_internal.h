@@ -34,7 +34,7 @@ struct FwdArgs {
     double ihx2, ihy2, ihz2;  // 1/h^2 per direction (0 for absent directions)
     double ta;              // tau^{-alpha}
     double kappa;
-    int form;               // 0 residual, 1 direct
+    int form;               // 0 residual, 1 direct, 2 the source part G alone (U not read)
     int ncorr;              // number of correction rows (k-1, or 0)
 };
 
@@ -77,6 +77,9 @@ hipError_t launch_prep(const double* v, const double* f, const double* fder, dou
 hipError_t launch_fill(double* U, const double* v, long long N, int M, int zero, hipStream_t st);
 hipError_t launch_forward(const FwdArgs& a, bool mixed, bool cq, int* nblocks_out, hipStream_t st);
 hipError_t launch_inverse(const InvArgs& a, bool mixed, int* nblocks_out, hipStream_t st);
+// Direct form, BDF-k: spectrum of the right-hand side from the stored source
+// spectrum Sg and the last k rows of U (replaces launch_forward).
+hipError_t launch_inject(const FwdArgs& a, const void* Sg, bool mixed, hipStream_t st);
 hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st);
 int space_pass_count(const SpaceArgs& a);
 const char* space_pass_name(const SpaceArgs& a, int pass);

@@ -334,6 +334,7 @@ __global__ __launch_bounds__(NT, PINT_FWD_WAVES) void k_fwd_heat(FwdArgs a) {
     const bool valid = d >= 0;
     const size_t M = a.M;
     const bool resid = a.form == 0;
+    const bool useU = a.form != 2;     // form 2: the source part G alone (U not read)
 
     int x = 0, y = 0, z = 0;
     if (valid) {
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(NT, PINT_FWD_WAVES) void k_fwd_heat(FwdArgs a) {
     for (int i = 0; i < PER; ++i) {
         const int q = (tid + i * NT) / W;
         const double* uq = Ub + (size_t)q * M;
-        const double u = uq[0];
+        const double u = useU ? uq[0] : 0.0;
         double acc = vt * a.s[q];
         if (fb) acc += fb[(size_t)q * M];
         if (resid) {
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(NT, PINT_FWD_WAVES) void k_fwd_heat(FwdArgs a) {
                 for (int j = 1; j < 7; ++j) ts += (q >= j) ? wk[j] * su[(q >= j ? q - j : 0) * W + dl] : 0.0;
                 const double au = diag * u - cim * su[q * W + lm] - cip * su[q * W + lp];
                 r -= a.ta * ts + au;
-            } else if (n <= a.k) {
+            } else if (a.form == 1 && n <= a.k) {
                 double acc = 0.0;
                 for (int j = n; j <= a.k; ++j) acc += wk[j] * su[(a.N + n - j - 1) * W + dl];
                 r += a.kappa * a.ta * acc;
@@ -794,6 +795,47 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_wide(FwdArgs a, int ncol, int nch
     for (int c = c0; c < c1; c += 2) {
         step(c, A, Bv);
         if (c + 1 < c1) step(c + 1, Bv, A);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct form, BDF-k (eq. BDF-k-F): the right-hand side is the source part G
+// (the same every sweep) plus a relaxation term that is nonzero only in rows
+// n = 1..k.  Its spectrum is therefore the stored spectrum of kappa^{q/N} G
+// (computed once when the data are bound) plus a k-term DFT per dof:
+//   H_p = Sg_p + sum_{n=1..k} kappa^{(n-1)/N} c_n e^{-2 pi i (n-1) p/N},
+//   c_n = kappa tau^{-1} sum_{j=n..k} w_j U^{N+n-j},
+// which replaces the forward kernel of a direct sweep (no FFT, U read only in
+// its last k rows).  One lane per spectrum slot and a chunk of frequencies.
+template <typename R>
+__global__ __launch_bounds__(256) void k_inject(FwdArgs a, const void* Sg, int pchunk) {
+    using T = cx<R>;
+    const int P0 = blockIdx.y * pchunk, P1 = min(a.N / 2 + 1, P0 + pchunk);
+    const int slot = blockIdx.x * 256 + threadIdx.x;
+    if (slot >= a.Mp) return;
+    const int d = slot_dof(slot, a.mx, a.mxp, a.Mp);
+    double c[6];
+#pragma unroll
+    for (int n = 1; n <= 6; ++n) {
+        double acc = 0.0;
+        if (d >= 0 && n <= a.k)
+            for (int j = n; j <= a.k; ++j) acc += a.wk[j] * a.U[(size_t)(a.N + n - j - 1) * a.M + d];
+        c[n - 1] = n <= a.k ? a.kappa * a.ta * acc * a.scale[n - 1] : 0.0;
+    }
+    const T* src = reinterpret_cast<const T*>(Sg);
+    T* dst = reinterpret_cast<T*>(a.S);
+    const T* tw = reinterpret_cast<const T*>(a.tw);
+    for (int p = P0; p < P1; ++p) {
+        const T g = src[(size_t)p * a.ldS + slot];
+        double hr = (double)g.x, hi = (double)g.y;
+#pragma unroll
+        for (int n = 1; n <= 6; ++n) {
+            if (n > a.k) break;
+            const T w = tw[((n - 1) * p) & (a.N - 1)];
+            hr += c[n - 1] * (double)w.x;
+            hi += c[n - 1] * (double)w.y;
+        }
+        dst[(size_t)p * a.ldS + slot] = mk<T>((R)hr, (R)hi);
     }
 }
 
@@ -1870,6 +1912,16 @@ hipError_t launch_fill(double* U, const double* v, long long N, int M, int zero,
 
 hipError_t launch_forward(const FwdArgs& a, bool mixed, bool cq, int* nb, hipStream_t st) {
     return mixed ? fwd_dispatch<float>(a, cq, nb, st) : fwd_dispatch<double>(a, cq, nb, st);
+}
+
+hipError_t launch_inject(const FwdArgs& a, const void* Sg, bool mixed, hipStream_t st) {
+    const int pchunk = 16;
+    const dim3 grid((unsigned)((a.Mp + 255) / 256), (unsigned)((a.N / 2 + 1 + pchunk - 1) / pchunk));
+    if (mixed)
+        hipLaunchKernelGGL(k_inject<float>, grid, dim3(256), 0, st, a, Sg, pchunk);
+    else
+        hipLaunchKernelGGL(k_inject<double>, grid, dim3(256), 0, st, a, Sg, pchunk);
+    return hipGetLastError();
 }
 
 hipError_t launch_inverse(const InvArgs& a, bool mixed, int* nb, hipStream_t st) {
