@@ -64,6 +64,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uns
 __device__ __forceinline__ double2 buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, double2) {
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
 }
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
 __device__ __forceinline__ float2 buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off, float2) {
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
@@ -125,9 +128,11 @@ template <bool INV, typename T> struct SmallDft<1, INV, T> {
 // Radix schedule of a 2^LOGL transform: the fewest stages of radix <= 16,
 // with the factors of two spread evenly over them (512 = 8 x 8 x 8,
 // 1024 = 16 x 8 x 8, 32 = 8 x 4, ...).
-constexpr int stage_count(int logl) { return (logl + 3) / 4; }
-constexpr int stage_radix(int logl, int st) {
-    return 1 << (logl / stage_count(logl) + (st < logl % stage_count(logl) ? 1 : 0));
+// MAXLOG = 3 caps the radix at 8 (one more LDS pass for some lengths, but
+// half the registers per butterfly).
+constexpr int stage_count(int logl, int maxlog = 4) { return (logl + maxlog - 1) / maxlog; }
+constexpr int stage_radix(int logl, int st, int maxlog = 4) {
+    return 1 << (logl / stage_count(logl, maxlog) + (st < logl % stage_count(logl, maxlog) ? 1 : 0));
 }
 
 // One Stockham stage of radix RAD and span Ns: butterfly j (with k = j mod Ns)
@@ -137,11 +142,12 @@ constexpr int stage_radix(int logl, int st) {
 // Twiddles w^r, r = 1..RAD-1, of one butterfly from the table entries for
 // w^e, w^{2e}, w^{4e}, w^{8e} (log2 RAD loads instead of RAD - 1); every other
 // power is a product of at most three of them.
-template <int RAD, bool INV, typename T>
+// TWS > 1 reads every TWS-th entry of a finer table (w of a TWS times longer transform).
+template <int RAD, bool INV, typename T, int TWS = 1>
 __device__ __forceinline__ void apply_twiddles(T* v, const T* __restrict__ tw, int e) {
     T p[4];
 #pragma unroll
-    for (int i = 0; (1 << i) < RAD; ++i) p[i] = tw[(1 << i) * e];
+    for (int i = 0; (1 << i) < RAD; ++i) p[i] = tw[(1 << i) * e * TWS];
 #pragma unroll
     for (int r = 1; r < RAD; ++r) {
         T w = mk<T>(1, 0);
@@ -163,14 +169,13 @@ __device__ __forceinline__ void apply_twiddles(T* v, const T* __restrict__ tw, i
 // Sequence layouts: BFAST s[t*B + b]; otherwise s[b*BSTR + t + (t >> PADSH)]
 // (one padding slot per 2^PADSH elements keeps the strided writes of the first
 // stage off a single LDS bank group; PADSH = 0 means no padding).
-template <typename R, int LOGL, int RAD, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH>
-__device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw, int Ns) {
+template <typename R, int LOGL, int RAD, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH, int TWS>
+__device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw, int Ns, int tid) {
     using T = cx<R>;
     constexpr int L = 1 << LOGL;
     constexpr int Q = L / RAD;
     constexpr int TOT = Q * B;
     constexpr int PER = (TOT + NT - 1) / NT;
-    const int tid = threadIdx.x;
     auto at = [](int t, int b) { return BFAST ? t * B + b : b * BSTR + t + (PADSH ? (t >> PADSH) : 0); };
     T v[PER][RAD];
 #pragma unroll
@@ -182,7 +187,7 @@ __device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw
 #pragma unroll
             for (int r = 0; r < RAD; ++r) v[i][r] = s[at(j + r * Q, b)];
             const int k = j & (Ns - 1);
-            if (Ns > 1) apply_twiddles<RAD, INV>(v[i], tw, k * (Q / Ns));
+            if (Ns > 1) apply_twiddles<RAD, INV, T, TWS>(v[i], tw, k * (Q / Ns));
             SmallDft<RAD, INV, T>::run(v[i]);
         }
     }
@@ -202,12 +207,12 @@ __device__ __forceinline__ void fft_stage(cx<R>* s, const cx<R>* __restrict__ tw
     __syncthreads();
 }
 
-template <typename R, int LOGL, int ST, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH>
-__device__ __forceinline__ void fft_stages(cx<R>* s, const cx<R>* __restrict__ tw, int Ns) {
-    if constexpr (ST < stage_count(LOGL)) {
-        constexpr int RAD = stage_radix(LOGL, ST);
-        fft_stage<R, LOGL, RAD, B, NT, INV, BFAST, BSTR, PADSH>(s, tw, Ns);
-        fft_stages<R, LOGL, ST + 1, B, NT, INV, BFAST, BSTR, PADSH>(s, tw, Ns * RAD);
+template <typename R, int LOGL, int ST, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH, int TWS, int MAXLOG>
+__device__ __forceinline__ void fft_stages(cx<R>* s, const cx<R>* __restrict__ tw, int Ns, int tid) {
+    if constexpr (ST < stage_count(LOGL, MAXLOG)) {
+        constexpr int RAD = stage_radix(LOGL, ST, MAXLOG);
+        fft_stage<R, LOGL, RAD, B, NT, INV, BFAST, BSTR, PADSH, TWS>(s, tw, Ns, tid);
+        fft_stages<R, LOGL, ST + 1, B, NT, INV, BFAST, BSTR, PADSH, TWS, MAXLOG>(s, tw, Ns * RAD, tid);
     }
 }
 
@@ -217,12 +222,31 @@ __device__ __forceinline__ void fft_stages(cx<R>* s, const cx<R>* __restrict__ t
 // remainder), in-register sub-DFTs, and one LDS round trip per stage.
 // Forward: X_k = sum_t x_t e^{-2 pi i t k/L}; INV uses e^{+...} and no 1/L.
 // tw[j] = e^{-2 pi i j/L}; the stages only index j < L/2 (in LDS or global memory).
+// With TWS > 1, tw is the table of a TWS times longer transform (tw[TWS j] is used).
 // Every thread of the block must call it; it ends with a barrier.
 // Always inlined: as a call it would make the caller wait for all of its
-// outstanding loads (prefetches) at the call and spill around it.
-template <typename R, int LOGL, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH = 0>
+// outstanding loads (prefetches) at the call and spill around it.  tid is the
+// caller's lane index (threadIdx.x, or a copy of it that a persistent loop
+// keeps from being treated as loop-invariant).
+template <typename R, int LOGL, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH = 0, int TWS = 1,
+          int MAXLOG = 4>
+__device__ __forceinline__ void lds_fft(cx<R>* s, const cx<R>* __restrict__ tw, int tid) {
+    fft_stages<R, LOGL, 0, B, NT, INV, BFAST, BSTR, PADSH, TWS, MAXLOG>(s, tw, 1, tid);
+}
+template <typename R, int LOGL, int B, int NT, bool INV, bool BFAST, int BSTR, int PADSH = 0, int TWS = 1,
+          int MAXLOG = 4>
 __device__ __forceinline__ void lds_fft(cx<R>* s, const cx<R>* __restrict__ tw) {
-    fft_stages<R, LOGL, 0, B, NT, INV, BFAST, BSTR, PADSH>(s, tw, 1);
+    fft_stages<R, LOGL, 0, B, NT, INV, BFAST, BSTR, PADSH, TWS, MAXLOG>(s, tw, 1, (int)threadIdx.x);
+}
+
+// threadIdx.x through an empty asm statement, called inside a persistent
+// loop: the compiler cannot prove the result loop-invariant, so the LDS
+// address arithmetic derived from it is recomputed per iteration instead of
+// being hoisted out of the loop and held (or spilled) across all of it.
+__device__ __forceinline__ int loop_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
 }
 
 // Padding shift for sequences stored element-contiguously: one slot per
@@ -274,14 +298,16 @@ __device__ __forceinline__ double nanmax(double a, double b) {
 // for earlier loads need not wait for these stores.  CHECK = false when the
 // caller's tile never extends past the last slot.
 template <typename R, int N, int B, int NT, bool CHECK = true>
-__device__ __forceinline__ void store_half_spectrum(const cx<R>* sm, cx<R>* S, int ldS, int d0, int M) {
+__device__ __forceinline__ void store_half_spectrum(const cx<R>* sm, cx<R>* S, int ldS, int d0, int M,
+                                                    int tid = -1) {
     constexpr int NP = N / 2 + 1;
     constexpr int W = 2 * B;
     constexpr int TOT = NP * W;
     constexpr int IT = (TOT + NT - 1) / NT;
+    if (tid < 0) tid = threadIdx.x;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int idx = threadIdx.x + it * NT;
+        const int idx = tid + it * NT;
         if ((it + 1) * NT <= TOT || idx < TOT) {
             const int e = idx % W, p = idx / W;
             const int b = e >> 1;
@@ -847,68 +873,353 @@ __global__ __launch_bounds__(256) void k_inject(FwdArgs a, const void* Sg, int p
 //   c = IFFT_2N( FFT_2N(omega, 0) . FFT_2N(u, 0) ),  u_i = U^{i+1}.
 // residual: r_n = G_n - tau^{-alpha} c_{n-1} - A_h U^n;
 // direct:   F_n = G_n + kappa tau^{-alpha} c_{N+n-1} (= sum_{j=n..N-1} w_j U^{N+n-j}).
+// Persistent: each workgroup (one per CU, the tile and twiddle tables fill the
+// LDS) walks tiles of W dofs, reading the twiddles into LDS once.  Per tile,
+// Phase A issues every global load at once (U, the stencil neighbours outside
+// the tile, v, f, corrections) and folds all but the history term into one
+// FP64 register per element (x neighbours inside the tile are read back from
+// LDS); the DFT of omega and the scale factors are fetched while the
+// transforms run.  In 2D/3D the tiles of a workgroup go down grid columns, so
+// the tiles that workgroups of one XCD hold at the same time are y neighbours
+// and the neighbour loads hit in that XCD's L2.
 template <typename R, int LOGN, int W, int NT>
-__global__ __launch_bounds__(NT) void k_fwd_cq(FwdArgs a) {
+__global__ __launch_bounds__(NT, 1) void k_fwd_cq(FwdArgs a, int nvirt) {
+    using T = cx<R>;
     constexpr int N = 1 << LOGN;
     constexpr int N2 = 2 * N;
     constexpr int B = W / 2;
+    constexpr int PER = N * W / NT;     // time rows of the tile per thread; also points per thread of the 2N product
+    static_assert(PER * NT == N * W, "tile shape");
+    constexpr int RS = NT / W;          // time rows between a thread's consecutive elements
+    static_assert(RS >= 8, "correction rows must lie in the first row group");
+    // twiddles in LDS when they fit beside the tile (N <= 1024), else read from the global tables
+    constexpr bool TWL = (size_t)N2 * B * 16 + (size_t)N * 16 + (size_t)(N / 2) * sizeof(T) <= 163840;
     __shared__ double2 cb[N2 * B];
+    __shared__ double2 stw2[TWL ? N : 1];   // e^{-2 pi i j/(2N)}, j < N
+    __shared__ T stw1[TWL ? N / 2 : 1];     // e^{-2 pi i j/N}, j < N/2, in the spectrum precision
     double* cbr = reinterpret_cast<double*>(cb);
+    const double2* tw2 = TWL ? stw2 : a.tw2;
+    const T* tw1 = TWL ? stw1 : reinterpret_cast<const T*>(a.tw);
 
-    const int ntiles = (a.Mp + W - 1) / W;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    const int d0 = tile * W;
-    const int tid = threadIdx.x;
-    const size_t M = a.M;
-
-    for (int idx = tid; idx < N * W; idx += NT) {
-        const int q = idx / W, d = slot_dof(d0 + idx % W, a.mx, a.mxp, a.Mp);
-        cbr[idx] = d >= 0 ? a.U[(size_t)q * M + d] : 0.0;
-    }
-    for (int idx = N * W + tid; idx < N2 * W; idx += NT) cbr[idx] = 0.0;
-    __syncthreads();
-    lds_fft<double, LOGN + 1, B, NT, false, true, 0>(cb, a.tw2);
-    for (int idx = tid; idx < N2 * B; idx += NT) cb[idx] = cmul(cb[idx], a.what[idx / B]);
-    __syncthreads();
-    lds_fft<double, LOGN + 1, B, NT, true, true, 0>(cb, a.tw2);
-
-    // The residual form reads convolution rows [0, N), the direct form rows
-    // [N, 2N); the time-FFT buffer (N x B values of cx<R>) goes into the other
-    // half, so it never overwrites a value still to be read.
-    const bool resid = a.form == 0;
-    cx<R>* sm = reinterpret_cast<cx<R>*>(cb + (resid ? N * B : 0));
-    R* smr = reinterpret_cast<R*>(sm);
-    for (int idx = tid; idx < N * W; idx += NT) {
-        const int q = idx / W, dl = idx % W, d = slot_dof(d0 + dl, a.mx, a.mxp, a.Mp);
-        const int n = q + 1;
-        double r = 0.0;
-        if (d >= 0) {
-            const size_t o = (size_t)q * M + d;
-            double g = a.ta * a.s[q] * a.v[d];
-            if (a.f) g += a.f[o + M];
-            if (n - 1 < a.ncorr) g += a.corr[(size_t)(n - 1) * M + d];
-            if (resid) {
-                const int x = d % a.mx, rr = d / a.mx, y = rr % a.my, z = rr / a.my;
-                const double u = a.U[o];
-                double au = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2) * u;
-                if (x > 0) au -= a.ihx2 * a.U[o - 1];
-                if (x < a.mx - 1) au -= a.ihx2 * a.U[o + 1];
-                if (y > 0) au -= a.ihy2 * a.U[o - a.mx];
-                if (y < a.my - 1) au -= a.ihy2 * a.U[o + a.mx];
-                if (z > 0) au -= a.ihz2 * a.U[o - (size_t)a.mx * a.my];
-                if (z < a.mz - 1) au -= a.ihz2 * a.U[o + (size_t)a.mx * a.my];
-                r = g - a.ta * cbr[q * W + dl] - au;
-            } else {
-                r = g + a.kappa * a.ta * cbr[(N + q) * W + dl];
-            }
-            r *= a.scale[q];
+    if constexpr (TWL) {
+        for (int j = threadIdx.x; j < N; j += NT) {
+            stw2[j] = a.tw2[j];
+            if (j < N / 2) stw1[j] = reinterpret_cast<const T*>(a.tw)[j];
         }
-        smr[idx] = (R)r;
     }
-    __syncthreads();
-    lds_fft<R, LOGN, B, NT, false, true, 0>(sm, reinterpret_cast<const cx<R>*>(a.tw));
-    store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<cx<R>*>(a.S), a.ldS, d0, a.Mp);
+    const int ntiles = (a.Mp + W - 1) / W;
+    const bool cols = a.my > 1 && a.mxp >= W;
+    const size_t M = a.M;
+    const bool resid = a.form == 0;
+    const size_t sy = (size_t)a.mx, sz = (size_t)a.mx * a.my;
+    const bool has3 = a.mz > 1;
+    const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
+    // the residual form reads convolution rows [0, N), the direct form rows
+    // [N, 2N); the time-FFT buffer (N x B values of cx<R>) goes into the other
+    // half, so it never overwrites a value still to be read
+    T* sm = reinterpret_cast<T*>(cb + (resid ? N * B : 0));
+    R* smr = reinterpret_cast<R*>(sm);
+    const int crow = resid ? 0 : N;
+
+    for (int vb = blockIdx.x; vb < nvirt; vb += gridDim.x) {
+        const int tile = cols ? xcd_tile_columns(vb, nvirt, a.mxp / W) : xcd_tile(vb, nvirt);
+        if (tile >= ntiles) continue;   // uniform over the workgroup
+        const int tid = loop_tid();
+        const int dl = tid % W;
+        const int qb = tid / W;
+        const int d0 = tile * W;
+        const int d = slot_dof(d0 + dl, a.mx, a.mxp, a.Mp);
+        const bool valid = d >= 0;
+        int x = 0, y = 0, z = 0;
+        if (valid) {
+            x = d % a.mx;
+            const int rr = d / a.mx;
+            y = rr % a.my;
+            z = rr / a.my;
+        }
+        const bool hxm = x > 0, hxp = x < a.mx - 1;
+        // Buffer loads: a scalar base per wave and row group (the wave's first
+        // time row qb0 + i RS) plus a 32-bit byte offset per lane that is fixed
+        // for the tile.  Absent stencil neighbours and padding slots take the
+        // offset kNoLane and read 0, so every load is unconditional.
+        const int qb0 = __builtin_amdgcn_readfirstlane(qb);
+        const bool nb = resid && valid;
+        const unsigned lu = valid ? ((unsigned)(qb - qb0) * (unsigned)M + (unsigned)d) * 8u : kNoLane;
+        const unsigned lxm = (nb && hxm && dl == 0) ? lu - 8u : kNoLane;
+        const unsigned lxp = (nb && hxp && dl == W - 1) ? lu + 8u : kNoLane;
+        const unsigned lym = (nb && y > 0) ? lu - 8u * (unsigned)sy : kNoLane;
+        const unsigned lyp = (nb && y < a.my - 1) ? lu + 8u * (unsigned)sy : kNoLane;
+        const unsigned lzm = (nb && z > 0) ? lu - 8u * (unsigned)sz : kNoLane;
+        const unsigned lzp = (nb && z < a.mz - 1) ? lu + 8u * (unsigned)sz : kNoLane;
+        const unsigned lq = (unsigned)(qb - qb0) * 8u;   // per-row tables s, scale
+        const double vt = a.ta * buf_ld(buf_rsrc(a.v, M * 8), valid ? (unsigned)d * 8u : kNoLane, 0.0);
+
+        double g[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const size_t r0 = (size_t)(qb0 + i * RS);
+            const auto rU = buf_rsrc(a.U + r0 * M, ((size_t)a.N - r0) * M * 8);
+            const double u = buf_ld(rU, lu, 0.0);
+            double acc = vt * buf_ld(buf_rsrc(a.s + r0, ((size_t)a.N - r0) * 8), lq, 0.0);
+            if (a.f) acc += buf_ld(buf_rsrc(a.f + (r0 + 1) * M, ((size_t)a.N - r0) * M * 8), lu, 0.0);
+            if (resid) {
+                acc += a.ihx2 * (buf_ld(rU, lxm, 0.0) + buf_ld(rU, lxp, 0.0)) +
+                       a.ihy2 * (buf_ld(rU, lym, 0.0) + buf_ld(rU, lyp, 0.0));
+                if (has3) acc += a.ihz2 * (buf_ld(rU, lzm, 0.0) + buf_ld(rU, lzp, 0.0));
+            }
+            cbr[tid + i * NT] = u;
+            cbr[N * W + tid + i * NT] = 0.0;   // zero padding to length 2N
+            g[i] = acc;
+        }
+        if (a.ncorr > 0) {
+            // correction rows q < ncorr <= 5 all lie in row group 0 (RS >= 8)
+            const unsigned lc = (valid && qb < a.ncorr) ? ((unsigned)qb * (unsigned)M + (unsigned)d) * 8u : kNoLane;
+            g[0] += buf_ld(buf_rsrc(a.corr, (size_t)a.ncorr * M * 8), lc, 0.0);
+        }
+        __syncthreads();
+        if (resid) {
+            // A_h U^n: centre and the x neighbours inside the tile
+            const double cim = (hxm && dl > 0) ? a.ihx2 : 0.0, cip = (hxp && dl < W - 1) ? a.ihx2 : 0.0;
+            const int om = dl > 0 ? -1 : 0, op = dl < W - 1 ? 1 : 0;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const double* sp = cbr + tid + i * NT;
+                g[i] -= diag * sp[0] - cim * sp[om] - cip * sp[op];
+            }
+        }
+        // DFT of omega at the points this thread multiplies (consumed after the forward FFT)
+        double2 wv[PER];
+        const auto rW = buf_rsrc(a.what, (size_t)N2 * 16);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) wv[j] = buf_ld(rW, (unsigned)((tid + j * NT) / B) * 16u, double2{});
+        lds_fft<double, LOGN + 1, B, NT, false, true, 0>(cb, tw2, tid);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) cb[tid + j * NT] = cmul(cb[tid + j * NT], wv[j]);
+        double sc[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const size_t r0 = (size_t)(qb0 + i * RS);
+            sc[i] = buf_ld(buf_rsrc(a.scale + r0, ((size_t)a.N - r0) * 8), lq, 0.0);
+        }
+        __syncthreads();
+        lds_fft<double, LOGN + 1, B, NT, true, true, 0>(cb, tw2, tid);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const double c = cbr[crow * W + tid + i * NT];
+            const double r = resid ? g[i] - a.ta * c : g[i] + a.kappa * a.ta * c;
+            smr[tid + i * NT] = valid ? (R)(r * sc[i]) : (R)0;
+        }
+        __syncthreads();
+        lds_fft<R, LOGN, B, NT, false, true, 0>(sm, tw1, tid);
+        store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<T*>(a.S), a.ldS, d0, a.Mp, tid);
+        __syncthreads();   // the next tile overwrites the buffer
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward kernel, CQ-BDF-k residual form on 2D grids, marching along y.
+// The history convolution of k_fwd_cq is split into two length-N transforms:
+// with z the tile's pair sequences, zero-padded to 2N, and t_j = e^{-pi i j/N},
+// the even points of FFT_2N(z, 0) are FFT_N(z) and the odd points FFT_N(z t),
+// so for j < N
+//   c_j = IFFT_N(W_even . FFT_N(z))_j + conj(t_j) IFFT_N(W_odd . FFT_N(z t))_j,
+// W the 2N-point DFT of (omega, 0) divided by 2N.  The FFT buffer is N x B and
+// the even part waits in a second N x W buffer, so the omega DFT, the twiddles
+// and the per-row factors all stay in LDS and no partial sum is held in
+// registers across a transform.  As in k_fwd_march, a workgroup owns W x slots
+// and walks a chunk of y; each lane keeps its time rows of U at y-1, y, y+1 in
+// registers (renamed, never copied), x neighbours inside the tile come from
+// the adjacent lanes (DPP), and the load of U at y+2 is issued once U at y-1
+// has been used, one whole position (four FP64 transforms, the time FFT and
+// the spectrum store) before it is needed.
+template <int W>
+__device__ __forceinline__ double lane_dpp(double v, bool next) {
+    if constexpr (W <= 16) {
+        // row_shl:1 / row_shr:1 inside 16-lane DPP rows (the W-lane groups never
+        // straddle a row); a lane with no source in its row reads 0
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+        if (next) {
+            lo = __builtin_amdgcn_update_dpp(0, lo, 0x101, 0xF, 0xF, true);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0x101, 0xF, 0xF, true);
+        } else {
+            lo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xF, 0xF, true);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xF, 0xF, true);
+        }
+        return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    } else {
+        return next ? __shfl_down(v, 1, 64) : __shfl_up(v, 1, 64);
+    }
+}
+// value of the partner lane (lane ^ 1): quad_perm [1, 0, 3, 2]
+__device__ __forceinline__ double lane_pair(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0xB1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// x slots per tile of the CQ march: 4096 (time row, slot) elements
+constexpr int cqm_tile(int logn) {
+    const int w = 4096 >> logn;
+    return w > 64 ? 64 : (w < 2 ? 2 : w);
+}
+template <typename R, int LOGN, int W> constexpr size_t cqm_lds() {
+    constexpr size_t N = size_t(1) << LOGN;
+    return N * W * 8 * 2 + 3 * N * 16 + (N / 2) * sizeof(cx<R>) + 2 * N * 8;
+}
+#ifndef PINT_CQM_MAXLOG
+#define PINT_CQM_MAXLOG 3
+#endif
+template <typename R, int LOGN, int W, int NT>
+__global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchunk, int chunk) {
+    using T = cx<R>;
+    constexpr int N = 1 << LOGN;
+    constexpr int B = W / 2;
+    constexpr int PER = N * W / NT;     // (time row, slot) elements per thread
+    constexpr int PC = N * B / NT;      // complex points per thread in the pointwise products
+    constexpr int RS = NT / W;          // time rows between a thread's consecutive elements
+    static_assert(PER * NT == N * W && PC * NT == N * B && RS >= 8, "tile shape");
+    __shared__ double2 buf[N * B];      // FP64 pair sequences; then the time-FFT buffer (cx<R>)
+    __shared__ double sev[N * W];       // the even part of the convolution
+    __shared__ double2 swe[N], swo[N];  // W_{2j}, W_{2j+1}
+    __shared__ double2 stw[N];          // e^{-pi i j/N}, j < N (twist; FFT_N twiddles at stride 2)
+    __shared__ T stw1[N / 2];           // e^{-2 pi i j/N} in the spectrum precision
+    __shared__ double ssn[N], ssc[N];   // tau^{-alpha} s_q and kappa^{q/N}
+    double* cbr = reinterpret_cast<double*>(buf);
+    R* smr = reinterpret_cast<R*>(buf);
+    T* sm = reinterpret_cast<T*>(buf);
+
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    if (lin >= ncol * nchunk) return;
+    const int xt = lin % ncol, chk = lin / ncol;
+    const int nm = a.my;
+    const int c0 = chk * chunk, c1 = min(nm, c0 + chunk);
+    const int tid = threadIdx.x;
+    const int dl = tid % W;
+    const int qb = tid / W;
+    const int x = xt * W + dl;
+    const bool valid = x < a.mx;
+    const size_t M = a.M;
+    const long long sdof = a.mx;                    // dof stride along y
+    const long long slot0 = (long long)xt * W;
+
+    for (int j = tid; j < N; j += NT) {
+        swe[j] = a.what[2 * j];
+        swo[j] = a.what[2 * j + 1];
+        stw[j] = a.tw2[j];
+        ssn[j] = a.ta * a.s[j];
+        ssc[j] = a.scale[j];
+        if (j < N / 2) stw1[j] = reinterpret_cast<const T*>(a.tw)[j];
+    }
+    // Loads: a uniform base per row group i and position c plus a 32-bit byte
+    // offset per lane fixed for the whole kernel (the host checks that it
+    // fits); padding slots and absent x neighbours read 0 through kNoLane.
+    const unsigned lo = valid ? (unsigned)(((long long)qb * (long long)M + x) * 8) : kNoLane;
+    const unsigned lhx = (valid && dl == 0 && x > 0) ? lo - 8u : ((valid && dl == W - 1 && x < a.mx - 1) ? lo + 8u : kNoLane);
+    const unsigned lv = valid ? (unsigned)x * 8u : kNoLane;
+    const size_t nU = (size_t)a.N * M;
+    const double diag = 2.0 * (a.ihx2 + a.ihy2);
+    const double cxm = dl > 0 ? a.ihx2 : 0.0, cxp = dl < W - 1 ? a.ihx2 : 0.0;   // inside the tile (DPP)
+    const double hxc = (dl == 0 || dl == W - 1) ? a.ihx2 : 0.0;                   // the halo value
+    const double sgn = (dl & 1) ? 1.0 : -1.0;      // odd lanes hold imaginary parts of the pairs
+
+    double A[PER], Bv[PER], C[PER];
+    auto load_row = [&](double (&dst)[PER], int c) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const size_t e0 = (size_t)i * RS * M + (size_t)c * sdof;
+            dst[i] = buf_ld(buf_rsrc(a.U + e0, (nU - e0) * 8), lo, 0.0);
+        }
+    };
+
+    // One position c with U at c-1, c, c+1 in Um, Uc, Up; Um is refilled with U at c+2.
+    // The x halo, v, f and the corrections of position c are read at its start
+    // and used after the transforms of the convolution.
+    auto step = [&](int c, double (&Um)[PER], double (&Uc)[PER], double (&Up)[PER]) {
+        const double cm = c > 0 ? a.ihy2 : 0.0, cp = c < nm - 1 ? a.ihy2 : 0.0;
+        const int t = loop_tid();   // LDS addressing is recomputed per position, not hoisted
+        double hx[PER], fr[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const size_t e0 = (size_t)i * RS * M + (size_t)c * sdof;
+            hx[i] = buf_ld(buf_rsrc(a.U + e0, (nU - e0) * 8), lhx, 0.0);
+        }
+        const double vv = buf_ld(buf_rsrc(a.v + (size_t)c * sdof, (M - (size_t)c * sdof) * 8), lv, 0.0);
+        if (a.f) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const size_t e0 = (size_t)(i * RS + 1) * M + (size_t)c * sdof;
+                fr[i] = buf_ld(buf_rsrc(a.f + e0, ((size_t)a.N * M + M - e0) * 8), lo, 0.0);
+            }
+        }
+        double cr = 0.0;
+        if (a.ncorr > 0) {   // rows q < ncorr <= 5 lie in row group 0
+            const size_t e0 = (size_t)c * sdof;
+            cr = buf_ld(buf_rsrc(a.corr + e0, ((size_t)a.ncorr * M - e0) * 8), qb < a.ncorr ? lo : kNoLane, 0.0);
+        }
+        // even points: FFT_N of the pair sequences of U at c
+#pragma unroll
+        for (int i = 0; i < PER; ++i) cbr[t + i * NT] = Uc[i];
+        __syncthreads();
+        lds_fft<double, LOGN, B, NT, false, true, 0, 0, 2, PINT_CQM_MAXLOG>(buf, stw, t);
+#pragma unroll
+        for (int j = 0; j < PC; ++j) buf[t + j * NT] = cmul(buf[t + j * NT], swe[(t + j * NT) / B]);
+        __syncthreads();
+        lds_fft<double, LOGN, B, NT, true, true, 0, 0, 2, PINT_CQM_MAXLOG>(buf, stw, t);
+        // park the even part; each lane overwrites its own element with z t_q
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = t / W + i * RS;
+            sev[t + i * NT] = cbr[t + i * NT];
+            const double2 tq = stw[q];
+            const double u = Uc[i];
+            cbr[t + i * NT] = u * tq.x + sgn * lane_pair(u) * tq.y;
+        }
+        __syncthreads();
+        // odd points
+        lds_fft<double, LOGN, B, NT, false, true, 0, 0, 2, PINT_CQM_MAXLOG>(buf, stw, t);
+#pragma unroll
+        for (int j = 0; j < PC; ++j) buf[t + j * NT] = cmul(buf[t + j * NT], swo[(t + j * NT) / B]);
+        __syncthreads();
+        lds_fft<double, LOGN, B, NT, true, true, 0, 0, 2, PINT_CQM_MAXLOG>(buf, stw, t);
+        // r = (G - A_h U^n - tau^{-alpha} c) kappa^{q/N}
+        double r[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = t / W + i * RS;
+            const double2 tq = stw[q];
+            const double p = cbr[t + i * NT];
+            const double c2 = p * tq.x - sgn * lane_pair(p) * tq.y;   // conj(t_q) times the pair value
+            const double u = Uc[i];
+            const double xm = lane_dpp<W>(u, false), xp = lane_dpp<W>(u, true);
+            const double au = diag * u - cxm * xm - cxp * xp - hxc * hx[i] - cm * Um[i] - cp * Up[i];
+            double g = ssn[q] * vv - au;
+            if (a.f) g += fr[i];
+            if (i == 0) g += cr;
+            r[i] = (g - a.ta * (sev[t + i * NT] + c2)) * ssc[q];
+        }
+        // U at c-1 is consumed: prefetch U at c+2
+        __builtin_amdgcn_sched_barrier(0);
+        load_row(Um, min(c + 2, nm - 1));
+        __syncthreads();   // the R buffer aliases FP64 elements of other lanes
+#pragma unroll
+        for (int i = 0; i < PER; ++i) smr[t + i * NT] = valid ? (R)r[i] : (R)0;
+        __syncthreads();
+        lds_fft<R, LOGN, B, NT, false, true, 0, 0, 1, PINT_CQM_MAXLOG>(sm, stw1, t);
+        store_half_spectrum<R, N, B, NT, false>(sm, reinterpret_cast<T*>(a.S), a.ldS, (int)(slot0 + (long long)c * a.mxp),
+                                                a.Mp, t);
+        __syncthreads();
+    };
+
+    load_row(A, max(c0 - 1, 0));
+    load_row(Bv, c0);
+    load_row(C, min(c0 + 1, nm - 1));
+    __syncthreads();   // tables
+    for (int c = c0; c < c1; c += 3) {
+        step(c, A, Bv, C);
+        if (c + 1 < c1) step(c + 1, Bv, C, A);
+        if (c + 2 < c1) step(c + 2, C, A, Bv);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1635,7 +1946,15 @@ int persistent_blocks(const void* fn, int nt) {
     return cus * per;
 }
 #define N_OF(logn) (1 << (logn))
-constexpr int kNTcq = 512;  // the length-2N FP64 convolution FFT needs more lanes per tile
+// Lanes of the CQ forward kernel (512: the register budget of two waves per SIMD
+// holds a radix-16 FP64 butterfly beside the per-element partial sums).
+#ifndef PINT_CQ_NT
+#define PINT_CQ_NT 512
+#endif
+constexpr int cq_nt(int logn) {
+    const int e = (1 << logn) * cq_tile(logn);
+    return e < PINT_CQ_NT ? e : PINT_CQ_NT;
+}
 
 // Marching forward launch: one workgroup per (x tile, line, chunk of the
 // outer axis), with the chunk length chosen so that the grid fills the device once.
@@ -1663,10 +1982,34 @@ template <typename R, int LOGN>
 hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
     if (cq) {
         constexpr int W = cq_tile(LOGN);
+        constexpr int WM = cqm_tile(LOGN);
+        if constexpr (cqm_lds<R, LOGN, WM>() <= 163840 && N_OF(LOGN) * WM >= 2 * PINT_CQ_NT) {
+            constexpr int NTM = PINT_CQ_NT;
+            // 2D residual form: march along y (32-bit lane offsets, whole tiles per grid row)
+            if (a.form == 0 && a.my > 1 && a.mz == 1 && a.mxp % WM == 0 &&
+                (long long)(NTM / WM + 2) * a.M * 8 < (1LL << 32)) {
+                const void* fn = reinterpret_cast<const void*>(&k_fwd_cqm<R, LOGN, WM, NTM>);
+                const int ncol = a.mxp / WM;
+                const int target = persistent_blocks(fn, NTM);
+                int nchunk = std::max(1, std::min(a.my, (target + ncol - 1) / ncol));
+                const int chunk = (a.my + nchunk - 1) / nchunk;
+                nchunk = (a.my + chunk - 1) / chunk;
+                const int grid = ((ncol * nchunk + 7) / 8) * 8;
+                if (nb) *nb = grid;
+                hipLaunchKernelGGL((k_fwd_cqm<R, LOGN, WM, NTM>), dim3(grid), dim3(NTM), 0, st, a, ncol, nchunk, chunk);
+                return hipGetLastError();
+            }
+        }
         const int ntiles = (a.Mp + W - 1) / W;
-        const int grid = ((ntiles + 7) / 8) * 8;
+        const int nvirt = ((ntiles + 7) / 8) * 8;
+        constexpr int NT = cq_nt(LOGN);
+        // per-lane byte offsets of the kernel's buffer loads are 32-bit
+        if ((long long)(64 / W + 1) * a.M * 8 >= (1LL << 32)) return hipErrorInvalidValue;
+        const void* fn = reinterpret_cast<const void*>(&k_fwd_cq<R, LOGN, W, NT>);
+        // a multiple of 8 workgroups, so workgroup b stays on XCD b mod 8 for all its tiles
+        const int grid = std::min(nvirt, std::max(8, persistent_blocks(fn, NT) / 8 * 8));
         if (nb) *nb = grid;
-        hipLaunchKernelGGL((k_fwd_cq<R, LOGN, W, kNTcq>), dim3(grid), dim3(kNTcq), 0, st, a);
+        hipLaunchKernelGGL((k_fwd_cq<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a, nvirt);
     } else {
         constexpr int W = fwd_tile(LOGN);
         constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
@@ -1681,7 +2024,7 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
                 if (a.mz == 1 && WW <= a.mxp && (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32))
                     return fwd_march<R, LOGN, WW, NTW, true>(a, nb, st);
             // the marching kernels address with 32-bit byte offsets per lane
-            if (W <= a.mxp && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32))
+            if (W <= a.mxp && a.mxp % W == 0 && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32))
                 return fwd_march<R, LOGN, W, NTM, false>(a, nb, st);
         }
         const int ntiles = (a.Mp + W - 1) / W;

@@ -64,6 +64,11 @@ SMALL = [
     (2, (30, 12), 64, 2, 0.5, 1e-3),
     (2, (1, 5), 8, 1, 1.0, 0.1),
     (3, (6, 9, 5), 16, 2, 1.0, 1e-3),
+    # 2D subdiffusion with whole x tiles per grid row (the forward pass marches along y)
+    (2, (45, 20), 1024, 2, 0.7, 1e-3),
+    (2, (61, 9), 256, 3, 0.5, 1e-3),
+    (2, (13, 40), 512, 3, 0.3, 1e-3),
+    (2, (29, 2), 128, 4, 0.5, 1e-3),
 ]
 
 
