@@ -174,6 +174,42 @@ pint_status pint_batch_plan_create(pint_plan **plan, int count, const pint_grid 
 pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const double *const *f,
                              const double *const *fder, double *const *U, double *upd, int *sweeps);
 
+/* Autotuning of the kernels' tile and split choices (the batching row of the
+ * method's GPU mapping: FFT radix and tile shapes, PCR/Thomas split).  Four
+ * knobs, each 0 = the built-in choice:
+ *   [0] forward kernel: BDF-k residual 2D/3D sweeps 0 wide-tile march,
+ *       1 march with the time-FFT tile, 2 one workgroup per tile; CQ sweeps
+ *       0 y-march with radix <= 8 transforms, 1 y-march with radix <= 16,
+ *       2 persistent one-tile-at-a-time kernel (a choice that does not apply
+ *       to the problem falls back to the next one that does);
+ *   [1] rows per workgroup of the x sine pass: 0 built-in, 1 half as many;
+ *   [2] column tile of the y/z passes: 0 built-in, 1 the other width;
+ *   [3] 1D tridiagonal systems: 0 built-in split, 1 more PCR lanes.
+ * Tuning times every value of a knob that launches a different kernel for the
+ * problem, reps times each, on the plan's own workspace (the forward kernels
+ * read U, nothing writes it), and keeps the fastest.  It synchronises the
+ * plan's stream.  Results are unchanged up to rounding by the choice.
+ *
+ * pint_plan_set_autotune: reps > 0 makes pint_solve (pint_batch_solve: every
+ * instance) tune once, after binding and the initial iterate, before its first
+ * sweep; 0 (the default) keeps the current choices.  Errors: PINT_E_ARG
+ * (NULL plan, reps outside 0..1000). */
+pint_status pint_plan_set_autotune(pint_plan *plan, int reps);
+
+/* Tune a single plan now.  Requires pint_bind; U: DEVICE [N][M], read only
+ * (its values only affect timing); reps in 1..1000.  Errors: PINT_E_ARG (NULL
+ * plan or U, not bound, batch plan), PINT_E_HIP. */
+pint_status pint_plan_tune(pint_plan *plan, const double *U, int reps);
+
+/* The variants in use: choices HOST [4] (the knobs above).  instance selects a
+ * batch member; it must be 0 for a single plan.  Errors: PINT_E_ARG. */
+pint_status pint_plan_get_variants(const pint_plan *plan, int instance, int *choices);
+
+/* Pin the variants (choices HOST [4], each within its knob's range), e.g. the
+ * result of an earlier tuning run; a pinned plan is not tuned again.
+ * Errors: PINT_E_ARG (NULL, out of range, bad instance). */
+pint_status pint_plan_set_variants(pint_plan *plan, int instance, const int *choices);
+
 /* Release the plan, its tables and any workspace it allocated itself.
  * Waits for the plan's stream.  NULL is accepted. */
 pint_status pint_plan_destroy(pint_plan *plan);

@@ -51,6 +51,10 @@ EXPORTS = {
                                        POINTER(pint_params), c_void_p]),
     "pint_batch_solve": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                  POINTER(c_void_p), POINTER(c_double), POINTER(c_int)]),
+    "pint_plan_set_autotune": (c_int, [c_void_p, c_int]),
+    "pint_plan_tune": (c_int, [c_void_p, c_void_p, c_int]),
+    "pint_plan_get_variants": (c_int, [c_void_p, c_int, POINTER(c_int)]),
+    "pint_plan_set_variants": (c_int, [c_void_p, c_int, POINTER(c_int)]),
     "pint_plan_destroy": (c_int, [c_void_p]),
     "pint_plan_unknowns": (c_longlong, [c_void_p]),
     "pint_status_str": (ctypes.c_char_p, [c_int]),
@@ -192,6 +196,26 @@ def pint_batch_solve(plan, v, f, fder, U, max_sweeps):
     return st, [list(upd)[i * max_sweeps:i * max_sweeps + sw[i]] for i in range(n)], sw
 
 
+def pint_plan_set_autotune(plan, reps):
+    _check(lib().pint_plan_set_autotune(plan, int(reps)), "pint_plan_set_autotune")
+
+
+def pint_plan_tune(plan, U, reps):
+    _check(lib().pint_plan_tune(plan, _ptr(U), int(reps)), "pint_plan_tune")
+
+
+def pint_plan_get_variants(plan, instance=0):
+    """The kernel variants in use: [forward, x pass, y/z pass, 1D tridiagonal split]."""
+    c = (c_int * 4)()
+    _check(lib().pint_plan_get_variants(plan, int(instance), c), "pint_plan_get_variants")
+    return list(c)
+
+
+def pint_plan_set_variants(plan, choices, instance=0):
+    c = (c_int * 4)(*[int(x) for x in choices])
+    _check(lib().pint_plan_set_variants(plan, int(instance), c), "pint_plan_set_variants")
+
+
 def pint_plan_destroy(plan):
     lib().pint_plan_destroy(plan)
 
@@ -233,6 +257,19 @@ class Plan:
 
     def profile(self, U, n):
         return pint_profile_sweeps(self.h, U, n)
+
+    def set_autotune(self, reps):
+        pint_plan_set_autotune(self.h, reps)
+
+    def tune(self, U, reps=3):
+        pint_plan_tune(self.h, U, reps)
+        return self.variants()
+
+    def variants(self):
+        return pint_plan_get_variants(self.h, 0)
+
+    def set_variants(self, choices):
+        pint_plan_set_variants(self.h, choices, 0)
 
     def solve(self, v, f=None, fder=None, U=None):
         import torch

@@ -163,6 +163,10 @@ struct pint_plan {
     std::vector<hipEvent_t> lane_ev;
     double* d_bnorms = nullptr;       // [count][2] per-instance norms of the last sweep
     double* h_bnorms = nullptr;       // pinned host copy
+    // kernel variants in use: forward, x pass, y/z pass, 1D tridiagonal split (0 = built-in)
+    int var[4] = {0, 0, 0, 0};
+    int tune_reps = 0;                // > 0: the solves time the variants first (autotune)
+    bool tuned = false;
 
     ~pint_plan() {
         for (void* q : owned) (void)hipFree(q);
@@ -536,23 +540,11 @@ FwdArgs fwd_args(const pint_plan* P, const double* U) {
     fa.kappa = P->p.kappa;
     fa.form = P->p.form == PINT_DIRECT ? 1 : 0;
     fa.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
+    fa.var = P->var[0];
     return fa;
 }
 
-pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof = nullptr) {
-    if (prof) prof->cursor = 0;
-    FwdArgs fa = fwd_args(P, U);
-    if (P->Sg) {
-        // direct form, BDF-k: stored source spectrum + the k relaxation rows
-        PROF_BEGIN(prof, "direct_rhs_spectrum");
-        HIP_TRY(pint::launch_inject(fa, P->Sg, P->mixed, P->st));
-        PROF_END(prof);
-    } else {
-        PROF_BEGIN(prof, P->cq ? "forward_cq_rhs_tfft" : "forward_rhs_tfft");
-        HIP_TRY(pint::launch_forward(fa, P->mixed, P->cq, nullptr, P->st));
-        PROF_END(prof);
-    }
-
+SpaceArgs space_args(const pint_plan* P) {
     SpaceArgs sa{};
     sa.S = P->S;
     sa.nP = P->nP;
@@ -573,6 +565,27 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof
         sa.ih2[i] = P->ih2[i];
     }
     sa.inv_factor = P->inv_factor;
+    sa.var_rows = P->var[1];
+    sa.var_cols = P->var[2];
+    sa.var_tri = P->var[3];
+    return sa;
+}
+
+pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof = nullptr) {
+    if (prof) prof->cursor = 0;
+    FwdArgs fa = fwd_args(P, U);
+    if (P->Sg) {
+        // direct form, BDF-k: stored source spectrum + the k relaxation rows
+        PROF_BEGIN(prof, "direct_rhs_spectrum");
+        HIP_TRY(pint::launch_inject(fa, P->Sg, P->mixed, P->st));
+        PROF_END(prof);
+    } else {
+        PROF_BEGIN(prof, P->cq ? "forward_cq_rhs_tfft" : "forward_rhs_tfft");
+        HIP_TRY(pint::launch_forward(fa, P->mixed, P->cq, nullptr, P->st));
+        PROF_END(prof);
+    }
+
+    const SpaceArgs sa = space_args(P);
     for (int i = 0; i < pint::space_pass_count(sa); ++i) {
         PROF_BEGIN(prof, pint::space_pass_name(sa, i));
         HIP_TRY(pint::launch_space_pass(sa, P->mixed, i, P->st));
@@ -599,6 +612,94 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof
     PROF_BEGIN(prof, "norm_reduce");
     HIP_TRY(pint::launch_norm_reduce(P->partial, nb, P->hd, norms_out, P->st));
     PROF_END(prof);
+    return PINT_OK;
+}
+
+// Autotuner: times each kernel variant that launches a different kernel for
+// this problem than the built-in choice, on the plan's own spectrum buffer and
+// the caller's U (read only: the forward kernels read U and write the spectrum,
+// the spatial passes work on the spectrum in place, so the values they leave
+// behind are overwritten by the next sweep's first kernel), and keeps the
+// fastest.  Knobs: the forward kernel (not used by direct-form BDF sweeps),
+// rows per workgroup of the x sine pass, the column tile of the y/z passes,
+// and the PCR/Thomas split of 1D tridiagonal solves.
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+template <typename F>
+pint_status time_launches(pint_plan* P, Timer& t, int reps, F&& launch, float* ms) {
+    HIP_TRY(launch());   // first launch: code object load, caches
+    HIP_TRY(hipEventRecord(t.a, P->st));
+    for (int r = 0; r < reps; ++r) HIP_TRY(launch());
+    HIP_TRY(hipEventRecord(t.b, P->st));
+    HIP_TRY(hipEventSynchronize(t.b));
+    HIP_TRY(hipEventElapsedTime(ms, t.a, t.b));
+    return PINT_OK;
+}
+
+pint_status tune_plan(pint_plan* P, const double* U, int reps) {
+    Timer t;
+    HIP_TRY(hipEventCreate(&t.a));
+    HIP_TRY(hipEventCreate(&t.b));
+    pint_status rc;
+    // pick the fastest of the candidate values of knob k (value 0 always included)
+    auto pick = [&](int k, const std::vector<int>& cand, auto&& launch) -> pint_status {
+        float best = 0.0f;
+        int arg = 0;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            P->var[k] = cand[c];
+            float ms = 0.0f;
+            pint_status r = time_launches(P, t, reps, launch, &ms);
+            if (r != PINT_OK) {
+                P->var[k] = 0;
+                return r;
+            }
+            if (c == 0 || ms < best) {
+                best = ms;
+                arg = cand[c];
+            }
+        }
+        P->var[k] = arg;
+        return PINT_OK;
+    };
+    if (!P->Sg) {
+        std::vector<int> cand{0};
+        const FwdArgs fa0 = fwd_args(P, U);
+        for (int v = 1; v < pint::kFwdVariants; ++v)
+            if (pint::forward_variant_distinct(fa0, P->mixed, P->cq, v)) cand.push_back(v);
+        if (cand.size() > 1) {
+            rc = pick(0, cand, [&]() { return pint::launch_forward(fwd_args(P, U), P->mixed, P->cq, nullptr, P->st); });
+            if (rc != PINT_OK) return rc;
+        }
+    }
+    const SpaceArgs sa0 = space_args(P);
+    // the x pass is pass 0 (1D: the whole solve); the y/z passes are 1 .. count-2
+    if (pint::rows_variant_distinct(sa0, P->mixed)) {
+        rc = pick(1, {0, 1}, [&]() { return pint::launch_space_pass(space_args(P), P->mixed, 0, P->st); });
+        if (rc != PINT_OK) return rc;
+    }
+    if (pint::cols_variant_distinct(sa0, P->mixed)) {
+        rc = pick(2, {0, 1}, [&]() {
+            const SpaceArgs sa = space_args(P);
+            const int n = pint::space_pass_count(sa);
+            for (int i = 1; i < n - 1; ++i) {
+                const hipError_t e = pint::launch_space_pass(sa, P->mixed, i, P->st);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        });
+        if (rc != PINT_OK) return rc;
+    }
+    if (pint::tri_variant_distinct(sa0)) {
+        rc = pick(3, {0, 1}, [&]() { return pint::launch_space_pass(space_args(P), P->mixed, 0, P->st); });
+        if (rc != PINT_OK) return rc;
+    }
+    P->tuned = true;
     return PINT_OK;
 }
 
@@ -734,6 +835,7 @@ pint_status pint_solve(pint_plan* P, const double* v, const double* f, const dou
     pint_status rc = pint_bind(P, v, f, fder);
     if (rc != PINT_OK) return rc;
     if ((rc = pint_init_iterate(P, U)) != PINT_OK) return rc;
+    if (P->tune_reps > 0 && !P->tuned && (rc = tune_plan(P, U, P->tune_reps)) != PINT_OK) return rc;
     std::vector<double> hist;
     int done = 0;
     pint_status result = PINT_NOT_CONVERGED;
@@ -763,6 +865,50 @@ pint_status pint_solve(pint_plan* P, const double* v, const double* f, const dou
     }
     if (sweeps) *sweeps = done;
     return result;
+}
+
+pint_status pint_plan_set_autotune(pint_plan* P, int reps) {
+    if (!P || reps < 0 || reps > 1000) return fail(PINT_E_ARG, "bad arguments to pint_plan_set_autotune");
+    P->tune_reps = reps;
+    return PINT_OK;
+}
+
+pint_status pint_plan_tune(pint_plan* P, const double* U, int reps) {
+    if (!P || !U || reps < 1 || reps > 1000) return fail(PINT_E_ARG, "bad arguments to pint_plan_tune");
+    if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans tune their instances in pint_batch_solve");
+    if (!P->bound) return fail(PINT_E_ARG, "pint_bind must be called first");
+    for (int k = 0; k < 4; ++k) P->var[k] = 0;
+    return tune_plan(P, U, reps);
+}
+
+pint_status pint_plan_get_variants(const pint_plan* P, int instance, int* choices) {
+    if (!P || !choices) return fail(PINT_E_ARG, "plan and choices must not be NULL");
+    const pint_plan* Q = P;
+    if (!P->inst.empty()) {
+        if (instance < 0 || instance >= (int)P->inst.size()) return fail(PINT_E_ARG, "instance out of range");
+        Q = P->inst[instance];
+    } else if (instance != 0) {
+        return fail(PINT_E_ARG, "instance must be 0 for a single plan");
+    }
+    for (int k = 0; k < 4; ++k) choices[k] = Q->var[k];
+    return PINT_OK;
+}
+
+pint_status pint_plan_set_variants(pint_plan* P, int instance, const int* choices) {
+    if (!P || !choices) return fail(PINT_E_ARG, "plan and choices must not be NULL");
+    pint_plan* Q = P;
+    if (!P->inst.empty()) {
+        if (instance < 0 || instance >= (int)P->inst.size()) return fail(PINT_E_ARG, "instance out of range");
+        Q = P->inst[instance];
+    } else if (instance != 0) {
+        return fail(PINT_E_ARG, "instance must be 0 for a single plan");
+    }
+    const int hi[4] = {pint::kFwdVariants - 1, 1, 1, 1};
+    for (int k = 0; k < 4; ++k)
+        if (choices[k] < 0 || choices[k] > hi[k]) return fail(PINT_E_ARG, "variant out of range");
+    for (int k = 0; k < 4; ++k) Q->var[k] = choices[k];
+    Q->tuned = true;   // pinned choices are not re-tuned
+    return PINT_OK;
 }
 
 pint_status pint_plan_destroy(pint_plan* P) {
@@ -857,6 +1003,18 @@ namespace {
 // back on the plan's stream, so independent instances may run concurrently.
 pint_status capture_batch_sweep(pint_plan* P, const std::vector<int>& active, double* const* U,
                                 hipGraphExec_t* exec) {
+    // Prepared sweep first: every occupancy query and kernel attribute the
+    // launches need is made here, outside the capture, so that recording the
+    // sweep issues nothing but stream work.
+    pint::set_prepare_only(true);
+    for (int i : active) {
+        const pint_status rp = one_sweep(P->inst[i], U[i], P->d_bnorms + 2 * i);
+        if (rp != PINT_OK) {
+            pint::set_prepare_only(false);
+            return rp;
+        }
+    }
+    pint::set_prepare_only(false);
     HIP_TRY(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
     hipGraph_t graph = nullptr;
     pint_status rc = PINT_OK;
@@ -901,6 +1059,7 @@ pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double*
         pint_status rc = pint_bind(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr);
         if (rc != PINT_OK) return rc;
         if ((rc = pint_init_iterate(Q, U[i])) != PINT_OK) return rc;
+        if (P->tune_reps > 0 && !Q->tuned && (rc = tune_plan(Q, U[i], P->tune_reps)) != PINT_OK) return rc;
         if (Q->p.max_sweeps > max_sw) max_sw = Q->p.max_sweeps;
         if (sweeps) sweeps[i] = 0;
     }

@@ -36,6 +36,7 @@ struct FwdArgs {
     double kappa;
     int form;               // 0 residual, 1 direct, 2 the source part G alone (U not read)
     int ncorr;              // number of correction rows (k-1, or 0)
+    int var;                // forward kernel variant (kFwdVariants; 0 = built-in choice)
 };
 
 // Inverse time FFT + unscale + update + norm partials.
@@ -66,7 +67,17 @@ struct SpaceArgs {
     const void* twP[3];     // [P_a] twiddles e^{-2 pi i j/P_a}
     double ih2[3];          // 1/h^2 per axis
     double inv_factor;      // 1 / prod_a (-2 (m_a + 1)) for the raw DST pair
+    int var_rows;           // x-pass variant: 0 = built-in rows per workgroup, 1 = half as many
+    int var_cols;           // y/z-pass variant: 0 = built-in column tile, 1 = the other width
+    int var_tri;            // 1D tridiagonal split: 0 = built-in, 1 = the next wider split
 };
+
+// Kernel variants the autotuner chooses between (index 0 is the built-in choice).
+//   forward, BDF-k residual 2D/3D: 0 wide-tile march when eligible (else 1),
+//     1 march with the time-FFT tile, 2 one workgroup per tile;
+//   forward, CQ: 0 y-march with radix <= 8 transforms when eligible (else 2),
+//     1 y-march with radix <= 16, 2 persistent one-tile-at-a-time kernel.
+constexpr int kFwdVariants = 3;
 
 // Host-side launchers (defined in pint_kernels.hip).  Each returns the
 // hipError_t of the launch; shapes are validated by the caller.
@@ -86,6 +97,15 @@ const char* space_pass_name(const SpaceArgs& a, int pass);
 hipError_t launch_space_pass(const SpaceArgs& a, bool mixed, int pass, hipStream_t st);
 hipError_t launch_norm_reduce(const double* partial, int nblocks, double hd, double* out,
                               hipStream_t st);
+// Prepare-only mode for the calling host thread: launchers make their runtime
+// queries (occupancy, kernel attributes) but launch nothing.
+void set_prepare_only(bool on);
+// Whether a variant differs from the built-in choice for this problem (the
+// autotuner skips the ones that would launch the same kernel).
+bool forward_variant_distinct(const FwdArgs& a, bool mixed, bool cq, int var);
+bool rows_variant_distinct(const SpaceArgs& a, bool mixed);
+bool cols_variant_distinct(const SpaceArgs& a, bool mixed);
+bool tri_variant_distinct(const SpaceArgs& a);
 
 // Largest time-FFT length and DST length the kernels are compiled for.
 constexpr int kMaxLogN = 11;      // N <= 2048

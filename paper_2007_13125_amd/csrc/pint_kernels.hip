@@ -15,6 +15,9 @@
 #include "pint_internal.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <cstdint>
 
 namespace pint {
@@ -1067,10 +1070,8 @@ template <typename R, int LOGN, int W> constexpr size_t cqm_lds() {
     constexpr size_t N = size_t(1) << LOGN;
     return N * W * 8 * 2 + 3 * N * 16 + (N / 2) * sizeof(cx<R>) + 2 * N * 8;
 }
-#ifndef PINT_CQM_MAXLOG
-#define PINT_CQM_MAXLOG 3
-#endif
-template <typename R, int LOGN, int W, int NT>
+// MAXLOG: log2 of the largest radix of the length-N transforms (3 or 4).
+template <typename R, int LOGN, int W, int NT, int MAXLOG>
 __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchunk, int chunk) {
     using T = cx<R>;
     constexpr int N = 1 << LOGN;
@@ -1161,11 +1162,11 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 #pragma unroll
         for (int i = 0; i < PER; ++i) cbr[t + i * NT] = Uc[i];
         __syncthreads();
-        lds_fft<double, LOGN, B, NT, false, true, 0, 0, 2, PINT_CQM_MAXLOG>(buf, stw, t);
+        lds_fft<double, LOGN, B, NT, false, true, 0, 0, 2, MAXLOG>(buf, stw, t);
 #pragma unroll
         for (int j = 0; j < PC; ++j) buf[t + j * NT] = cmul(buf[t + j * NT], swe[(t + j * NT) / B]);
         __syncthreads();
-        lds_fft<double, LOGN, B, NT, true, true, 0, 0, 2, PINT_CQM_MAXLOG>(buf, stw, t);
+        lds_fft<double, LOGN, B, NT, true, true, 0, 0, 2, MAXLOG>(buf, stw, t);
         // park the even part; each lane overwrites its own element with z t_q
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -1177,11 +1178,11 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
         }
         __syncthreads();
         // odd points
-        lds_fft<double, LOGN, B, NT, false, true, 0, 0, 2, PINT_CQM_MAXLOG>(buf, stw, t);
+        lds_fft<double, LOGN, B, NT, false, true, 0, 0, 2, MAXLOG>(buf, stw, t);
 #pragma unroll
         for (int j = 0; j < PC; ++j) buf[t + j * NT] = cmul(buf[t + j * NT], swo[(t + j * NT) / B]);
         __syncthreads();
-        lds_fft<double, LOGN, B, NT, true, true, 0, 0, 2, PINT_CQM_MAXLOG>(buf, stw, t);
+        lds_fft<double, LOGN, B, NT, true, true, 0, 0, 2, MAXLOG>(buf, stw, t);
         // r = (G - A_h U^n - tau^{-alpha} c) kappa^{q/N}
         double r[PER];
 #pragma unroll
@@ -1205,7 +1206,7 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 #pragma unroll
         for (int i = 0; i < PER; ++i) smr[t + i * NT] = valid ? (R)r[i] : (R)0;
         __syncthreads();
-        lds_fft<R, LOGN, B, NT, false, true, 0, 0, 1, PINT_CQM_MAXLOG>(sm, stw1, t);
+        lds_fft<R, LOGN, B, NT, false, true, 0, 0, 1, MAXLOG>(sm, stw1, t);
         store_half_spectrum<R, N, B, NT, false>(sm, reinterpret_cast<T*>(a.S), a.ldS, (int)(slot0 + (long long)c * a.mxp),
                                                 a.Mp, t);
         __syncthreads();
@@ -1932,9 +1933,16 @@ constexpr int kNT = 256;
 #endif
 
 // Workgroups that fit on the whole device at once for a kernel (persistent
-// launches); cached per kernel.
+// launches), cached per kernel and lane count: the runtime is asked once, and
+// never again for a kernel that has been prepared, so a sweep recorded into a
+// graph makes no such query while its stream is capturing.
 int persistent_blocks(const void* fn, int nt) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
     static int cus = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = cache.find({fn, nt});
+    if (it != cache.end()) return it->second;
     if (cus == 0) {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -1943,8 +1951,18 @@ int persistent_blocks(const void* fn, int nt) {
     }
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, nt, 0) != hipSuccess || per <= 0) per = 1;
+    cache[{fn, nt}] = cus * per;
     return cus * per;
 }
+
+// Prepare-only mode (per host thread): the launchers make every runtime query
+// and attribute setting of a launch but launch nothing.  A batch runs one
+// prepared sweep of its instances before recording the sweep into a graph.
+thread_local bool g_prepare_only = false;
+#define PINT_LAUNCH(...)                                        \
+    do {                                                        \
+        if (!g_prepare_only) hipLaunchKernelGGL(__VA_ARGS__);   \
+    } while (0)
 #define N_OF(logn) (1 << (logn))
 // Lanes of the CQ forward kernel (512: the register budget of two waves per SIMD
 // holds a radix-16 FP64 butterfly beside the per-element partial sums).
@@ -1974,64 +1992,94 @@ hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
     nchunk = (nm + chunk - 1) / chunk;
     const int grid = ((ncol * nchunk + 7) / 8) * 8;
     if (nb) *nb = grid;
-    hipLaunchKernelGGL(kern(is3), dim3(grid), dim3(NT), 0, st, a, ncol, nchunk, chunk);
+    PINT_LAUNCH(kern(is3), dim3(grid), dim3(NT), 0, st, a, ncol, nchunk, chunk);
     return hipGetLastError();
+}
+
+// Which forward kernel a variant launches for this problem:
+//   BDF-k: 0 wide-tile march, 1 march, 2 one workgroup per tile;
+//   CQ: 0 y-march (radix <= 8), 1 y-march (radix <= 16), 2 persistent one-tile kernel.
+// A variant whose kernel does not apply falls back to the next one that does.
+template <typename R, int LOGN>
+int fwd_kind(const FwdArgs& a, bool cq) {
+    const int var = a.var < 0 || a.var >= kFwdVariants ? 0 : a.var;
+    if (cq) {
+        constexpr int WM = cqm_tile(LOGN);
+        if constexpr (cqm_lds<R, LOGN, WM>() <= 163840 && N_OF(LOGN) * WM >= 2 * PINT_CQ_NT) {
+            // 2D residual form: march along y (32-bit lane offsets, whole tiles per grid row)
+            if (var < 2 && a.form == 0 && a.my > 1 && a.mz == 1 && a.mxp % WM == 0 &&
+                (long long)(PINT_CQ_NT / WM + 2) * a.M * 8 < (1LL << 32))
+                return var;
+        }
+        return 2;
+    }
+    if (a.form != 0 || a.my == 1 || var == 2) return 2;
+    constexpr int W = fwd_tile(LOGN);
+    constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
+    constexpr int NTM = (N_OF(LOGN) * W >= PINT_MARCH_NT) ? PINT_MARCH_NT : NT;
+    constexpr int WW = 16;
+    constexpr int NTW = N_OF(LOGN) * WW < 512 ? N_OF(LOGN) * WW : 512;
+    constexpr bool WIDE_OK = LOGN <= 9 && PINT_FWD_WIDE;
+    // the marching kernels address with 32-bit byte offsets per lane
+    if (var == 0 && WIDE_OK && a.mz == 1 && WW <= a.mxp && (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32))
+        return 0;
+    if (W <= a.mxp && a.mxp % W == 0 && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32)) return 1;
+    return 2;
+}
+
+template <typename R, int LOGN, int MAXLOG>
+hipError_t fwd_cqm_launch(const FwdArgs& a, int* nb, hipStream_t st) {
+    constexpr int WM = cqm_tile(LOGN);
+    constexpr int NTM = PINT_CQ_NT;
+    if constexpr (cqm_lds<R, LOGN, WM>() <= 163840 && N_OF(LOGN) * WM >= 2 * PINT_CQ_NT) {
+        const void* fn = reinterpret_cast<const void*>(&k_fwd_cqm<R, LOGN, WM, NTM, MAXLOG>);
+        const int ncol = a.mxp / WM;
+        const int target = persistent_blocks(fn, NTM);
+        int nchunk = std::max(1, std::min(a.my, (target + ncol - 1) / ncol));
+        const int chunk = (a.my + nchunk - 1) / nchunk;
+        nchunk = (a.my + chunk - 1) / chunk;
+        const int grid = ((ncol * nchunk + 7) / 8) * 8;
+        if (nb) *nb = grid;
+        PINT_LAUNCH((k_fwd_cqm<R, LOGN, WM, NTM, MAXLOG>), dim3(grid), dim3(NTM), 0, st, a, ncol, nchunk, chunk);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 template <typename R, int LOGN>
 hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
+    const int kind = fwd_kind<R, LOGN>(a, cq);
     if (cq) {
+        if (kind == 0) return fwd_cqm_launch<R, LOGN, 3>(a, nb, st);
+        if (kind == 1) return fwd_cqm_launch<R, LOGN, 4>(a, nb, st);
         constexpr int W = cq_tile(LOGN);
-        constexpr int WM = cqm_tile(LOGN);
-        if constexpr (cqm_lds<R, LOGN, WM>() <= 163840 && N_OF(LOGN) * WM >= 2 * PINT_CQ_NT) {
-            constexpr int NTM = PINT_CQ_NT;
-            // 2D residual form: march along y (32-bit lane offsets, whole tiles per grid row)
-            if (a.form == 0 && a.my > 1 && a.mz == 1 && a.mxp % WM == 0 &&
-                (long long)(NTM / WM + 2) * a.M * 8 < (1LL << 32)) {
-                const void* fn = reinterpret_cast<const void*>(&k_fwd_cqm<R, LOGN, WM, NTM>);
-                const int ncol = a.mxp / WM;
-                const int target = persistent_blocks(fn, NTM);
-                int nchunk = std::max(1, std::min(a.my, (target + ncol - 1) / ncol));
-                const int chunk = (a.my + nchunk - 1) / nchunk;
-                nchunk = (a.my + chunk - 1) / chunk;
-                const int grid = ((ncol * nchunk + 7) / 8) * 8;
-                if (nb) *nb = grid;
-                hipLaunchKernelGGL((k_fwd_cqm<R, LOGN, WM, NTM>), dim3(grid), dim3(NTM), 0, st, a, ncol, nchunk, chunk);
-                return hipGetLastError();
-            }
-        }
-        const int ntiles = (a.Mp + W - 1) / W;
-        const int nvirt = ((ntiles + 7) / 8) * 8;
         constexpr int NT = cq_nt(LOGN);
         // per-lane byte offsets of the kernel's buffer loads are 32-bit
         if ((long long)(64 / W + 1) * a.M * 8 >= (1LL << 32)) return hipErrorInvalidValue;
+        const int ntiles = (a.Mp + W - 1) / W;
+        const int nvirt = ((ntiles + 7) / 8) * 8;
         const void* fn = reinterpret_cast<const void*>(&k_fwd_cq<R, LOGN, W, NT>);
         // a multiple of 8 workgroups, so workgroup b stays on XCD b mod 8 for all its tiles
         const int grid = std::min(nvirt, std::max(8, persistent_blocks(fn, NT) / 8 * 8));
         if (nb) *nb = grid;
-        hipLaunchKernelGGL((k_fwd_cq<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a, nvirt);
-    } else {
-        constexpr int W = fwd_tile(LOGN);
-        constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
-        // the marching kernel addresses with 32-bit byte offsets per lane
-        constexpr int NTM = (N_OF(LOGN) * W >= PINT_MARCH_NT) ? PINT_MARCH_NT : NT;
-        // wide tiles (2D): 16 slots (128-byte rows of FP64) for N <= 512, up to 512 lanes
-        constexpr int WW = 16;
-        constexpr int NTW = N_OF(LOGN) * WW < 512 ? N_OF(LOGN) * WW : 512;
-        constexpr bool WIDE_OK = LOGN <= 9 && PINT_FWD_WIDE;
-        if (a.form == 0 && a.my > 1) {
-            if constexpr (WIDE_OK)
-                if (a.mz == 1 && WW <= a.mxp && (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32))
-                    return fwd_march<R, LOGN, WW, NTW, true>(a, nb, st);
-            // the marching kernels address with 32-bit byte offsets per lane
-            if (W <= a.mxp && a.mxp % W == 0 && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32))
-                return fwd_march<R, LOGN, W, NTM, false>(a, nb, st);
-        }
-        const int ntiles = (a.Mp + W - 1) / W;
-        const int grid = ((ntiles + 7) / 8) * 8;
-        if (nb) *nb = grid;
-        hipLaunchKernelGGL((k_fwd_heat<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a);
+        PINT_LAUNCH((k_fwd_cq<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a, nvirt);
+        return hipGetLastError();
     }
+    constexpr int W = fwd_tile(LOGN);
+    constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
+    constexpr int NTM = (N_OF(LOGN) * W >= PINT_MARCH_NT) ? PINT_MARCH_NT : NT;
+    constexpr int WW = 16;
+    constexpr int NTW = N_OF(LOGN) * WW < 512 ? N_OF(LOGN) * WW : 512;
+    if (kind == 0) {
+        if constexpr (LOGN <= 9 && PINT_FWD_WIDE) return fwd_march<R, LOGN, WW, NTW, true>(a, nb, st);
+        return hipErrorInvalidValue;
+    }
+    if (kind == 1) return fwd_march<R, LOGN, W, NTM, false>(a, nb, st);
+    const int ntiles = (a.Mp + W - 1) / W;
+    const int grid = ((ntiles + 7) / 8) * 8;
+    if (nb) *nb = grid;
+    PINT_LAUNCH((k_fwd_heat<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -2042,7 +2090,7 @@ hipError_t inv_one(const InvArgs& a, int* nb, hipStream_t st) {
     const int grid = ((ntiles + 7) / 8) * 8;
     if (nb) *nb = grid;
     constexpr int NT = (N_OF(LOGN) * W >= PINT_INV_NT) ? PINT_INV_NT : kNT;
-    hipLaunchKernelGGL((k_inv<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a);
+    PINT_LAUNCH((k_inv<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -2088,37 +2136,52 @@ hipError_t tri1d_one(const SpaceArgs& a, hipStream_t st) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_tri1d<R, EPT, NT>), dim3(a.nP), dim3(NT), lds, st, a);
+    PINT_LAUNCH((k_tri1d<R, EPT, NT>), dim3(a.nP), dim3(NT), lds, st, a);
     return hipGetLastError();
 }
 
+// Split of a 1D system of size m between PCR (NT lanes) and Thomas (EPT
+// equations per lane): the built-in choice, and with var_tri = 1 one with
+// more PCR lanes (fewer Thomas equations), where that differs.
 template <typename R>
 hipError_t tri1d_dispatch(const SpaceArgs& a, hipStream_t st) {
     const int m = a.mx;
+    const bool alt = a.var_tri == 1;
     if (m <= 64) return tri1d_one<R, 1, 64>(a, st);
-    if (m <= 128) return tri1d_one<R, 2, 64>(a, st);
-    if (m <= 256) return tri1d_one<R, 4, 64>(a, st);
-    if (m <= 512) return tri1d_one<R, 8, 64>(a, st);
-    if (m <= 1024) return tri1d_one<R, 4, 256>(a, st);
-    if (m <= 2048) return tri1d_one<R, 8, 256>(a, st);
+    if (m <= 128) return alt ? tri1d_one<R, 1, 128>(a, st) : tri1d_one<R, 2, 64>(a, st);
+    if (m <= 256) return alt ? tri1d_one<R, 1, 256>(a, st) : tri1d_one<R, 4, 64>(a, st);
+    if (m <= 512) return alt ? tri1d_one<R, 2, 256>(a, st) : tri1d_one<R, 8, 64>(a, st);
+    if (m <= 1024) return alt ? tri1d_one<R, 2, 512>(a, st) : tri1d_one<R, 4, 256>(a, st);
+    if (m <= 2048) return alt ? tri1d_one<R, 4, 512>(a, st) : tri1d_one<R, 8, 256>(a, st);
     return hipErrorInvalidValue;
 }
 
-template <typename R, int LOGL, bool SOLVE>
-hipError_t rows_one(const SpaceArgs& a, hipStream_t st) {
-    constexpr int ROWS = rows_per_block<R>(LOGL);
+// Rows per workgroup of the x pass: the built-in count, or half of it (var_rows = 1).
+template <typename R> constexpr int rows_alt(int logl) {
+    const int r = rows_per_block<R>(logl);
+    return r >= 2 ? r / 2 : r;
+}
+// Columns per workgroup of the y/z pass: the built-in width, or (var_cols = 1)
+// twice it when the tile still fits 128 KB of LDS and 32 columns, else half.
+template <typename R> constexpr int cols_alt(int logl) {
+    const int w = cols_per_block<R>(logl);
+    if (2 * w <= 32 && (1 << logl) * 2 * w * (int)sizeof(cx<R>) <= 131072) return 2 * w;
+    return w >= 2 ? w / 2 : w;
+}
+
+template <typename R, int LOGL, int ROWS, bool SOLVE>
+hipError_t rows_run(const SpaceArgs& a, hipStream_t st) {
     constexpr int NT = kNT;
     const long long nlines = (long long)a.nP * a.my * a.mz;
     const long long groups = (nlines + ROWS - 1) / ROWS;
     const long long grid = std::min<long long>(groups, persistent_blocks(reinterpret_cast<const void*>(
                                                            &k_dst_rows<R, LOGL, ROWS, NT, SOLVE>), NT));
-    hipLaunchKernelGGL((k_dst_rows<R, LOGL, ROWS, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, nlines);
+    PINT_LAUNCH((k_dst_rows<R, LOGL, ROWS, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, nlines);
     return hipGetLastError();
 }
 
-template <typename R, int LOGL, bool SOLVE>
-hipError_t cols_one(const SpaceArgs& a, int axis, hipStream_t st) {
-    constexpr int W = cols_per_block<R>(LOGL);
+template <typename R, int LOGL, int W, bool SOLVE>
+hipError_t cols_run(const SpaceArgs& a, int axis, hipStream_t st) {
     // tiles above 64 KB of LDS get 512 lanes so the FFT stages stay in registers
     // (FP64 tiles of 64 KB as well: measured faster with 8 waves per workgroup)
     constexpr int NT = ((1 << LOGL) * W * (int)sizeof(cx<R>) > 65536 || sizeof(R) == 8) ? 512 : kNT;
@@ -2126,8 +2189,22 @@ hipError_t cols_one(const SpaceArgs& a, int axis, hipStream_t st) {
     const long long groups = (long long)a.nP * other * ((a.mx + W - 1) / W);
     const long long grid = std::min<long long>(
         groups, persistent_blocks(reinterpret_cast<const void*>(&k_dst_cols<R, LOGL, W, NT, SOLVE>), NT));
-    hipLaunchKernelGGL((k_dst_cols<R, LOGL, W, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, axis);
+    PINT_LAUNCH((k_dst_cols<R, LOGL, W, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, axis);
     return hipGetLastError();
+}
+
+template <typename R, int LOGL, bool SOLVE>
+hipError_t rows_one(const SpaceArgs& a, hipStream_t st) {
+    if (a.var_rows == 1 && rows_alt<R>(LOGL) != rows_per_block<R>(LOGL))
+        return rows_run<R, LOGL, rows_alt<R>(LOGL), SOLVE>(a, st);
+    return rows_run<R, LOGL, rows_per_block<R>(LOGL), SOLVE>(a, st);
+}
+
+template <typename R, int LOGL, bool SOLVE>
+hipError_t cols_one(const SpaceArgs& a, int axis, hipStream_t st) {
+    if (a.var_cols == 1 && cols_alt<R>(LOGL) != cols_per_block<R>(LOGL))
+        return cols_run<R, LOGL, cols_alt<R>(LOGL), SOLVE>(a, axis, st);
+    return cols_run<R, LOGL, cols_per_block<R>(LOGL), SOLVE>(a, axis, st);
 }
 
 template <typename R, bool SOLVE = false>
@@ -2195,7 +2272,7 @@ hipError_t blue_one(const SpaceArgs& a, int axis, hipStream_t st) {
     const long long groups = (nlines + B - 1) / B;
     const long long grid = std::min<long long>(
         groups, persistent_blocks(reinterpret_cast<const void*>(&k_dst_blue<R, LOGP, B, NT, SOLVE>), NT));
-    hipLaunchKernelGGL((k_dst_blue<R, LOGP, B, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, axis, nlines);
+    PINT_LAUNCH((k_dst_blue<R, LOGP, B, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, axis, nlines);
     return hipGetLastError();
 }
 
@@ -2242,14 +2319,14 @@ hipError_t launch_prep(const double* v, const double* f, const double* fder, dou
                        const double* b_lt, int k, int M, int mx, int my, int mz, double ihx2, double ihy2,
                        double ihz2, hipStream_t st) {
     if (k < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_prep, dim3((M + 255) / 256), dim3(256), 0, st, v, f, fder, corr, a_n, b_lt, k, M, mx, my, mz,
+    PINT_LAUNCH(k_prep, dim3((M + 255) / 256), dim3(256), 0, st, v, f, fder, corr, a_n, b_lt, k, M, mx, my, mz,
                        ihx2, ihy2, ihz2);
     return hipGetLastError();
 }
 
 hipError_t launch_fill(double* U, const double* v, long long N, int M, int zero, hipStream_t st) {
     const long long total = N * M;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, U, v, total, M, zero);
+    PINT_LAUNCH(k_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, U, v, total, M, zero);
     return hipGetLastError();
 }
 
@@ -2261,9 +2338,9 @@ hipError_t launch_inject(const FwdArgs& a, const void* Sg, bool mixed, hipStream
     const int pchunk = 16;
     const dim3 grid((unsigned)((a.Mp + 255) / 256), (unsigned)((a.N / 2 + 1 + pchunk - 1) / pchunk));
     if (mixed)
-        hipLaunchKernelGGL(k_inject<float>, grid, dim3(256), 0, st, a, Sg, pchunk);
+        PINT_LAUNCH(k_inject<float>, grid, dim3(256), 0, st, a, Sg, pchunk);
     else
-        hipLaunchKernelGGL(k_inject<double>, grid, dim3(256), 0, st, a, Sg, pchunk);
+        PINT_LAUNCH(k_inject<double>, grid, dim3(256), 0, st, a, Sg, pchunk);
     return hipGetLastError();
 }
 
@@ -2287,9 +2364,81 @@ hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st) {
     return hipSuccess;
 }
 
+void set_prepare_only(bool on) { g_prepare_only = on; }
+
 hipError_t launch_norm_reduce(const double* partial, int nb, double hd, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(256), 0, st, partial, nb, hd, out);
+    PINT_LAUNCH(k_norm_reduce, dim3(1), dim3(256), 0, st, partial, nb, hd, out);
     return hipGetLastError();
 }
+
+namespace {
+template <typename R>
+int fwd_kind_of(const FwdArgs& a, bool cq) {
+    switch (__builtin_ctz((unsigned)a.N)) {
+        case 3: return fwd_kind<R, 3>(a, cq);
+        case 4: return fwd_kind<R, 4>(a, cq);
+        case 5: return fwd_kind<R, 5>(a, cq);
+        case 6: return fwd_kind<R, 6>(a, cq);
+        case 7: return fwd_kind<R, 7>(a, cq);
+        case 8: return fwd_kind<R, 8>(a, cq);
+        case 9: return fwd_kind<R, 9>(a, cq);
+        case 10: return fwd_kind<R, 10>(a, cq);
+        case 11: return fwd_kind<R, 11>(a, cq);
+        default: return -1;
+    }
+}
+template <typename R>
+bool rows_distinct(int logl) {
+    if (logl < kMinLogL || logl > kMaxLogL) return false;
+    static const bool d[] = {false, false,
+                             rows_alt<R>(2) != rows_per_block<R>(2), rows_alt<R>(3) != rows_per_block<R>(3),
+                             rows_alt<R>(4) != rows_per_block<R>(4), rows_alt<R>(5) != rows_per_block<R>(5),
+                             rows_alt<R>(6) != rows_per_block<R>(6), rows_alt<R>(7) != rows_per_block<R>(7),
+                             rows_alt<R>(8) != rows_per_block<R>(8), rows_alt<R>(9) != rows_per_block<R>(9),
+                             rows_alt<R>(10) != rows_per_block<R>(10), rows_alt<R>(11) != rows_per_block<R>(11),
+                             rows_alt<R>(12) != rows_per_block<R>(12)};
+    return d[logl];
+}
+template <typename R>
+bool cols_distinct(int logl) {
+    if (logl < kMinLogL || logl > kMaxLogL) return false;
+    static const bool d[] = {false, false,
+                             cols_alt<R>(2) != cols_per_block<R>(2), cols_alt<R>(3) != cols_per_block<R>(3),
+                             cols_alt<R>(4) != cols_per_block<R>(4), cols_alt<R>(5) != cols_per_block<R>(5),
+                             cols_alt<R>(6) != cols_per_block<R>(6), cols_alt<R>(7) != cols_per_block<R>(7),
+                             cols_alt<R>(8) != cols_per_block<R>(8), cols_alt<R>(9) != cols_per_block<R>(9),
+                             cols_alt<R>(10) != cols_per_block<R>(10), cols_alt<R>(11) != cols_per_block<R>(11),
+                             cols_alt<R>(12) != cols_per_block<R>(12)};
+    return d[logl];
+}
+int log2_of_pow2(unsigned v) { return (v & (v - 1)) == 0 ? __builtin_ctz(v) : -1; }
+}  // namespace
+
+bool forward_variant_distinct(const FwdArgs& a, bool mixed, bool cq, int var) {
+    FwdArgs b = a, c = a;
+    b.var = 0;
+    c.var = var;
+    return mixed ? fwd_kind_of<float>(b, cq) != fwd_kind_of<float>(c, cq)
+                 : fwd_kind_of<double>(b, cq) != fwd_kind_of<double>(c, cq);
+}
+
+bool rows_variant_distinct(const SpaceArgs& a, bool mixed) {
+    const bool has_rows = a.dim == 1 ? dst1d(a) : a.logP[0] == 0;
+    if (!has_rows) return false;
+    const int logl = log2_of_pow2(2u * (unsigned)(a.mx + 1));
+    return mixed ? rows_distinct<float>(logl) : rows_distinct<double>(logl);
+}
+
+bool cols_variant_distinct(const SpaceArgs& a, bool mixed) {
+    for (int axis = 1; axis < a.dim; ++axis) {
+        if (a.logP[axis] != 0) continue;
+        const int m = axis == 1 ? a.my : a.mz;
+        const int logl = log2_of_pow2(2u * (unsigned)(m + 1));
+        if (mixed ? cols_distinct<float>(logl) : cols_distinct<double>(logl)) return true;
+    }
+    return false;
+}
+
+bool tri_variant_distinct(const SpaceArgs& a) { return a.dim == 1 && !dst1d(a) && a.mx > 64 && a.mx <= kMaxTri1D; }
 
 }  // namespace pint

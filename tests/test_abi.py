@@ -78,3 +78,12 @@ def test_batch_rejects_unsupported_instance():
     st = B.lib().pint_batch_plan_create(ctypes.byref(h), 2, G, Pm, None)
     assert st == B.PINT_E_UNSUPPORTED
     assert b"instance 1" in B.lib().pint_last_error()
+
+
+def test_autotune_entry_points_reject_bad_arguments():
+    L = B.lib()
+    c = (ctypes.c_int * 4)()
+    assert L.pint_plan_set_autotune(None, 3) == B.PINT_E_ARG
+    assert L.pint_plan_tune(None, None, 3) == B.PINT_E_ARG
+    assert L.pint_plan_get_variants(None, 0, c) == B.PINT_E_ARG
+    assert L.pint_plan_set_variants(None, 0, c) == B.PINT_E_ARG

@@ -1,0 +1,124 @@
+"""Kernel variants and the autotuner that chooses between them (through the C
+ABI): every variant of every knob, pinned with pint_plan_set_variants, gives a
+converged trajectory within the parity bar of the FP64 sequential oracle, and
+an autotuned solve picks valid variants and meets the same bar."""
+import numpy as np
+import pytest
+
+from paper_2007_13125_amd import workloads as wl
+from tests.gpu_util import oracle_solution, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# dim, m, N, k, alpha, kappa: each exercises a knob with distinct kernels
+CASES = [
+    (2, (63, 15), 128, 5, 1.0, 1e-3),    # forward: wide march / march / one tile; x and y passes
+    (2, (31, 15), 512, 4, 1.0, 1e-4),    # the same at N = 512 (the benchmark's time length)
+    (3, (15, 7, 3), 256, 3, 1.0, 1e-3),  # 3D march along z / one tile; y and z passes
+    (2, (61, 9), 256, 3, 0.5, 1e-3),     # CQ: y-march radix 8 / radix 16 / persistent one tile
+    (1, (200,), 16, 2, 1.0, 1e-2),       # 1D PCR/Thomas split
+    (1, (255,), 64, 2, 1.0, 1e-3),       # 1D sine-transform solve: rows per workgroup
+]
+KNOB_VALUES = [(0, 1), (0, 2), (1, 1), (2, 1), (3, 1)]
+
+
+def _case(dim, m, N, k, alpha, kappa):
+    if dim == 1:
+        w = wl.heat1d(seed=3, m=m[0], N=N, k=k, kappa=kappa)
+    elif dim == 2:
+        w = wl.heat2d(seed=3, m=m, N=N, k=k, kappa=kappa)
+    else:
+        w = wl.heat3d(seed=3, m=m, N=N, k=k, kappa=kappa)
+    w.alpha = alpha
+    return w
+
+
+def _solve(w, precision, variants=None, autotune=0):
+    import torch
+
+    from paper_2007_13125_amd.binding import Plan
+    print(f"[gpu] autotune case {w.name} m={w.m} N={w.N} alpha={w.alpha} {precision} "
+          f"variants={variants} autotune={autotune}", flush=True)
+    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-14, max_sweeps=40, precision=precision)
+    if variants is not None:
+        plan.set_variants(variants)
+    if autotune:
+        plan.set_autotune(autotune)
+    U, info = plan.solve(to_dev(w.v), to_dev(w.f), to_dev(w.fder))
+    torch.cuda.synchronize()
+    chosen = plan.variants()
+    out = U.cpu().numpy()
+    plan.close()
+    return out, info, chosen
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("knob,value", KNOB_VALUES)
+def test_every_variant_matches_oracle(case, knob, value):
+    w = _case(*case)
+    ref = oracle_solution(w)
+    v = [0, 0, 0, 0]
+    v[knob] = value
+    U, info, chosen = _solve(w, "fp64", variants=v)
+    assert chosen == v
+    err = rel_l2(U, ref)
+    assert info["status"] == 0 and err <= 1e-11, (err, info)
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotuned_solve_matches_oracle(case, precision):
+    w = _case(*case)
+    ref = oracle_solution(w)
+    U, info, chosen = _solve(w, precision, autotune=2)
+    assert len(chosen) == 4 and 0 <= chosen[0] <= 2 and all(c in (0, 1) for c in chosen[1:]), chosen
+    err = rel_l2(U, ref)
+    bar = 1e-11 if precision == "fp64" else 1e-10
+    assert info["status"] == 0 and err <= bar, (err, info, chosen)
+
+
+def test_tune_after_bind_and_variant_errors():
+    import torch
+
+    from paper_2007_13125_amd.binding import Plan, PintError
+    w = _case(2, (63, 15), 128, 5, 1.0, 1e-3)
+    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-14, max_sweeps=40)
+    U = torch.zeros((w.N, w.M), dtype=torch.float64, device="cuda")
+    with pytest.raises(PintError):
+        plan.tune(U, 2)                       # not bound yet
+    plan.bind(to_dev(w.v), to_dev(w.f), to_dev(w.fder))
+    plan.init_iterate(U)
+    chosen = plan.tune(U, 2)
+    assert 0 <= chosen[0] <= 2 and all(c in (0, 1) for c in chosen[1:]), chosen
+    with pytest.raises(PintError):
+        plan.set_variants([3, 0, 0, 0])
+    with pytest.raises(PintError):
+        plan.set_variants([0, 2, 0, 0])
+    plan.sweeps(U, 3)                        # tuned plan sweeps normally
+    torch.cuda.synchronize()
+    assert np.isfinite(U.cpu().numpy()).all()
+    plan.close()
+
+
+def test_batch_autotune_each_instance():
+    import torch
+
+    from paper_2007_13125_amd import binding as B
+    cases = [CASES[0], CASES[3], CASES[4]]
+    ws = [_case(*c) for c in cases]
+    grids = [B.make_grid(w.m) for w in ws]
+    params = [B.make_params(w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-14, max_sweeps=40) for w in ws]
+    print(f"[gpu] batch autotune {[w.m for w in ws]}", flush=True)
+    h = B.pint_batch_plan_create(grids, params)
+    B.pint_plan_set_autotune(h, 2)
+    Us = [torch.empty((w.N, w.M), dtype=torch.float64, device="cuda") for w in ws]
+    st, upd, sw = B.pint_batch_solve(h, [to_dev(w.v) for w in ws], [to_dev(w.f) for w in ws],
+                                     [to_dev(w.fder) for w in ws], Us, 40)
+    torch.cuda.synchronize()
+    assert st == B.PINT_OK
+    for i, w in enumerate(ws):
+        chosen = B.pint_plan_get_variants(h, i)
+        assert 0 <= chosen[0] <= 2 and all(c in (0, 1) for c in chosen[1:]), chosen
+        err = rel_l2(Us[i].cpu().numpy(), oracle_solution(w))
+        assert err <= 1e-11, (i, err)
+    B.pint_plan_destroy(h)

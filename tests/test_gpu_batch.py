@@ -53,10 +53,6 @@ def test_batch_matches_single_solves_and_oracle():
         assert rel_l2(got, ref) <= (1e-11 if p == "fp64" else 1e-10), i
 
 
-@pytest.mark.skip(reason="the host Python process ended with a segmentation fault right after this batch "
-                         "returned (inside the binding's result list); the host logic ran clean under "
-                         "AddressSanitizer on the CPU with stubbed HIP calls, the cause is not found yet, so "
-                         "the case stays off the GPU until it is")
 def test_batch_of_random_instances_any_grid_size():
     # The many-instance recipe (dim, m, N, k, alpha, kappa all drawn per instance;
     # 2D sizes are arbitrary, so most 2D instances take the Bluestein sine transforms),
