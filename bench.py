@@ -58,7 +58,7 @@ def measured_traffic(precision, kernel):
         return None
 
 
-def run_precision(w, precision, steps, warmup, form="residual"):
+def run_precision(w, precision, steps, warmup, form="residual", tune=True):
     import torch
 
     from paper_2007_13125_amd.binding import Plan
@@ -70,6 +70,9 @@ def run_precision(w, precision, steps, warmup, form="residual"):
     plan.bind(v, f, fd)
     U = torch.empty((w.N, w.M), dtype=torch.float64, device=dev)
     plan.init_iterate(U)
+    # kernel variants chosen by the library's autotuner (plan setup, outside the timed region)
+    variants = plan.tune(U, 3) if tune else plan.variants()
+    plan.init_iterate(U)
     if warmup:
         plan.sweeps(U, warmup)
     torch.cuda.synchronize()
@@ -78,7 +81,7 @@ def run_precision(w, precision, steps, warmup, form="residual"):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) / steps * 1e3
-    return plan, (v, f, fd), ms_per_step, prof
+    return plan, (v, f, fd), ms_per_step, prof, variants
 
 
 def time_to_tol(w, plan, data, Uref, tol=1e-10, max_sweeps=12):
@@ -211,7 +214,11 @@ def summarize(outdir):
               f"Calibration: a plain {COPY_BYTES >> 20} MiB device copy read FETCH_SIZE = {fcal:.0f} KiB and "
               f"WRITE_SIZE = {wcal:.0f} KiB, so HBM read bytes = {rf:.3f} x FETCH_SIZE KiB x 1024 and write "
               f"bytes = {wf:.3f} x WRITE_SIZE KiB x 1024.", "",
+              "Kernels with few dispatches are the autotuner's trial launches of the variants not chosen.", "",
               "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | write MB |", "|---|---|---|---|---|"]
+    # the autotuner also launches the other variants of a slot a few times: the
+    # record keeps, per slot, the kernel with the most dispatches (the timed one)
+    calls = {}
     for k, vals in counters["FETCH_SIZE"].items():
         slot = slot_of(k)
         if slot is None:
@@ -220,7 +227,9 @@ def summarize(outdir):
         wk = sum(counters["WRITE_SIZE"][k]) / len(counters["WRITE_SIZE"][k])
         rd, wr = rf * fk * 1024, wf * wk * 1024
         prec = "mixed" if "<float" in k else "fp64"
-        rec["kernels"][prec][slot] = {"read": rd, "write": wr}
+        if len(vals) > calls.get((prec, slot), 0):
+            calls[(prec, slot)] = len(vals)
+            rec["kernels"][prec][slot] = {"read": rd, "write": wr, "kernel": short(k), "dispatches": len(vals)}
         lines.append(f"| `{short(k)}` | {fk:.4g} | {wk:.4g} | {rd / 1e6:.1f} | {wr / 1e6:.1f} |")
     open(PROFILE_STEM + "_kernels.md", "w").write("\n".join(lines) + "\n")
     json.dump(rec, open(PROFILE_STEM + "_traffic.json", "w"), indent=1)
@@ -233,6 +242,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel variants (no autotuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 256 MiB on the device (counter calibration for profiles)")
     ap.add_argument("--summarize", metavar="DIR",
@@ -256,7 +266,7 @@ def main():
     out = {}
     plans = {}
     for precision in ("fp64", "mixed"):
-        plan, data, ms, prof = run_precision(w, precision, args.steps, args.warmup)
+        plan, data, ms, prof, var = run_precision(w, precision, args.steps, args.warmup, tune=not args.no_tune)
         mixed = precision == "mixed"
         kern = {name: ms_k for name, ms_k in prof}
         sweep_bytes = sum(kernel_bytes(n, N, M, mixed, has_f) for n, _ in prof)
@@ -268,6 +278,7 @@ def main():
             "sweep_alg_bytes": sweep_bytes,
             "sweep_hbm_frac": sweep_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "dominant": {"kernel": dom[0], "ms": dom[1], "bytes": dom_bytes, "GBps": achieved},
+            "variants": var,
         }
         plans[precision] = (plan, data)
     # reference trajectory for time-to-1e-10: the FP64 path converged to 1e-14
@@ -278,7 +289,8 @@ def main():
     plan64.sweeps(Uref, 8)
     torch.cuda.synchronize()
     # the paper's direct form in FP64 (its roundoff floor, ~eps/kappa ~ 6e-12 here, is below 1e-10)
-    pd, dd, ms_d, prof_d = run_precision(w, "fp64", args.steps, args.warmup, form="direct")
+    pd, dd, ms_d, prof_d, var_d = run_precision(w, "fp64", args.steps, args.warmup, form="direct",
+                                                tune=not args.no_tune)
     plans["fp64_direct"] = (pd, dd)
     ttt = {p: time_to_tol(w, plans[p][0], plans[p][1], Uref) for p in ("fp64", "fp64_direct", "mixed")}
 
@@ -305,6 +317,8 @@ def main():
                      "traffic": measured_traffic("fp64", d["kernel"]), "alg_bytes": d["bytes"]},
         "kernels_ms": out["fp64"]["kernels_ms"],
         "sweep_hbm_frac": out["fp64"]["sweep_hbm_frac"],
+        "variants": {"fp64": out["fp64"]["variants"], "mixed": out["mixed"]["variants"], "fp64_direct": var_d,
+                     "knobs": ["forward kernel", "x pass rows", "y pass columns", "1D tridiagonal split"]},
         "mixed": {k: out["mixed"][k] for k in ("value", "ms_per_step", "kernels_ms", "sweep_hbm_frac",
                                                "dominant")},
         "time_to_1e-10": {p: {"sweeps": ttt[p]["sweeps"], "ms": ttt[p]["ms"]} for p in ttt},

@@ -186,9 +186,11 @@ pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const doub
  *   [2] column tile of the y/z passes: 0 built-in, 1 the other width;
  *   [3] 1D tridiagonal systems: 0 built-in split, 1 more PCR lanes.
  * Tuning times every value of a knob that launches a different kernel for the
- * problem, reps times each, on the plan's own workspace (the forward kernels
- * read U, nothing writes it), and keeps the fastest.  It synchronises the
- * plan's stream.  Results are unchanged up to rounding by the choice.
+ * problem (reps launches, in three interleaved rounds, best round kept) on the
+ * plan's own workspace (the forward kernels read U, nothing writes it), and
+ * keeps the fastest; a value other than 0 must be at least 3% faster than the
+ * built-in one.  It synchronises the plan's stream.  Results are unchanged up
+ * to rounding by the choice.
  *
  * pint_plan_set_autotune: reps > 0 makes pint_solve (pint_batch_solve: every
  * instance) tune once, after binding and the initial iterate, before its first

@@ -647,23 +647,31 @@ pint_status tune_plan(pint_plan* P, const double* U, int reps) {
     HIP_TRY(hipEventCreate(&t.a));
     HIP_TRY(hipEventCreate(&t.b));
     pint_status rc;
-    // pick the fastest of the candidate values of knob k (value 0 always included)
+    // Fastest candidate value of knob k (cand[0] = 0, the built-in choice): the
+    // candidates are timed in three interleaved rounds (so a clock ramp does not
+    // favour the later ones) and each keeps its best round; another value
+    // replaces the built-in one only when it is at least 3% faster.
     auto pick = [&](int k, const std::vector<int>& cand, auto&& launch) -> pint_status {
-        float best = 0.0f;
-        int arg = 0;
-        for (size_t c = 0; c < cand.size(); ++c) {
-            P->var[k] = cand[c];
-            float ms = 0.0f;
-            pint_status r = time_launches(P, t, reps, launch, &ms);
-            if (r != PINT_OK) {
-                P->var[k] = 0;
-                return r;
-            }
-            if (c == 0 || ms < best) {
-                best = ms;
-                arg = cand[c];
+        std::vector<float> best(cand.size(), 0.0f);
+        for (int round = 0; round < 3; ++round) {
+            for (size_t c = 0; c < cand.size(); ++c) {
+                P->var[k] = cand[c];
+                float ms = 0.0f;
+                pint_status r = time_launches(P, t, reps, launch, &ms);
+                if (r != PINT_OK) {
+                    P->var[k] = 0;
+                    return r;
+                }
+                if (round == 0 || ms < best[c]) best[c] = ms;
             }
         }
+        int arg = 0;
+        float bt = best[0];
+        for (size_t c = 1; c < cand.size(); ++c)
+            if (best[c] < 0.97f * best[0] && best[c] < bt) {
+                bt = best[c];
+                arg = cand[c];
+            }
         P->var[k] = arg;
         return PINT_OK;
     };
