@@ -154,21 +154,20 @@ pint_status pint_solve(pint_plan *plan, const double *v, const double *f, const 
 
 /* Many independent problems in one plan (each instance with its own grid and
  * params; N, k, alpha, precision may all differ).  Every instance is validated
- * as in pint_plan_create and gets its own tables and workspace.  One sweep of
- * all instances still iterating is recorded once into a HIP graph, forked over
- * up to 8 streams of default priority so that small instances run
- * concurrently, and replayed each sweep; the graph is re-recorded only when an
- * instance stops.  count >= 1; grids/params are HOST arrays of count entries.
- * Errors: as pint_plan_create (the message names the instance). */
+ * as in pint_plan_create and gets its own tables and workspace.  The instances
+ * are solved one after another on the plan's stream through the single-plan
+ * path (the graph-replayed batch sweep is switched off: it ended the host
+ * process with an unexplained crash).  count >= 1; grids/params are HOST arrays
+ * of count entries.  Errors: as pint_plan_create (the message names the
+ * instance). */
 pint_status pint_batch_plan_create(pint_plan **plan, int count, const pint_grid *grids,
                                    const pint_params *params, void *hip_stream);
 
 /* Batch solve.  v, f, fder, U: HOST arrays of count DEVICE pointers with the
  * meaning of pint_solve (f and fder entries, or the f/fder arrays themselves,
  * may be NULL).  upd: HOST [count][S] with S the largest max_sweeps of the
- * instances (may be NULL); sweeps: HOST [count] (may be NULL).  After each
- * replay the per-instance norms come back in one copy; an instance stops at its
- * own tol, max_sweeps or divergence and is left untouched afterwards.
+ * instances (may be NULL); sweeps: HOST [count] (may be NULL).  Each instance
+ * stops at its own tol, max_sweeps or divergence.
  * Returns PINT_OK if every instance converged, PINT_NOT_CONVERGED if one hit
  * max_sweeps, PINT_E_DIVERGED if one diverged (the others still finish). */
 pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const double *const *f,
@@ -177,8 +176,9 @@ pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const doub
 /* Autotuning of the kernels' tile and split choices (the batching row of the
  * method's GPU mapping: FFT radix and tile shapes, PCR/Thomas split).  Four
  * knobs, each 0 = the built-in choice:
- *   [0] forward kernel: BDF-k residual 2D/3D sweeps 0 wide-tile march,
- *       1 march with the time-FFT tile, 2 one workgroup per tile; CQ sweeps
+ *   [0] forward kernel: BDF-k residual 2D/3D sweeps 0 wide-tile march along
+ *       the outer axis, 1 march with the time-FFT tile, 2 one workgroup per
+ *       tile; CQ sweeps
  *       0 y-march with radix <= 8 transforms, 1 y-march with radix <= 16,
  *       2 persistent one-tile-at-a-time kernel (a choice that does not apply
  *       to the problem falls back to the next one that does);

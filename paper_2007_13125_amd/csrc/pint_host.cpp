@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -1006,6 +1007,13 @@ pint_status pint_batch_plan_create(pint_plan** plan, int count, const pint_grid*
 
 namespace {
 
+// Batch sweeps recorded into one HIP graph and replayed (below) are switched
+// off: runs of that path twice ended the host process with a segmentation
+// fault inside pint_batch_solve whose cause has not been found.  With the
+// switch off, pint_batch_solve solves the instances one after another through
+// the single-plan path (same kernels, same results, no graph, no fork streams).
+constexpr bool kBatchGraph = false;
+
 // Record one sweep of every active instance into a HIP graph: the instances
 // are forked over the lane streams (instance i on lane i mod lanes) and joined
 // back on the plan's stream, so independent instances may run concurrently.
@@ -1060,6 +1068,31 @@ pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double*
                              double* const* U, double* upd, int* sweeps) {
     if (!P || P->inst.empty() || !v || !U) return fail(PINT_E_ARG, "bad arguments to pint_batch_solve");
     const int count = (int)P->inst.size();
+    if (!kBatchGraph) {
+        // Instances solved one after another through the single-plan path.
+        int smax = 0;
+        for (int i = 0; i < count; ++i) {
+            if (!v[i] || !U[i]) return fail(PINT_E_ARG, "instance " + std::to_string(i) + ": NULL v or U");
+            smax = std::max(smax, P->inst[i]->p.max_sweeps);
+        }
+        pint_status result = PINT_OK;
+        for (int i = 0; i < count; ++i) {
+            pint_plan* Q = P->inst[i];
+            Q->tune_reps = P->tune_reps;
+            int done = 0;
+            const pint_status rc = pint_solve(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr, U[i],
+                                              upd ? upd + (size_t)i * smax : nullptr, nullptr, &done);
+            if (sweeps) sweeps[i] = done;
+            if (rc == PINT_E_DIVERGED) {
+                result = rc;
+            } else if (rc == PINT_NOT_CONVERGED) {
+                if (result == PINT_OK) result = rc;
+            } else if (rc != PINT_OK) {
+                return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+            }
+        }
+        return result;
+    }
     int max_sw = 0;
     for (int i = 0; i < count; ++i) {
         if (!v[i] || !U[i]) return fail(PINT_E_ARG, "instance " + std::to_string(i) + ": NULL v or U");

@@ -73,8 +73,8 @@ struct SpaceArgs {
 };
 
 // Kernel variants the autotuner chooses between (index 0 is the built-in choice).
-//   forward, BDF-k residual 2D/3D: 0 wide-tile march when eligible (else 1),
-//     1 march with the time-FFT tile, 2 one workgroup per tile;
+//   forward, BDF-k residual 2D/3D: 0 wide-tile march along the outer axis when
+//     eligible (else 1), 1 march with the time-FFT tile, 2 one workgroup per tile;
 //   forward, CQ: 0 y-march with radix <= 8 transforms when eligible (else 2),
 //     1 y-march with radix <= 16, 2 persistent one-tile-at-a-time kernel.
 constexpr int kFwdVariants = 3;

@@ -1980,7 +1980,7 @@ template <typename R, int LOGN, int W, int NT, bool WIDE>
 hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
     const bool is3 = a.mz > 1;
     auto kern = [](bool three) {
-        if constexpr (WIDE) return (void)three, &k_fwd_wide<R, LOGN, W, NT, false>;   // 2D only
+        if constexpr (WIDE) return three ? &k_fwd_wide<R, LOGN, W, NT, true> : &k_fwd_wide<R, LOGN, W, NT, false>;
         else return three ? &k_fwd_march<R, LOGN, W, NT, true> : &k_fwd_march<R, LOGN, W, NT, false>;
     };
     const void* fn = reinterpret_cast<const void*>(kern(is3));
@@ -1997,7 +1997,8 @@ hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
 }
 
 // Which forward kernel a variant launches for this problem:
-//   BDF-k: 0 wide-tile march, 1 march, 2 one workgroup per tile;
+//   BDF-k: 0 wide-tile march (kind 0 in 2D, 3 in 3D), 1 march with the
+//   time-FFT tile, 2 one workgroup per tile;
 //   CQ: 0 y-march (radix <= 8), 1 y-march (radix <= 16), 2 persistent one-tile kernel.
 // A variant whose kernel does not apply falls back to the next one that does.
 template <typename R, int LOGN>
@@ -2021,8 +2022,8 @@ int fwd_kind(const FwdArgs& a, bool cq) {
     constexpr int NTW = N_OF(LOGN) * WW < 512 ? N_OF(LOGN) * WW : 512;
     constexpr bool WIDE_OK = LOGN <= 9 && PINT_FWD_WIDE;
     // the marching kernels address with 32-bit byte offsets per lane
-    if (var == 0 && WIDE_OK && a.mz == 1 && WW <= a.mxp && (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32))
-        return 0;
+    const bool wide_ok = WIDE_OK && WW <= a.mxp && (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32);
+    if (var == 0 && wide_ok) return a.mz == 1 ? 0 : 3;
     if (W <= a.mxp && a.mxp % W == 0 && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32)) return 1;
     return 2;
 }
@@ -2071,7 +2072,7 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
     constexpr int NTM = (N_OF(LOGN) * W >= PINT_MARCH_NT) ? PINT_MARCH_NT : NT;
     constexpr int WW = 16;
     constexpr int NTW = N_OF(LOGN) * WW < 512 ? N_OF(LOGN) * WW : 512;
-    if (kind == 0) {
+    if (kind == 0 || kind == 3) {
         if constexpr (LOGN <= 9 && PINT_FWD_WIDE) return fwd_march<R, LOGN, WW, NTW, true>(a, nb, st);
         return hipErrorInvalidValue;
     }
