@@ -37,11 +37,6 @@ pint_status fail(pint_status s, const std::string& msg) {
     } while (0)
 
 bool is_pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
-int ilog2(long long x) {
-    int l = 0;
-    while ((1LL << l) < x) ++l;
-    return l;
-}
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 using cld = std::complex<long double>;
