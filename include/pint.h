@@ -178,9 +178,9 @@ pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const doub
  * knobs, each 0 = the built-in choice:
  *   [0] forward kernel: BDF-k residual 2D/3D sweeps 0 wide-tile march along
  *       the outer axis, 1 march with the time-FFT tile, 2 one workgroup per
- *       tile; CQ sweeps
+ *       tile, 3 half-width wide-tile march with two workgroups per CU; CQ sweeps
  *       0 y-march with radix <= 8 transforms, 1 y-march with radix <= 16,
- *       2 persistent one-tile-at-a-time kernel (a choice that does not apply
+ *       2 (and 3) persistent one-tile-at-a-time kernel (a choice that does not apply
  *       to the problem falls back to the next one that does);
  *   [1] rows per workgroup of the x sine pass: 0 built-in, 1 half as many;
  *   [2] column tile of the y/z passes: 0 built-in, 1 the other width;

@@ -74,10 +74,11 @@ struct SpaceArgs {
 
 // Kernel variants the autotuner chooses between (index 0 is the built-in choice).
 //   forward, BDF-k residual 2D/3D: 0 wide-tile march along the outer axis when
-//     eligible (else 1), 1 march with the time-FFT tile, 2 one workgroup per tile;
+//     eligible (else 1), 1 march with the time-FFT tile, 2 one workgroup per tile,
+//     3 half-width wide-tile march, two workgroups per CU (N in 64..512);
 //   forward, CQ: 0 y-march with radix <= 8 transforms when eligible (else 2),
 //     1 y-march with radix <= 16, 2 persistent one-tile-at-a-time kernel.
-constexpr int kFwdVariants = 3;
+constexpr int kFwdVariants = 4;
 
 // Host-side launchers (defined in pint_kernels.hip).  Each returns the
 // hipError_t of the launch; shapes are validated by the caller.

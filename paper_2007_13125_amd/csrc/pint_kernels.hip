@@ -651,20 +651,25 @@ __global__ __launch_bounds__(NT, PINT_MARCH_WAVES) void k_fwd_march(FwdArgs a, i
 //  - the x neighbours outside the tile are loaded by the two edge lanes only
 //    (every other lane's load is masked off) and written to halo columns of
 //    the LDS tile, so Phase B applies one stencil to every slot.
-template <typename R, int LOGN, int W, int NT, bool IS3>
-__global__ __launch_bounds__(NT, 1) void k_fwd_wide(FwdArgs a, int ncol, int nchunk, int chunk) {
+//  - TAB = false (two workgroups per CU): the per-row factors are not staged
+//    in LDS; tau^{-1} s_q (nonzero only for q < k, all in row group 0) is read
+//    once per lane and kappa^{q/N} follows row group by row group from
+//    kappa^{qb/N} times powers of kappa^{RS/N}.
+template <typename R, int LOGN, int W, int NT, bool IS3, bool TAB = true>
+__global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int ncol, int nchunk, int chunk) {
     using T = cx<R>;
     constexpr int N = 1 << LOGN;
     constexpr int B = W / 2;
     constexpr int PER = N * W / NT;
     static_assert(PER * NT == N * W, "tile shape");
     constexpr int RS = NT / W;                       // time rows between row groups i and i+1
+    static_assert(TAB || (PER >= 2 && RS >= 7), "row group 0 must hold every q < k");
     constexpr int WS = W + 2;                        // LDS row: halo, W slots, halo
     constexpr int Z = 6;                             // zero time rows below row 0
     constexpr int CI = (6 * W + NT - 1) / NT < PER ? (6 * W + NT - 1) / NT : PER;
     __shared__ double su[(Z + N) * WS];
     __shared__ double sg[N * W];
-    __shared__ double ssn[N], ssc[N];                // tau^{-1} s_n and kappa^{q/N}
+    __shared__ double ssn[TAB ? N : 1], ssc[TAB ? N : 1];   // tau^{-1} s_n and kappa^{q/N}
     __shared__ T stw[N / 2];
     double* u0 = su + Z * WS + 1;                    // u0[q WS + l]: slot l of time row q (l = -1, W: halo)
     T* sm = reinterpret_cast<T*>(sg);                // FFT buffer [N][B]
@@ -688,11 +693,16 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_wide(FwdArgs a, int ncol, int nch
     const long long slot0 = (long long)x0 + (IS3 ? (long long)a.mxp * yl : 0);
 
     for (int i = tid; i < N; i += NT) {
-        ssn[i] = a.ta * a.s[i];
-        ssc[i] = a.scale[i];
+        if constexpr (TAB) {
+            ssn[i] = a.ta * a.s[i];
+            ssc[i] = a.scale[i];
+        }
         if (i < N / 2) stw[i] = reinterpret_cast<const T*>(a.tw)[i];
     }
     for (int j = tid; j < Z * WS; j += NT) su[j] = 0.0;
+    const double sn0 = TAB ? 0.0 : a.ta * a.s[qb];   // tau^{-1} s_q of row group 0
+    const double sc0 = TAB ? 0.0 : a.scale[qb];      // kappa^{qb/N}
+    const double scs = TAB ? 0.0 : a.scale[RS];      // kappa^{RS/N}
 
     // halo loads: lane dl = 0 reads x0 - 1, lane dl = W-1 reads x0 + W; all others, and
     // neighbours outside the grid, are masked off (they read 0 without a memory access)
@@ -761,7 +771,8 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_wide(FwdArgs a, int ncol, int nch
         for (int i = 0; i < PER; ++i) {
             const int q = qb + i * RS;
             double* p = u0 + sb + i * SSTEP;
-            double acc = vv * ssn[q] + cf * fr[i] + cm * p[0] + cp * Up[i];   // p[0]: U at c-1
+            const double sn = TAB ? ssn[q] : (i == 0 ? sn0 : 0.0);
+            double acc = vv * sn + cf * fr[i] + cm * p[0] + cp * Up[i];   // p[0]: U at c-1
             if (IS3) acc += cym * ym[i] + cyp * yp[i];
             if (i < CI) acc += ccf[i] * cr[i];
             p[0] = valid ? Uc[i] : 0.0;
@@ -775,6 +786,7 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_wide(FwdArgs a, int ncol, int nch
         __syncthreads();
         if constexpr (sizeof(R) == 8) {
             // LDS to LDS: a partial unroll keeps the hoisted stencil reads few
+            double sc = sc0;
 #pragma unroll 2
             for (int i = 0; i < PER; ++i) {
                 const int q = qb + i * RS;
@@ -784,12 +796,14 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_wide(FwdArgs a, int ncol, int nch
 #pragma unroll
                 for (int j = 1; j < 7; ++j) ts += wk[j] * p[-j * WS];
                 const double au = diag * u - cx * (p[-1] + p[1]);
-                const double r = (sg[tid + i * NT] - (a.ta * ts + au)) * ssc[q];
+                const double r = (sg[tid + i * NT] - (a.ta * ts + au)) * (TAB ? ssc[q] : sc);
                 sg[tid + i * NT] = valid ? r : 0.0;
+                if (!TAB) sc *= scs;
             }
             __syncthreads();
         } else {
             R rr[PER];
+            double sc = sc0;
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
                 const int q = qb + i * RS;
@@ -799,8 +813,9 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_wide(FwdArgs a, int ncol, int nch
 #pragma unroll
                 for (int j = 1; j < 7; ++j) ts += wk[j] * p[-j * WS];
                 const double au = diag * u - cx * (p[-1] + p[1]);
-                const double r = (sg[tid + i * NT] - (a.ta * ts + au)) * ssc[q];
+                const double r = (sg[tid + i * NT] - (a.ta * ts + au)) * (TAB ? ssc[q] : sc);
                 rr[i] = valid ? (R)r : (R)0;
+                if (!TAB) sc *= scs;
             }
             __syncthreads();
 #pragma unroll
@@ -1976,11 +1991,12 @@ constexpr int cq_nt(int logn) {
 
 // Marching forward launch: one workgroup per (x tile, line, chunk of the
 // outer axis), with the chunk length chosen so that the grid fills the device once.
-template <typename R, int LOGN, int W, int NT, bool WIDE>
+template <typename R, int LOGN, int W, int NT, bool WIDE, bool TAB = true>
 hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
     const bool is3 = a.mz > 1;
     auto kern = [](bool three) {
-        if constexpr (WIDE) return three ? &k_fwd_wide<R, LOGN, W, NT, true> : &k_fwd_wide<R, LOGN, W, NT, false>;
+        if constexpr (WIDE)
+            return three ? &k_fwd_wide<R, LOGN, W, NT, true, TAB> : &k_fwd_wide<R, LOGN, W, NT, false, TAB>;
         else return three ? &k_fwd_march<R, LOGN, W, NT, true> : &k_fwd_march<R, LOGN, W, NT, false>;
     };
     const void* fn = reinterpret_cast<const void*>(kern(is3));
@@ -1998,7 +2014,8 @@ hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
 
 // Which forward kernel a variant launches for this problem:
 //   BDF-k: 0 wide-tile march (kind 0 in 2D, 3 in 3D), 1 march with the
-//   time-FFT tile, 2 one workgroup per tile;
+//   time-FFT tile, 2 one workgroup per tile, 3 half-width wide-tile march with
+//   two workgroups per CU (kind 4);
 //   CQ: 0 y-march (radix <= 8), 1 y-march (radix <= 16), 2 persistent one-tile kernel.
 // A variant whose kernel does not apply falls back to the next one that does.
 template <typename R, int LOGN>
@@ -2024,6 +2041,9 @@ int fwd_kind(const FwdArgs& a, bool cq) {
     // the marching kernels address with 32-bit byte offsets per lane
     const bool wide_ok = WIDE_OK && WW <= a.mxp && (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32);
     if (var == 0 && wide_ok) return a.mz == 1 ? 0 : 3;
+    // half-width wide tiles, two workgroups per CU
+    if (var == 3 && WIDE_OK && N_OF(LOGN) * 8 >= 2 * 256 && 8 <= a.mxp && (256 / 8 + 2) * (long long)a.M * 8 < (1LL << 32))
+        return 4;
     if (W <= a.mxp && a.mxp % W == 0 && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32)) return 1;
     return 2;
 }
@@ -2074,6 +2094,10 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
     constexpr int NTW = N_OF(LOGN) * WW < 512 ? N_OF(LOGN) * WW : 512;
     if (kind == 0 || kind == 3) {
         if constexpr (LOGN <= 9 && PINT_FWD_WIDE) return fwd_march<R, LOGN, WW, NTW, true>(a, nb, st);
+        return hipErrorInvalidValue;
+    }
+    if (kind == 4) {
+        if constexpr (LOGN <= 9 && LOGN >= 6 && PINT_FWD_WIDE) return fwd_march<R, LOGN, 8, 256, true, false>(a, nb, st);
         return hipErrorInvalidValue;
     }
     if (kind == 1) return fwd_march<R, LOGN, W, NTM, false>(a, nb, st);

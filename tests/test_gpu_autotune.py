@@ -19,7 +19,7 @@ CASES = [
     (1, (200,), 16, 2, 1.0, 1e-2),       # 1D PCR/Thomas split
     (1, (255,), 64, 2, 1.0, 1e-3),       # 1D sine-transform solve: rows per workgroup
 ]
-KNOB_VALUES = [(0, 1), (0, 2), (1, 1), (2, 1), (3, 1)]
+KNOB_VALUES = [(0, 1), (0, 2), (0, 3), (1, 1), (2, 1), (3, 1)]
 
 
 def _case(dim, m, N, k, alpha, kappa):
@@ -71,7 +71,7 @@ def test_autotuned_solve_matches_oracle(case, precision):
     w = _case(*case)
     ref = oracle_solution(w)
     U, info, chosen = _solve(w, precision, autotune=2)
-    assert len(chosen) == 4 and 0 <= chosen[0] <= 2 and all(c in (0, 1) for c in chosen[1:]), chosen
+    assert len(chosen) == 4 and 0 <= chosen[0] <= 3 and all(c in (0, 1) for c in chosen[1:]), chosen
     err = rel_l2(U, ref)
     bar = 1e-11 if precision == "fp64" else 1e-10
     assert info["status"] == 0 and err <= bar, (err, info, chosen)
@@ -89,9 +89,9 @@ def test_tune_after_bind_and_variant_errors():
     plan.bind(to_dev(w.v), to_dev(w.f), to_dev(w.fder))
     plan.init_iterate(U)
     chosen = plan.tune(U, 2)
-    assert 0 <= chosen[0] <= 2 and all(c in (0, 1) for c in chosen[1:]), chosen
+    assert 0 <= chosen[0] <= 3 and all(c in (0, 1) for c in chosen[1:]), chosen
     with pytest.raises(PintError):
-        plan.set_variants([3, 0, 0, 0])
+        plan.set_variants([4, 0, 0, 0])
     with pytest.raises(PintError):
         plan.set_variants([0, 2, 0, 0])
     plan.sweeps(U, 3)                        # tuned plan sweeps normally
@@ -122,7 +122,7 @@ def test_batch_autotune_each_instance():
     assert st == B.PINT_OK
     for i, w in enumerate(ws):
         chosen = B.pint_plan_get_variants(h, i)
-        assert 0 <= chosen[0] <= 2 and all(c in (0, 1) for c in chosen[1:]), chosen
+        assert 0 <= chosen[0] <= 3 and all(c in (0, 1) for c in chosen[1:]), chosen
         err = rel_l2(Us[i].cpu().numpy(), oracle_solution(w))
         assert err <= 1e-11, (i, err)
     B.pint_plan_destroy(h)

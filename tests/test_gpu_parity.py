@@ -69,6 +69,8 @@ SMALL = [
     (2, (61, 9), 256, 3, 0.5, 1e-3),
     (2, (13, 40), 512, 3, 0.3, 1e-3),
     (2, (29, 2), 128, 4, 0.5, 1e-3),
+    # 2D subdiffusion at the longest time axis (one-tile CQ kernel, twiddles read from global memory)
+    (2, (13, 7), 2048, 2, 0.5, 1e-2),
 ]
 
 
