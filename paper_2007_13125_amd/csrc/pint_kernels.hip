@@ -1041,15 +1041,16 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cq(FwdArgs a, int nvirt) {
 // the even points of FFT_2N(z, 0) are FFT_N(z) and the odd points FFT_N(z t),
 // so for j < N
 //   c_j = IFFT_N(W_even . FFT_N(z))_j + conj(t_j) IFFT_N(W_odd . FFT_N(z t))_j,
-// W the 2N-point DFT of (omega, 0) divided by 2N.  The FFT buffer is N x B and
-// the even part waits in a second N x W buffer, so the omega DFT, the twiddles
-// and the per-row factors all stay in LDS and no partial sum is held in
-// registers across a transform.  As in k_fwd_march, a workgroup owns W x slots
-// and walks a chunk of y; each lane keeps its time rows of U at y-1, y, y+1 in
-// registers (renamed, never copied), x neighbours inside the tile come from
-// the adjacent lanes (DPP), and the load of U at y+2 is issued once U at y-1
-// has been used, one whole position (four FP64 transforms, the time FFT and
-// the spectrum store) before it is needed.
+// W the 2N-point DFT of (omega, 0) divided by 2N.  Both halves go through one
+// batched length-N transform pair over 2B sequences (z and z t side by side in
+// an N x 2B buffer, half the size of the 2N x B one), so the omega DFT, the
+// twiddles and the per-row factors all stay in LDS and no partial sum is held
+// in registers across a transform.  As in k_fwd_march, a workgroup owns W x
+// slots and walks a chunk of y; each lane keeps its time rows of U at y-1, y,
+// y+1 in registers (renamed, never copied), x neighbours inside the tile come
+// from the adjacent lanes (DPP), and the load of U at y+2 is issued once U at
+// y-1 has been used, one whole position (two batched FP64 transforms, the time
+// FFT and the spectrum store) before it is needed.
 template <int W>
 __device__ __forceinline__ double lane_dpp(double v, bool next) {
     if constexpr (W <= 16) {
@@ -1092,11 +1093,12 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
     constexpr int N = 1 << LOGN;
     constexpr int B = W / 2;
     constexpr int PER = N * W / NT;     // (time row, slot) elements per thread
-    constexpr int PC = N * B / NT;      // complex points per thread in the pointwise products
+    constexpr int PC = 2 * N * B / NT;  // complex points per thread in the pointwise products
     constexpr int RS = NT / W;          // time rows between a thread's consecutive elements
-    static_assert(PER * NT == N * W && PC * NT == N * B && RS >= 8, "tile shape");
-    __shared__ double2 buf[N * B];      // FP64 pair sequences; then the time-FFT buffer (cx<R>)
-    __shared__ double sev[N * W];       // the even part of the convolution
+    static_assert(PER * NT == N * W && PC * NT == 2 * N * B && RS >= 8, "tile shape");
+    // 2B sequences transformed together: the B pair sequences z (even points)
+    // and the B twisted sequences z t (odd points); row q holds 2W doubles
+    __shared__ double2 buf[N * 2 * B];  // then the time-FFT buffer (cx<R>, N x B)
     __shared__ double2 swe[N], swo[N];  // W_{2j}, W_{2j+1}
     __shared__ double2 stw[N];          // e^{-pi i j/N}, j < N (twist; FFT_N twiddles at stride 2)
     __shared__ T stw1[N / 2];           // e^{-2 pi i j/N} in the spectrum precision
@@ -1173,38 +1175,34 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
             const size_t e0 = (size_t)c * sdof;
             cr = buf_ld(buf_rsrc(a.corr + e0, ((size_t)a.ncorr * M - e0) * 8), qb < a.ncorr ? lo : kNoLane, 0.0);
         }
-        // even points: FFT_N of the pair sequences of U at c
-#pragma unroll
-        for (int i = 0; i < PER; ++i) cbr[t + i * NT] = Uc[i];
-        __syncthreads();
-        lds_fft<double, LOGN, B, NT, false, true, 0, 0, 2, MAXLOG>(buf, stw, t);
-#pragma unroll
-        for (int j = 0; j < PC; ++j) buf[t + j * NT] = cmul(buf[t + j * NT], swe[(t + j * NT) / B]);
-        __syncthreads();
-        lds_fft<double, LOGN, B, NT, true, true, 0, 0, 2, MAXLOG>(buf, stw, t);
-        // park the even part; each lane overwrites its own element with z t_q
+        // both halves of the 2N-point transform in one batch: z in the first W
+        // doubles of each row, z t_q in the second W (pair partner from the adjacent lane)
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int q = t / W + i * RS;
-            sev[t + i * NT] = cbr[t + i * NT];
+            const int e = q * 2 * W + t % W;
             const double2 tq = stw[q];
             const double u = Uc[i];
-            cbr[t + i * NT] = u * tq.x + sgn * lane_pair(u) * tq.y;
+            cbr[e] = u;
+            cbr[e + W] = u * tq.x + sgn * lane_pair(u) * tq.y;
         }
         __syncthreads();
-        // odd points
-        lds_fft<double, LOGN, B, NT, false, true, 0, 0, 2, MAXLOG>(buf, stw, t);
+        lds_fft<double, LOGN, 2 * B, NT, false, true, 0, 0, 2, MAXLOG>(buf, stw, t);
 #pragma unroll
-        for (int j = 0; j < PC; ++j) buf[t + j * NT] = cmul(buf[t + j * NT], swo[(t + j * NT) / B]);
+        for (int j = 0; j < PC; ++j) {
+            const int idx = t + j * NT, pf = idx / (2 * B);
+            buf[idx] = cmul(buf[idx], (idx % (2 * B)) < B ? swe[pf] : swo[pf]);
+        }
         __syncthreads();
-        lds_fft<double, LOGN, B, NT, true, true, 0, 0, 2, MAXLOG>(buf, stw, t);
+        lds_fft<double, LOGN, 2 * B, NT, true, true, 0, 0, 2, MAXLOG>(buf, stw, t);
         // r = (G - A_h U^n - tau^{-alpha} c) kappa^{q/N}
         double r[PER];
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int q = t / W + i * RS;
+            const int e = q * 2 * W + t % W;
             const double2 tq = stw[q];
-            const double p = cbr[t + i * NT];
+            const double p = cbr[e + W];
             const double c2 = p * tq.x - sgn * lane_pair(p) * tq.y;   // conj(t_q) times the pair value
             const double u = Uc[i];
             const double xm = lane_dpp<W>(u, false), xp = lane_dpp<W>(u, true);
@@ -1212,7 +1210,7 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
             double g = ssn[q] * vv - au;
             if (a.f) g += fr[i];
             if (i == 0) g += cr;
-            r[i] = (g - a.ta * (sev[t + i * NT] + c2)) * ssc[q];
+            r[i] = (g - a.ta * (cbr[e] + c2)) * ssc[q];
         }
         // U at c-1 is consumed: prefetch U at c+2
         __builtin_amdgcn_sched_barrier(0);
