@@ -739,7 +739,13 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
                                               buf_rsrc(arr + e0, (unsigned long long)(n - e0) * 8ull), (int)off, 0, 0));
     };
-    double A[PER], Bv[PER], fr[PER], hx[PER], ym[PER], yp[PER], cr[CI];
+    // 3D: with YAHEAD the y-neighbour lines of position c are loaded together
+    // with U at c (two positions ahead, in the same step as the workgroups that
+    // own those lines load them, so L2 serves them; two sets alternate with the
+    // steps); otherwise one position ahead with the other side loads.  The FP64
+    // kernel keeps the latter: the second set does not fit its registers.
+    constexpr bool YAHEAD = IS3 && sizeof(R) == 4;
+    double A[PER], Bv[PER], fr[PER], hx[PER], ymA[PER], ypA[PER], ymB[YAHEAD ? PER : 1], ypB[YAHEAD ? PER : 1], cr[CI];
     double vv;
     auto load_row = [&](double (&dst)[PER], int c) {
 #pragma unroll
@@ -750,9 +756,9 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
         for (int i = 0; i < PER; ++i) {
             const size_t e0 = (size_t)i * RS * M + (size_t)c * sdof;
             hx[i] = at(a.U, nU, e0, lhx);
-            if (IS3) {
-                ym[i] = at(a.U, nU, e0, lym);
-                yp[i] = at(a.U, nU, e0, lyp);
+            if constexpr (IS3 && !YAHEAD) {
+                ymA[i] = at(a.U, nU, e0, lym);
+                ypA[i] = at(a.U, nU, e0, lyp);
             }
             fr[i] = at(fbase, nU, e0, lo);
         }
@@ -760,12 +766,23 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
         for (int i = 0; i < CI; ++i) cr[i] = at(cbase, nC, (size_t)c * sdof, lcr[i]);
         vv = at(a.v, M, (size_t)c * sdof, lv);
     };
+    auto load_ynb = [&](double (&ym)[PER], double (&yp)[PER], int c) {   // y neighbours at position c
+        if constexpr (YAHEAD) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const size_t e0 = (size_t)i * RS * M + (size_t)c * sdof;
+                ym[i] = at(a.U, nU, e0, lym);
+                yp[i] = at(a.U, nU, e0, lyp);
+            }
+        }
+    };
     // LDS index of element i of this lane: (q_i, dl) with q_i = qb + i RS
     const int sb = qb * WS + dl;
     constexpr int SSTEP = RS * WS;
 
-    // One position c with U at c and c+1 in Uc, Up (Uc is refilled with U at c+2).
-    auto step = [&](int c, double (&Uc)[PER], double (&Up)[PER]) {
+    // One position c with U at c and c+1 in Uc, Up (Uc is refilled with U at c+2)
+    // and, in 3D, the y neighbours at c in Ym, Yp (refilled with those at c+2).
+    auto step = [&](int c, double (&Uc)[PER], double (&Up)[PER], double (&Ym)[PER], double (&Yp)[PER]) {
         const double cm = c > 0 ? co : 0.0, cp = c < nm - 1 ? co : 0.0;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -773,7 +790,7 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
             double* p = u0 + sb + i * SSTEP;
             const double sn = TAB ? ssn[q] : (i == 0 ? sn0 : 0.0);
             double acc = vv * sn + cf * fr[i] + cm * p[0] + cp * Up[i];   // p[0]: U at c-1
-            if (IS3) acc += cym * ym[i] + cyp * yp[i];
+            if (IS3) acc += cym * Ym[i] + cyp * Yp[i];
             if (i < CI) acc += ccf[i] * cr[i];
             p[0] = valid ? Uc[i] : 0.0;
             if (dl == 0) p[-1] = hx[i];
@@ -782,6 +799,7 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
         }
         __builtin_amdgcn_sched_barrier(0);
         load_row(Uc, min(c + 2, nm - 1));
+        load_ynb(Ym, Yp, min(c + 2, nm - 1));
         load_side(min(c + 1, nm - 1));
         __syncthreads();
         if constexpr (sizeof(R) == 8) {
@@ -834,11 +852,20 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
     for (int i = 0; i < PER; ++i) u0[sb + i * SSTEP] = valid ? A[i] : 0.0;
     load_row(A, c0);
     load_row(Bv, min(c0 + 1, nm - 1));
+    if constexpr (YAHEAD) {
+        load_ynb(ymA, ypA, c0);
+        load_ynb(ymB, ypB, min(c0 + 1, nm - 1));
+    }
     load_side(c0);
     __syncthreads();
     for (int c = c0; c < c1; c += 2) {
-        step(c, A, Bv);
-        if (c + 1 < c1) step(c + 1, Bv, A);
+        if constexpr (YAHEAD) {
+            step(c, A, Bv, ymA, ypA);
+            if (c + 1 < c1) step(c + 1, Bv, A, ymB, ypB);
+        } else {
+            step(c, A, Bv, ymA, ypA);
+            if (c + 1 < c1) step(c + 1, Bv, A, ymA, ypA);
+        }
     }
 }
 
