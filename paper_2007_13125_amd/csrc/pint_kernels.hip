@@ -492,7 +492,10 @@ __global__ __launch_bounds__(NT, PINT_MARCH_WAVES) void k_fwd_march(FwdArgs a, i
     if (lin >= ncol * nchunk) return;
     const int col = lin % ncol, chk = lin / ncol;
     const int nxt = a.mxp / W;
-    const int xt = col % nxt, yl = col / nxt;          // x tile, y line (3D)
+    // x tile and y line (3D): consecutive workgroups take consecutive y lines of
+    // one x tile, so the lines whose U a workgroup reads as y neighbours are
+    // marched at the same time by workgroups on the same XCD (shared L2)
+    const int xt = IS3 ? col / a.my : col % nxt, yl = IS3 ? col % a.my : col / nxt;
     const int nm = IS3 ? a.mz : a.my;                  // length of the marching axis
     const int c0 = chk * chunk, c1 = min(nm, c0 + chunk);
     const int tid = threadIdx.x;
@@ -679,7 +682,7 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
     if (lin >= ncol * nchunk) return;
     const int col = lin % ncol, chk = lin / ncol;
     const int nxt = a.mxp / W;
-    const int xt = col % nxt, yl = col / nxt;
+    const int xt = IS3 ? col / a.my : col % nxt, yl = IS3 ? col % a.my : col / nxt;   // 3D: y lines fastest
     const int nm = IS3 ? a.mz : a.my;
     const int c0 = chk * chunk, c1 = min(nm, c0 + chunk);
     const int tid = threadIdx.x;
