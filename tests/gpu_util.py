@@ -12,14 +12,16 @@ def to_dev(a):
     return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def gpu_solve(w, precision="fp64", form="residual", init="v", tol=None, max_sweeps=40, norm="inf"):
+def gpu_solve(w, precision="fp64", form="residual", init="v", tol=None, max_sweeps=40, norm="inf", variants=None):
     import torch
 
     from paper_2007_13125_amd.binding import Plan
     print(f"[gpu] solve {w.name} m={w.m} N={w.N} k={w.k} alpha={w.alpha} kappa={w.kappa} "
-          f"{precision}/{form}/{init}", flush=True)
+          f"{precision}/{form}/{init} variants={variants}", flush=True)
     plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=tol or w.tol, max_sweeps=max_sweeps,
                 precision=precision, form=form, init=init, norm=norm)
+    if variants is not None:
+        plan.set_variants(variants)
     U, info = plan.solve(to_dev(w.v), to_dev(w.f), to_dev(w.fder))
     torch.cuda.synchronize()
     out = U.cpu().numpy()

@@ -27,6 +27,30 @@ def test_heat2d_full(precision):
     assert err <= (1e-11 if precision == "fp64" else 1e-10)
 
 
+_MODAL = {}
+
+
+def _modal_ref(w, seed):
+    key = (w.name, seed)
+    if key not in _MODAL:
+        dofs = np.random.default_rng(seed).choice(w.M, 4096, replace=False)
+        _MODAL[key] = (dofs, oracle_modal(w, dofs))
+    return _MODAL[key]
+
+
+# every kernel variant the autotuner may pick for the benchmark workload
+# (forward kernel 1..3, half the rows per x-pass workgroup, the other y-pass tile)
+@pytest.mark.parametrize("variants", [[1, 0, 0, 0], [2, 0, 0, 0], [3, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_heat2d_full_every_variant(precision, variants):
+    w = wl.heat2d()
+    U, info = gpu_solve(w, precision=precision, tol=1e-13, max_sweeps=12, variants=variants)
+    dofs, ref = _modal_ref(w, 0)
+    err = rel_l2(U[:, dofs], ref)
+    print(f"heat2d {precision} {variants}: sweeps={info['sweeps']} rel_l2={err:.2e}", flush=True)
+    assert err <= (1e-11 if precision == "fp64" else 1e-10)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_heat3d_full(precision):
     w = wl.heat3d()
@@ -38,10 +62,11 @@ def test_heat3d_full(precision):
     assert err <= (1e-11 if precision == "fp64" else 1e-10)
 
 
+@pytest.mark.parametrize("variants", [None, [1, 1, 0, 0]])   # built-in, and the autotuner's usual pick
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_subdiff2d_full(precision):
+def test_subdiff2d_full(precision, variants):
     w = wl.subdiff2d()
-    U, info = gpu_solve(w, precision=precision, tol=1e-13, max_sweeps=12)
+    U, info = gpu_solve(w, precision=precision, tol=1e-13, max_sweeps=12, variants=variants)
     print(f"subdiff2d {precision}: sweeps={info['sweeps']} upd={info['upd']}", flush=True)
     bar = 1e-11 if precision == "fp64" else 1e-10
     # (1) the first 32 levels against the sequential oracle (causality: they do not
