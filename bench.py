@@ -112,6 +112,30 @@ def time_to_tol(w, plan, data, Uref, tol=1e-10, max_sweeps=12):
     return {"sweeps": mstar, "ms": best * 1e3, "errors": errs}
 
 
+def other_configs(steps, tune):
+    """The other multi-dimensional workloads of the method's evaluation (parity-test
+    cases, not bench lines): tuned sweep time per precision and its algorithmic
+    HBM fraction."""
+    import torch
+
+    from paper_2007_13125_amd import workloads as wl
+    out = {}
+    for name in ("subdiff2d", "heat3d"):
+        w = getattr(wl, name)()
+        entry = {"grid": list(w.m), "N": w.N, "k": w.k, "alpha": w.alpha, "kappa": w.kappa, "unknowns": w.N * w.M}
+        for precision in ("fp64", "mixed"):
+            plan, _, ms, prof, var = run_precision(w, precision, steps, 1, tune=tune)
+            mixed = precision == "mixed"
+            nbytes = sum(kernel_bytes(n, w.N, w.M, mixed, w.f is not None) for n, _ in prof)
+            entry[precision] = {"ms_per_step": ms, "value": w.N * w.M / (ms * 1e-3),
+                                "sweep_hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "kernels_ms": {n: t for n, t in prof}, "variants": var}
+            plan.close()
+            torch.cuda.empty_cache()
+        out[name] = entry
+    return out
+
+
 def cpu_baseline(seconds_hint=20.0):
     """The FP64 oracle's dense-DFT sweep (Algorithm 1 with dense DFT matrices and
     sparse LU per frequency), timed on a bounded sample: the same recipe on a
@@ -243,6 +267,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel variants (no autotuning)")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the sweep timings of the 2D subdiffusion and 3D heat workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 256 MiB on the device (counter calibration for profiles)")
     ap.add_argument("--summarize", metavar="DIR",
@@ -324,6 +350,8 @@ def main():
         "time_to_1e-10": {p: {"sweeps": ttt[p]["sweeps"], "ms": ttt[p]["ms"]} for p in ttt},
         "fp64_direct": {"ms_per_step": ms_d, "kernels_ms": {n: t for n, t in prof_d}},
     }
+    if not args.no_other_configs:
+        res["other_configs"] = other_configs(5, not args.no_tune)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     for p in plans.values():
