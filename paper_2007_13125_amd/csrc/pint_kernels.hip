@@ -745,9 +745,11 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
     // 3D: with YAHEAD the y-neighbour lines of position c are loaded together
     // with U at c (two positions ahead, in the same step as the workgroups that
     // own those lines load them, so L2 serves them; two sets alternate with the
-    // steps); otherwise one position ahead with the other side loads.  The FP64
-    // kernel keeps the latter: the second set does not fit its registers.
-    constexpr bool YAHEAD = IS3 && sizeof(R) == 4;
+    // steps); otherwise one position ahead with the other side loads.
+    // FP64 needs radix <= 8 time-FFT stages (half the registers per butterfly) to make
+    // room for the second set; both precisions fit it only up to 8 rows per lane
+    constexpr bool YAHEAD = IS3 && PER <= 8;
+    constexpr int FMAXLOG = (YAHEAD && sizeof(R) == 8) ? 3 : 4;
     double A[PER], Bv[PER], fr[PER], hx[PER], ymA[PER], ypA[PER], ymB[YAHEAD ? PER : 1], ypB[YAHEAD ? PER : 1], cr[CI];
     double vv;
     auto load_row = [&](double (&dst)[PER], int c) {
@@ -843,7 +845,7 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
             for (int i = 0; i < PER; ++i) smr[tid + i * NT] = rr[i];
             __syncthreads();
         }
-        lds_fft<R, LOGN, B, NT, false, true, 0>(sm, stw);
+        lds_fft<R, LOGN, B, NT, false, true, 0, 0, 1, FMAXLOG>(sm, stw);
         store_half_spectrum<R, N, B, NT, false>(sm, reinterpret_cast<T*>(a.S), a.ldS, (int)(slot0 + c * sslot), a.Mp);
         __syncthreads();
     };
@@ -2023,10 +2025,14 @@ template <typename R, int LOGN, int W, int NT, bool WIDE, bool TAB = true>
 hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
     const bool is3 = a.mz > 1;
     auto kern = [](bool three) {
-        if constexpr (WIDE)
+        if constexpr (WIDE && LOGN <= 8)
             return three ? &k_fwd_wide<R, LOGN, W, NT, true, TAB> : &k_fwd_wide<R, LOGN, W, NT, false, TAB>;
+        else if constexpr (WIDE)   // the 3D wide tile is used up to N = 256 only
+            return (void)three, &k_fwd_wide<R, LOGN, W, NT, false, TAB>;
         else return three ? &k_fwd_march<R, LOGN, W, NT, true> : &k_fwd_march<R, LOGN, W, NT, false>;
     };
+    if constexpr (WIDE && LOGN > 8)
+        if (is3) return hipErrorInvalidValue;   // never chosen (fwd_kind)
     const void* fn = reinterpret_cast<const void*>(kern(is3));
     const int ncol = (a.mxp / W) * (is3 ? a.my : 1);
     const int nm = is3 ? a.mz : a.my;
@@ -2067,10 +2073,14 @@ int fwd_kind(const FwdArgs& a, bool cq) {
     constexpr int NTW = N_OF(LOGN) * WW < 512 ? N_OF(LOGN) * WW : 512;
     constexpr bool WIDE_OK = LOGN <= 9 && PINT_FWD_WIDE;
     // the marching kernels address with 32-bit byte offsets per lane
-    const bool wide_ok = WIDE_OK && WW <= a.mxp && (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32);
+    // (3D: up to N = 256, where the wide tile's eight rows per lane leave room
+    // for the y-neighbour loads without spilling)
+    const bool wide_ok = WIDE_OK && (a.mz == 1 || LOGN <= 8) && WW <= a.mxp &&
+                         (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32);
     if (var == 0 && wide_ok) return a.mz == 1 ? 0 : 3;
     // half-width wide tiles, two workgroups per CU
-    if (var == 3 && WIDE_OK && N_OF(LOGN) * 8 >= 2 * 256 && 8 <= a.mxp && (256 / 8 + 2) * (long long)a.M * 8 < (1LL << 32))
+    if (var == 3 && WIDE_OK && (a.mz == 1 || LOGN <= 8) && N_OF(LOGN) * 8 >= 2 * 256 && 8 <= a.mxp &&
+        (256 / 8 + 2) * (long long)a.M * 8 < (1LL << 32))
         return 4;
     if (W <= a.mxp && a.mxp % W == 0 && (long long)(NTM / W + 2) * a.M * 8 < (1LL << 32)) return 1;
     return 2;

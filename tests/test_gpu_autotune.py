@@ -15,6 +15,7 @@ CASES = [
     (2, (63, 15), 128, 5, 1.0, 1e-3),    # forward: wide march / march / one tile; x and y passes
     (2, (31, 15), 512, 4, 1.0, 1e-4),    # the same at N = 512 (the benchmark's time length)
     (3, (15, 7, 3), 256, 3, 1.0, 1e-3),  # 3D march along z / one tile; y and z passes
+    (3, (15, 3, 5), 512, 2, 1.0, 1e-3),  # 3D at N = 512 (the wide tile is not used there)
     (2, (61, 9), 256, 3, 0.5, 1e-3),     # CQ: y-march radix 8 / radix 16 / persistent one tile
     (1, (200,), 16, 2, 1.0, 1e-2),       # 1D PCR/Thomas split
     (1, (255,), 64, 2, 1.0, 1e-3),       # 1D sine-transform solve: rows per workgroup

@@ -71,6 +71,9 @@ SMALL = [
     (2, (29, 2), 128, 4, 0.5, 1e-3),
     # 2D subdiffusion at the longest time axis (one-tile CQ kernel, twiddles read from global memory)
     (2, (13, 7), 2048, 2, 0.5, 1e-2),
+    # the longest supported grid lines (sine transforms of length 4096 along x, then along y)
+    (2, (2047, 3), 8, 2, 1.0, 1e-2),
+    (2, (3, 2047), 16, 3, 0.5, 1e-2),
 ]
 
 
