@@ -223,7 +223,7 @@ def summarize(outdir):
              f"Device: one MI355X (gfx950).  Source: `{KERNEL_SOURCE}` sha256 prefix `{sha[:16]}`.", "",
              "Commands (run from /tmp with TMPDIR=/tmp; each writes CSV under the -d folder), then "
              "`python bench.py --summarize <out>` writes this file and the traffic record:", "", "```"]
-    cmd = "python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --copy-calibration"
+    cmd = "python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-other-configs --copy-calibration"
     lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o heat2d -- {cmd}",
               f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/FETCH_SIZE -o heat2d -- {cmd}",
               f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/WRITE_SIZE -o heat2d -- {cmd}",
