@@ -92,3 +92,50 @@ def test_subdiff2d_full(precision, variants):
     res = ta * L + AU - G
     scale = np.linalg.norm(ta * L) + np.linalg.norm(AU) + np.linalg.norm(G)
     assert np.linalg.norm(res) / scale <= bar * 10, np.linalg.norm(res) / scale
+
+
+# Instances of the many-instance recipe (dim 1 or 2, m_i in 63..1023, N in 32..1024,
+# k in 1..6, alpha in {1, 0.3, 0.7}, kappa log-uniform in [1e-6, 1e-2]) at their full
+# recipe sizes, mixed precision with the autotuner on, each through the single-plan
+# path that a batch solve runs per instance.  The first instances of the recipe's
+# seed with at most 2^25 unknowns (the larger ones differ only in size).  Stop test
+# 1e-10 on the update: on the fine 1D grids at small kappa the mixed-precision update
+# norm levels off between 2e-13 and 3e-11 (the FP64 rounding noise of the residual,
+# ~eps |A_h| |U|, goes through the FP32 transforms, whose rounding the kappa^{-q/N}
+# unscaling amplifies by up to 1/kappa; in FP64 the same instances level off near
+# 5e-14), so a smaller tolerance is not reached there.
+def _recipe_instances(count=24, cap=2 ** 25):
+    out, i = [], 0
+    while len(out) < count:
+        w = wl.batch_instance(i)
+        if w.N * w.M <= cap:
+            out.append(i)
+        i += 1
+    return out
+
+
+@pytest.mark.parametrize("i", _recipe_instances())
+def test_batch_recipe_instance_full_size(i):
+    import torch
+
+    from paper_2007_13125_amd.binding import Plan
+    from tests.gpu_util import to_dev
+    w = wl.batch_instance(i)
+    print(f"[gpu] recipe instance {i}: m={w.m} N={w.N} k={w.k} alpha={w.alpha} kappa={w.kappa:.3g}", flush=True)
+    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-10, max_sweeps=40, precision="mixed")
+    plan.set_autotune(2)
+    U, info = plan.solve(to_dev(w.v), to_dev(w.f), to_dev(w.fder))
+    torch.cuda.synchronize()
+    chosen = plan.variants()
+    plan.close()
+    print(f"recipe {i}: status={info['status']} sweeps={info['sweeps']} upd={list(info['upd'])}", flush=True)
+    if len(w.m) == 1:
+        ref = oracle_solution(w)
+        err = rel_l2(U.cpu().numpy(), ref)
+    else:
+        dofs = np.random.default_rng(i).choice(w.M, 2048, replace=False)
+        ref = oracle_modal(w, dofs)
+        err = rel_l2(U[:, torch.from_numpy(dofs).to(U.device)].cpu().numpy(), ref)
+    print(f"recipe {i}: variants={chosen} rel_l2={err:.2e}", flush=True)
+    assert err <= 1e-10
+    assert info["status"] == 0
