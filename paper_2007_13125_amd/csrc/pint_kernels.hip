@@ -1782,6 +1782,226 @@ __global__ __launch_bounds__(NT) void k_dst_cols(SpaceArgs a, int axis) {
     }
 }
 
+// The same column pass with the odd extension folded into the first and last
+// FFT stages (lengths L = 2^8..2^11, with a radix schedule that starts and ends with
+// the same radix R0 = L / Q: 16 x 16, 8 x 8 x 8, 16 x 4 x 16, 16 x 8 x 16).  For an
+// odd sequence of length L (y_0 = y_{L/2} = 0,
+// y_{L-t} = -y_t), butterfly j of the first Stockham stage reads y_{j + Q r};
+// its upper half r >= R0/2 is minus the lower half of butterfly Q - j, reversed:
+// y_{j + Q r} = -x_{(Q - j) + Q (R0 - 1 - r)}.  So a lane loads only the values
+// x_{g + Q s}, s < R0/2, of its butterfly g (the last butterfly, g = Q, stands for
+// j = 0 and needs nothing else), trades them through LDS with butterfly Q - g,
+// and writes the first stage's outputs without the odd extension ever being
+// stored.  At the other end the last stage's butterfly j holds Y_{j + Q r}: its
+// lower half is the transform on k = 1..m, which is divided by the shift (SOLVE)
+// and traded the same way into the first stage of the second transform, or
+// (last stage of the last transform) stored straight from registers.  Per value
+// this moves ~10 LDS passes where k_dst_cols moves ~15 (solve) and ~3 where it
+// moves ~5.5 (transform only).
+constexpr int fused_r0(int logl) { return (logl == 8 || logl == 10 || logl == 11) ? 16 : (logl == 9 ? 8 : 0); }
+
+template <typename R, int LOGL, int W, int NT, bool SOLVE>
+__global__ __launch_bounds__(NT) void k_dst_colsf(SpaceArgs a, int axis) {
+    using T = cx<R>;
+    constexpr int L = 1 << LOGL;
+    constexpr int R0 = fused_r0(LOGL);
+    static_assert(R0 == 8 || R0 == 16, "length without a fused radix schedule");
+    constexpr int LR0 = R0 == 16 ? 4 : 3;
+    constexpr int H = R0 / 2;
+    constexpr int Q = L / R0;                  // butterflies per column in the first and last stage
+    constexpr int LMID = LOGL - 2 * LR0;       // one middle stage of radix 2^LMID (0: none)
+    static_assert(LMID == 0 || LMID == 2 || LMID == 3, "middle stage radix");
+    constexpr int TASKS = Q * W;
+    constexpr int TPL = (TASKS + NT - 1) / NT; // butterflies per lane
+    static_assert(NT % W == 0, "a lane keeps one column");
+    static_assert(TASKS % NT == 0 || TASKS < NT, "whole butterflies per lane");
+    __shared__ T sm[L * W];
+    constexpr bool TWL = (L * W + L / 2) * (int)sizeof(T) + (L / 2) * 8 <= 155648;
+    __shared__ T stw[TWL ? L / 2 : 1];
+    __shared__ double smu[SOLVE ? L / 2 : 1];
+    const int m = axis == 1 ? a.my : a.mz;     // = L/2 - 1
+    const long long st = axis == 1 ? (long long)a.mxp : (long long)a.mxp * a.my;
+    const int other = axis == 1 ? a.mz : a.my;
+    const int nxg = (a.mx + W - 1) / W;
+    const long long ngroups = (long long)a.nP * other * nxg;
+    T* S = reinterpret_cast<T*>(a.S);
+    const T zero = mk<T>((R)0, (R)0);
+    const T* tw = TWL ? stw : reinterpret_cast<const T*>(a.twL[axis]);
+    if (TWL)
+        for (int j = threadIdx.x; j < L / 2; j += NT) stw[j] = reinterpret_cast<const T*>(a.twL[axis])[j];
+    if (SOLVE)
+        for (int j = threadIdx.x; j < m; j += NT) smu[j] = a.mu[axis][j];
+    const int wl = threadIdx.x % W;
+    struct Grp {
+        int p, o, x0;
+        long long base;
+    };
+    auto decode = [&](long long gid) {
+        Grp g;
+        const int xg = (int)(gid % nxg);
+        const long long rest = gid / nxg;
+        g.o = (int)(rest % other);
+        g.p = (int)(rest / other);
+        g.x0 = xg * W;
+        g.base = (long long)g.p * a.ldS + g.x0 +
+                 (axis == 1 ? (long long)g.o * a.mxp * a.my : (long long)g.o * a.mxp);
+        return g;
+    };
+    // butterfly g = 1..Q of task i (g = Q stands for j = 0)
+    auto task_g = [&](int i) { return (int)(threadIdx.x + i * NT) / W + 1; };
+    auto task_on = [&](int i) { return TASKS % NT == 0 || (int)(threadIdx.x + i * NT) < TASKS; };
+    T val[TPL][H];
+    double mux_next = 0.0, muo_next = 0.0;
+    double2 sg_next = double2{};
+    const unsigned long long sbytes = (unsigned long long)a.nP * a.ldS * sizeof(T);
+    // byte offset of value t (1..m) of the lane's column from the group base, or kNoLane
+    auto lane_off = [&](int t, bool ok) {
+        return ok ? (unsigned)(((long long)(t - 1) * st + wl) * (long long)sizeof(T)) : kNoLane;
+    };
+    auto fetch = [&](const Grp& g, bool live) {
+        const bool colok = live && g.x0 + wl < a.mx;
+        const long long b0 = live ? g.base : 0;
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + b0, live ? sbytes - (unsigned long long)b0 * sizeof(T) : 0);
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+            const int gg = task_g(i);
+#pragma unroll
+            for (int s = 0; s < H; ++s) {
+                const int t = gg + Q * s;
+                val[i][s] = buf_ld(rs, lane_off(t, colok && task_on(i) && t <= m), zero);
+            }
+        }
+        if (SOLVE) {
+            mux_next = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                      buf_rsrc(a.mu[0], (unsigned long long)a.mx * 8),
+                                                      (int)(colok ? (unsigned)(g.x0 + wl) * 8u : kNoLane), 0, 0));
+            sg_next = buf_ld(buf_rsrc(a.sigma, (unsigned long long)a.nP * 16), live ? (unsigned)g.p * 16u : kNoLane,
+                             double2{});
+            muo_next = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                      buf_rsrc(a.mu[1], (unsigned long long)a.my * 8),
+                                                      (int)(live && axis == 2 ? (unsigned)g.o * 8u : kNoLane), 0, 0));
+        }
+    };
+    // Odd sequences in natural layout sm[k W + col], k = 0..L/2 (k = 0 and L/2
+    // hold zero): the first stage's butterfly j takes its lower half from
+    // k = j + Q s and its upper half from k = (Q - j) + Q s, negated and
+    // reversed; it writes position j R0 + r after a barrier.
+    auto zero_ends = [&]() {
+        if (threadIdx.x < 2 * W) sm[((threadIdx.x < W) ? 0 : L / 2) * W + wl] = zero;
+    };
+    auto first_stage = [&]() {
+        T v[TPL][R0];
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+            if (!task_on(i)) continue;
+            const int j = task_g(i) % Q;
+#pragma unroll
+            for (int s2 = 0; s2 < H; ++s2) {
+                v[i][s2] = sm[(j + Q * s2) * W + wl];
+                const T p = sm[((Q - j) + Q * s2) * W + wl];
+                v[i][R0 - 1 - s2] = mk<T>(-p.x, -p.y);
+            }
+            SmallDft<R0, false, T>::run(v[i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+            if (!task_on(i)) continue;
+            const int j = task_g(i) % Q;
+#pragma unroll
+            for (int r = 0; r < R0; ++r) sm[(j * R0 + r) * W + wl] = v[i][r];
+        }
+        __syncthreads();
+    };
+    // Last stage (span Q): butterfly j = g mod Q reads y_{j + Q r}, twiddles
+    // w^{r j}, DFT; returns the lower half (k = j + Q r, r < H) in Y.
+    auto last_stage = [&](T (&Y)[TPL][H]) {
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+            if (!task_on(i)) continue;
+            const int j = task_g(i) % Q;
+            T v[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[r] = sm[(j + Q * r) * W + wl];
+            apply_twiddles<R0, false, T>(v, tw, j);
+            SmallDft<R0, false, T>::run(v);
+#pragma unroll
+            for (int r = 0; r < H; ++r) Y[i][r] = v[r];
+        }
+    };
+    auto middle = [&]() {
+        if constexpr (LMID > 0) fft_stage<R, LOGL, (1 << LMID), W, NT, false, true, 0, 0, 1>(sm, tw, R0, threadIdx.x);
+    };
+
+    long long gid = blockIdx.x;
+    if (gid < ngroups) fetch(decode(gid), true);
+    for (; gid < ngroups; gid += gridDim.x) {
+        const Grp g = decode(gid);
+        const double mux = mux_next, muo = muo_next;
+        const double2 sg = sg_next;
+        const bool colok = g.x0 + wl < a.mx;
+        // the loaded values x_t, t = g + Q s <= m, into the natural layout
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+            if (!task_on(i)) continue;
+            const int gg = task_g(i);
+#pragma unroll
+            for (int s2 = 0; s2 < H; ++s2) {
+                const int t = gg + Q * s2;
+                if (t <= m) sm[t * W + wl] = val[i][s2];
+            }
+        }
+        zero_ends();
+        __syncthreads();
+        // the next group's loads fly during this group's transforms
+        fetch(decode(gid + gridDim.x), gid + gridDim.x < ngroups);
+        first_stage();
+        middle();
+        T Y[TPL][H];
+        last_stage(Y);
+        if constexpr (SOLVE) {
+            const double base_re = sg.x + (axis == 2 ? muo : 0.0) + mux;
+            __syncthreads();   // every last-stage read is done before the natural-layout writes
+#pragma unroll
+            for (int i = 0; i < TPL; ++i) {
+                if (!task_on(i)) continue;
+                const int j = task_g(i) % Q;
+#pragma unroll
+                for (int r = 0; r < H; ++r) {
+                    const int k = j + Q * r;
+                    if (k >= 1 && k <= m) {
+                        // columns past the grid get 0 (a scalar factor: a select of the
+                        // complex value itself is lowered through scratch memory)
+                        const double dre = base_re + smu[k - 1];
+                        const double inv = colok ? a.inv_factor / (dre * dre + sg.y * sg.y) : 0.0;
+                        sm[k * W + wl] = cmul(Y[i][r], mk<T>((R)(dre * inv), (R)(-sg.y * inv)));
+                    }
+                }
+            }
+            zero_ends();
+            __syncthreads();
+            // the same raw transform again (the sine transform is its own inverse
+            // up to the factor folded into inv_factor, sign included)
+            first_stage();
+            middle();
+            last_stage(Y);
+        }
+        {
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + g.base, sbytes - (unsigned long long)g.base * sizeof(T));
+#pragma unroll
+            for (int i = 0; i < TPL; ++i) {
+                const int j = task_g(i) % Q;
+#pragma unroll
+                for (int r = 0; r < H; ++r) {
+                    const int t = j + Q * r;
+                    buf_st(rs, lane_off(t, colok && task_on(i) && t >= 1 && t <= m), Y[i][r]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Raw sine transform of any length (axes whose 2(m+1) is not a power of two),
 // by Bluestein's chirp-z identity jk = (j^2 + k^2 - (k-j)^2)/2:
 //   Y_k = sum_{t<L} y_t e^{-2 pi i t k/L} = c_k sum_t (y_t c_t) conj(c_{k-t}),
@@ -2243,16 +2463,40 @@ hipError_t rows_run(const SpaceArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+#ifndef PINT_COLS_FUSED
+#define PINT_COLS_FUSED 1
+#endif
+// Whether the y/z pass of length 2^LOGL with W columns and NT lanes takes the
+// kernel with the odd extension folded into the first and last FFT stages.
+// Butterflies of its first stage per workgroup: Q W.  It runs min(Q W, 512)
+// lanes with one butterfly per lane, or two of radix 8 (more spill registers).
+template <int LOGL, int W> constexpr int cols_fused_tasks() {
+    return fused_r0(LOGL) ? ((1 << LOGL) / fused_r0(LOGL)) * W : 0;
+}
+template <int LOGL, int W> constexpr bool cols_fused() {
+    return PINT_COLS_FUSED && fused_r0(LOGL) != 0 &&
+           cols_fused_tasks<LOGL, W>() <= (fused_r0(LOGL) == 16 ? 512 : 1024) && cols_fused_tasks<LOGL, W>() >= 64;
+}
+template <int LOGL, int W> constexpr int cols_fused_nt() {
+    return cols_fused_tasks<LOGL, W>() > 512 ? 512 : cols_fused_tasks<LOGL, W>();
+}
+
 template <typename R, int LOGL, int W, bool SOLVE>
 hipError_t cols_run(const SpaceArgs& a, int axis, hipStream_t st) {
     // tiles above 64 KB of LDS get 512 lanes so the FFT stages stay in registers
     // (FP64 tiles of 64 KB as well: measured faster with 8 waves per workgroup)
-    constexpr int NT = ((1 << LOGL) * W * (int)sizeof(cx<R>) > 65536 || sizeof(R) == 8) ? 512 : kNT;
+    constexpr bool FUSED = cols_fused<LOGL, W>();
+    constexpr int NT = FUSED ? cols_fused_nt<LOGL, W>()
+                             : (((1 << LOGL) * W * (int)sizeof(cx<R>) > 65536 || sizeof(R) == 8) ? 512 : kNT);
     const int other = axis == 1 ? a.mz : a.my;
     const long long groups = (long long)a.nP * other * ((a.mx + W - 1) / W);
-    const long long grid = std::min<long long>(
-        groups, persistent_blocks(reinterpret_cast<const void*>(&k_dst_cols<R, LOGL, W, NT, SOLVE>), NT));
-    PINT_LAUNCH((k_dst_cols<R, LOGL, W, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, axis);
+    auto kern = []() {
+        if constexpr (FUSED) return &k_dst_colsf<R, LOGL, W, NT, SOLVE>;
+        else return &k_dst_cols<R, LOGL, W, NT, SOLVE>;
+    };
+    const long long grid =
+        std::min<long long>(groups, persistent_blocks(reinterpret_cast<const void*>(kern()), NT));
+    PINT_LAUNCH(kern(), dim3((unsigned)grid), dim3(NT), 0, st, a, axis);
     return hipGetLastError();
 }
 

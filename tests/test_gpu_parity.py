@@ -74,6 +74,14 @@ SMALL = [
     # the longest supported grid lines (sine transforms of length 4096 along x, then along y)
     (2, (2047, 3), 8, 2, 1.0, 1e-2),
     (2, (3, 2047), 16, 3, 0.5, 1e-2),
+    # y/z passes whose odd extension is folded into the first and last FFT stages
+    # (lengths 256..2048, column groups cut by the end of the grid rows)
+    (2, (9, 127), 16, 2, 1.0, 1e-3),
+    (2, (5, 255), 16, 3, 0.5, 1e-3),
+    (2, (3, 511), 8, 2, 1.0, 1e-2),
+    (2, (6, 1023), 8, 2, 1.0, 1e-2),
+    (3, (5, 255, 3), 8, 2, 1.0, 1e-2),
+    (3, (3, 7, 255), 8, 2, 1.0, 1e-2),
 ]
 
 
