@@ -2444,10 +2444,31 @@ template <typename R> constexpr int rows_alt(int logl) {
     const int r = rows_per_block<R>(logl);
     return r >= 2 ? r / 2 : r;
 }
-// Columns per workgroup of the y/z pass: the built-in width, or (var_cols = 1)
-// twice it when the tile still fits 128 KB of LDS and 32 columns, else half.
-template <typename R> constexpr int cols_alt(int logl) {
-    const int w = cols_per_block<R>(logl);
+#ifndef PINT_COLS_FUSED
+#define PINT_COLS_FUSED 1
+#endif
+// Butterflies per workgroup in the first stage of the folded y/z kernel (Q W), and
+// whether that kernel takes W columns of length 2^logl: at most 512 lanes with one
+// butterfly each, or two of radix 8 (more spill registers).
+constexpr int fused_tasks(int logl, int w) { return fused_r0(logl) ? ((1 << logl) / fused_r0(logl)) * w : 0; }
+constexpr bool fused_ok(int logl, int w) {
+    return PINT_COLS_FUSED && fused_r0(logl) != 0 && fused_tasks(logl, w) >= 64 &&
+           fused_tasks(logl, w) <= (fused_r0(logl) == 16 ? 512 : 1024);
+}
+// Columns per workgroup of the y/z pass.  With the folded kernel: 16 columns for
+// the solve pass (256-byte FP64 / 128-byte FP32 row segments) and 32 for the
+// transform-only pass, or half that, when the tile fits 128 KB of LDS (the
+// fastest measured on the 2D and 3D workloads); otherwise the LDS-sized width.
+template <typename R, bool SOLVE> constexpr int cols_default(int logl) {
+    const int c0 = SOLVE ? 16 : 32;
+    for (int c = c0; c >= c0 / 2; c /= 2)
+        if ((1 << logl) * c * (int)sizeof(cx<R>) <= 131072 && fused_ok(logl, c)) return c;
+    return cols_per_block<R>(logl);
+}
+// The other width (var_cols = 1): twice the built-in one when the tile still
+// fits 128 KB of LDS and 32 columns, else half.
+template <typename R, bool SOLVE> constexpr int cols_alt(int logl) {
+    const int w = cols_default<R, SOLVE>(logl);
     if (2 * w <= 32 && (1 << logl) * 2 * w * (int)sizeof(cx<R>) <= 131072) return 2 * w;
     return w >= 2 ? w / 2 : w;
 }
@@ -2463,30 +2484,14 @@ hipError_t rows_run(const SpaceArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-#ifndef PINT_COLS_FUSED
-#define PINT_COLS_FUSED 1
-#endif
-// Whether the y/z pass of length 2^LOGL with W columns and NT lanes takes the
-// kernel with the odd extension folded into the first and last FFT stages.
-// Butterflies of its first stage per workgroup: Q W.  It runs min(Q W, 512)
-// lanes with one butterfly per lane, or two of radix 8 (more spill registers).
-template <int LOGL, int W> constexpr int cols_fused_tasks() {
-    return fused_r0(LOGL) ? ((1 << LOGL) / fused_r0(LOGL)) * W : 0;
-}
-template <int LOGL, int W> constexpr bool cols_fused() {
-    return PINT_COLS_FUSED && fused_r0(LOGL) != 0 &&
-           cols_fused_tasks<LOGL, W>() <= (fused_r0(LOGL) == 16 ? 512 : 1024) && cols_fused_tasks<LOGL, W>() >= 64;
-}
-template <int LOGL, int W> constexpr int cols_fused_nt() {
-    return cols_fused_tasks<LOGL, W>() > 512 ? 512 : cols_fused_tasks<LOGL, W>();
-}
 
 template <typename R, int LOGL, int W, bool SOLVE>
 hipError_t cols_run(const SpaceArgs& a, int axis, hipStream_t st) {
     // tiles above 64 KB of LDS get 512 lanes so the FFT stages stay in registers
     // (FP64 tiles of 64 KB as well: measured faster with 8 waves per workgroup)
-    constexpr bool FUSED = cols_fused<LOGL, W>();
-    constexpr int NT = FUSED ? cols_fused_nt<LOGL, W>()
+    // the folded kernel (lengths it covers) runs min(Q W, 512) lanes
+    constexpr bool FUSED = fused_ok(LOGL, W);
+    constexpr int NT = FUSED ? (fused_tasks(LOGL, W) > 512 ? 512 : fused_tasks(LOGL, W))
                              : (((1 << LOGL) * W * (int)sizeof(cx<R>) > 65536 || sizeof(R) == 8) ? 512 : kNT);
     const int other = axis == 1 ? a.mz : a.my;
     const long long groups = (long long)a.nP * other * ((a.mx + W - 1) / W);
@@ -2509,9 +2514,9 @@ hipError_t rows_one(const SpaceArgs& a, hipStream_t st) {
 
 template <typename R, int LOGL, bool SOLVE>
 hipError_t cols_one(const SpaceArgs& a, int axis, hipStream_t st) {
-    if (a.var_cols == 1 && cols_alt<R>(LOGL) != cols_per_block<R>(LOGL))
-        return cols_run<R, LOGL, cols_alt<R>(LOGL), SOLVE>(a, axis, st);
-    return cols_run<R, LOGL, cols_per_block<R>(LOGL), SOLVE>(a, axis, st);
+    if (a.var_cols == 1 && cols_alt<R, SOLVE>(LOGL) != cols_default<R, SOLVE>(LOGL))
+        return cols_run<R, LOGL, cols_alt<R, SOLVE>(LOGL), SOLVE>(a, axis, st);
+    return cols_run<R, LOGL, cols_default<R, SOLVE>(LOGL), SOLVE>(a, axis, st);
 }
 
 template <typename R, bool SOLVE = false>
@@ -2707,16 +2712,10 @@ bool rows_distinct(int logl) {
     return d[logl];
 }
 template <typename R>
-bool cols_distinct(int logl) {
+bool cols_distinct(int logl, bool solve) {
     if (logl < kMinLogL || logl > kMaxLogL) return false;
-    static const bool d[] = {false, false,
-                             cols_alt<R>(2) != cols_per_block<R>(2), cols_alt<R>(3) != cols_per_block<R>(3),
-                             cols_alt<R>(4) != cols_per_block<R>(4), cols_alt<R>(5) != cols_per_block<R>(5),
-                             cols_alt<R>(6) != cols_per_block<R>(6), cols_alt<R>(7) != cols_per_block<R>(7),
-                             cols_alt<R>(8) != cols_per_block<R>(8), cols_alt<R>(9) != cols_per_block<R>(9),
-                             cols_alt<R>(10) != cols_per_block<R>(10), cols_alt<R>(11) != cols_per_block<R>(11),
-                             cols_alt<R>(12) != cols_per_block<R>(12)};
-    return d[logl];
+    return solve ? cols_alt<R, true>(logl) != cols_default<R, true>(logl)
+                 : cols_alt<R, false>(logl) != cols_default<R, false>(logl);
 }
 int log2_of_pow2(unsigned v) { return (v & (v - 1)) == 0 ? __builtin_ctz(v) : -1; }
 }  // namespace
@@ -2741,7 +2740,8 @@ bool cols_variant_distinct(const SpaceArgs& a, bool mixed) {
         if (a.logP[axis] != 0) continue;
         const int m = axis == 1 ? a.my : a.mz;
         const int logl = log2_of_pow2(2u * (unsigned)(m + 1));
-        if (mixed ? cols_distinct<float>(logl) : cols_distinct<double>(logl)) return true;
+        const bool solve = axis == a.dim - 1;   // the last axis carries the divide
+        if (mixed ? cols_distinct<float>(logl, solve) : cols_distinct<double>(logl, solve)) return true;
     }
     return false;
 }
