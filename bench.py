@@ -347,7 +347,9 @@ def main():
                      "knobs": ["forward kernel", "x pass rows", "y pass columns", "1D tridiagonal split"]},
         "mixed": {k: out["mixed"][k] for k in ("value", "ms_per_step", "kernels_ms", "sweep_hbm_frac",
                                                "dominant")},
-        "time_to_1e-10": {p: {"sweeps": ttt[p]["sweeps"], "ms": ttt[p]["ms"]} for p in ttt},
+        # relative L2 error after each sweep (against the FP64 path converged to ~1e-14)
+        "time_to_1e-10": {p: {"sweeps": ttt[p]["sweeps"], "ms": ttt[p]["ms"],
+                              "rel_l2_per_sweep": [float("%.3g" % e) for e in ttt[p]["errors"]]} for p in ttt},
         "fp64_direct": {"ms_per_step": ms_d, "kernels_ms": {n: t for n, t in prof_d}},
     }
     if not args.no_other_configs:
