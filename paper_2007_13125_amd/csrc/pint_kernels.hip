@@ -1783,21 +1783,21 @@ __global__ __launch_bounds__(NT) void k_dst_cols(SpaceArgs a, int axis) {
 }
 
 // The same column pass with the odd extension folded into the first and last
-// FFT stages (lengths L = 2^8..2^11, with a radix schedule that starts and ends with
-// the same radix R0 = L / Q: 16 x 16, 8 x 8 x 8, 16 x 4 x 16, 16 x 8 x 16).  For an
-// odd sequence of length L (y_0 = y_{L/2} = 0,
-// y_{L-t} = -y_t), butterfly j of the first Stockham stage reads y_{j + Q r};
-// its upper half r >= R0/2 is minus the lower half of butterfly Q - j, reversed:
-// y_{j + Q r} = -x_{(Q - j) + Q (R0 - 1 - r)}.  So a lane loads only the values
-// x_{g + Q s}, s < R0/2, of its butterfly g (the last butterfly, g = Q, stands for
-// j = 0 and needs nothing else), trades them through LDS with butterfly Q - g,
-// and writes the first stage's outputs without the odd extension ever being
-// stored.  At the other end the last stage's butterfly j holds Y_{j + Q r}: its
-// lower half is the transform on k = 1..m, which is divided by the shift (SOLVE)
-// and traded the same way into the first stage of the second transform, or
-// (last stage of the last transform) stored straight from registers.  Per value
-// this moves ~10 LDS passes where k_dst_cols moves ~15 (solve) and ~3 where it
-// moves ~5.5 (transform only).
+// FFT stages (lengths L = 2^8..2^11, with a radix schedule that starts and ends
+// with the same radix R0 = L / Q: 16 x 16, 8 x 8 x 8, 16 x 4 x 16, 16 x 8 x 16).
+// For an odd sequence of length L (y_0 = y_{L/2} = 0, y_{L-t} = -y_t), butterfly
+// j of the first Stockham stage reads y_{j + Q r}; its upper half r >= R0/2 is
+// minus the lower half of butterfly Q - j, reversed:
+// y_{j + Q r} = -x_{(Q - j) + Q (R0 - 1 - r)}.  So the loaded values x_t,
+// t = 1..m, are written once in natural order (positions 0 and L/2 hold zero),
+// and butterfly j reads x at j + Q s and at (Q - j) + Q s, s < R0/2: the odd
+// extension is never stored, and no full-length read precedes the first stage.
+// At the other end the last stage's butterfly j holds Y_{j + Q r}, whose lower
+// half is the transform on k = 1..m: it is divided by the shift (SOLVE) and
+// written in natural order for the second transform, or (last stage of the last
+// transform) stored straight from registers.  That is two LDS passes fewer per
+// transform than k_dst_cols (5.5 instead of 7.5 per value for L = 512, 3.5
+// instead of 5.5 for L = 256), and one more fewer at the divide.
 constexpr int fused_r0(int logl) { return (logl == 8 || logl == 10 || logl == 11) ? 16 : (logl == 9 ? 8 : 0); }
 
 template <typename R, int LOGL, int W, int NT, bool SOLVE>
