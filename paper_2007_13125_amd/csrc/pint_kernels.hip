@@ -2002,6 +2002,148 @@ __global__ __launch_bounds__(NT) void k_dst_colsf(SpaceArgs a, int axis) {
     }
 }
 
+// The x pass without the divide, with the odd extension folded into the first
+// and last FFT stages as in k_dst_colsf (same radix schedules and butterfly
+// pairing), on the element-contiguous padded row layout of k_dst_rows: the row
+// values are written once in natural order, butterfly j of the first stage reads
+// positions j + Q s and (Q - j) + Q s, and the last stage's lower half is stored
+// straight from registers.  Butterfly (row b, j) of task i: j fastest, so the
+// stores of a wave cover consecutive positions of a row.
+template <typename R, int LOGL, int ROWS, int NT>
+__global__ __launch_bounds__(NT) void k_dst_rowsf(SpaceArgs a, long long nlines) {
+    using T = cx<R>;
+    constexpr int L = 1 << LOGL;
+    constexpr int PS = pad_shift(LOGL);
+    constexpr int LP = L + (L >> PS);            // padded sequence stride
+    constexpr int R0 = fused_r0(LOGL);
+    static_assert(R0 == 8 || R0 == 16, "length without a fused radix schedule");
+    constexpr int LR0 = R0 == 16 ? 4 : 3;
+    constexpr int HR = R0 / 2;
+    constexpr int Q = L / R0;
+    constexpr int LMID = LOGL - 2 * LR0;
+    static_assert(LMID == 0 || LMID == 2 || LMID == 3, "middle stage radix");
+    constexpr int TASKS = ROWS * Q;
+    constexpr int TPL = (TASKS + NT - 1) / NT;
+    static_assert(TASKS % NT == 0 || TASKS < NT, "whole butterflies per lane");
+    __shared__ T sm[ROWS * LP];
+    constexpr bool TWL = (ROWS * LP + L / 2) * (int)sizeof(T) <= 81920;
+    __shared__ T stw[TWL ? L / 2 : 1];
+    const T* tw = TWL ? stw : reinterpret_cast<const T*>(a.twL[0]);
+    if (TWL)
+        for (int j = threadIdx.x; j < L / 2; j += NT) stw[j] = reinterpret_cast<const T*>(a.twL[0])[j];
+    auto ix = [](int b, int t) { return b * LP + t + (t >> PS); };
+    const int m = a.mx;                          // = L/2 - 1
+    const int lpp = a.my * a.mz;
+    T* S = reinterpret_cast<T*>(a.S);
+    const T zero = mk<T>((R)0, (R)0);
+    const long long ngroups = (nlines + ROWS - 1) / ROWS;
+    constexpr int H = L / 2;
+    constexpr int LH = LOGL - 1;
+    constexpr int PER = (ROWS * H + NT - 1) / NT;
+    __shared__ long long rowoff[2][ROWS];
+    T val[PER];
+    auto offsets = [&](long long grp, int slot) {
+        if (threadIdx.x < ROWS) {
+            const long long g = grp * ROWS + threadIdx.x;
+            const unsigned gu = (unsigned)g;
+            rowoff[slot][threadIdx.x] =
+                g < nlines ? (long long)(gu / (unsigned)lpp) * a.ldS + (long long)(gu % (unsigned)lpp) * a.mxp : -1;
+        }
+    };
+    const unsigned long long sbytes = (unsigned long long)a.nP * a.ldS * sizeof(T);
+    auto first_row = [&](long long grp) {
+        const unsigned g = (unsigned)(grp * ROWS);
+        return (long long)(g / (unsigned)lpp) * a.ldS + (long long)(g % (unsigned)lpp) * a.mxp;
+    };
+    auto lane_off = [&](int slot, long long o0, int b, int t, bool ok) {
+        const long long off = rowoff[slot][b];
+        return (ok && off >= 0) ? (unsigned)((off - o0 + t) * (long long)sizeof(T)) : kNoLane;
+    };
+    auto fetch = [&](int slot, long long grp) {
+        const bool live = grp < ngroups;
+        const long long o0 = live ? first_row(grp) : 0;
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + o0, live ? sbytes - (unsigned long long)o0 * sizeof(T) : 0);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * NT;
+            const bool in = (ROWS * H) % NT == 0 || e < ROWS * H;
+            const int b = in ? e >> LH : 0, t = e & (H - 1);
+            val[i] = buf_ld(rs, lane_off(slot, o0, b, t, in && t < m), zero);
+        }
+    };
+    auto task_on = [&](int i) { return TASKS % NT == 0 || (int)(threadIdx.x + i * NT) < TASKS; };
+    auto task_b = [&](int i) { return (int)(threadIdx.x + i * NT) / Q; };
+    auto task_j = [&](int i) { return (int)(threadIdx.x + i * NT) % Q; };
+    long long grp = blockIdx.x;
+    int slot = 0;
+    if (grp < ngroups) {
+        offsets(grp, 0);
+        __syncthreads();
+        fetch(0, grp);
+    }
+    for (; grp < ngroups; grp += gridDim.x, slot ^= 1) {
+        // natural order: x_t at t = 1..m, zeros at 0 and L/2
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * NT;
+            const int b = e >> LH, t = (e & (H - 1)) + 1;
+            if (((ROWS * H) % NT == 0 || e < ROWS * H) && t <= m) sm[ix(b, t)] = val[i];
+        }
+        if (threadIdx.x < 2 * ROWS) {
+            const int b = threadIdx.x >> 1;
+            sm[ix(b, (threadIdx.x & 1) ? H : 0)] = zero;
+        }
+        offsets(grp + gridDim.x, slot ^ 1);
+        __syncthreads();
+        fetch(slot ^ 1, grp + gridDim.x);
+        // first stage (span 1) from the natural-order halves
+        {
+            T v[TPL][R0];
+#pragma unroll
+            for (int i = 0; i < TPL; ++i) {
+                if (!task_on(i)) continue;
+                const int b = task_b(i), j = task_j(i);
+#pragma unroll
+                for (int s2 = 0; s2 < HR; ++s2) {
+                    v[i][s2] = sm[ix(b, j + Q * s2)];
+                    const T p = sm[ix(b, (Q - j) + Q * s2)];
+                    v[i][R0 - 1 - s2] = mk<T>(-p.x, -p.y);
+                }
+                SmallDft<R0, false, T>::run(v[i]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < TPL; ++i) {
+                if (!task_on(i)) continue;
+                const int b = task_b(i), j = task_j(i);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) sm[ix(b, j * R0 + r)] = v[i][r];
+            }
+            __syncthreads();
+        }
+        if constexpr (LMID > 0)
+            fft_stage<R, LOGL, (1 << LMID), ROWS, NT, false, false, LP, PS, 1>(sm, tw, R0, threadIdx.x);
+        // last stage (span Q); its lower half Y_{j + Q r}, r < R0/2, is the transform on k = 1..m
+        const long long o0 = first_row(grp);
+        const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + o0, sbytes - (unsigned long long)o0 * sizeof(T));
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+            const int b = task_b(i), j = task_j(i);
+            T v[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[r] = task_on(i) ? sm[ix(b, j + Q * r)] : zero;
+            apply_twiddles<R0, false, T>(v, tw, j);
+            SmallDft<R0, false, T>::run(v);
+#pragma unroll
+            for (int r = 0; r < HR; ++r) {
+                const int t = j + Q * r;
+                buf_st(rs, lane_off(slot, o0, task_on(i) ? b : 0, t - 1, task_on(i) && t >= 1 && t <= m), v[r]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Raw sine transform of any length (axes whose 2(m+1) is not a power of two),
 // by Bluestein's chirp-z identity jk = (j^2 + k^2 - (k-j)^2)/2:
 //   Y_k = sum_{t<L} y_t e^{-2 pi i t k/L} = c_k sum_t (y_t c_t) conj(c_{k-t}),
@@ -2473,14 +2615,28 @@ template <typename R, bool SOLVE> constexpr int cols_alt(int logl) {
     return w >= 2 ? w / 2 : w;
 }
 
+#ifndef PINT_ROWS_FUSED
+#define PINT_ROWS_FUSED 1
+#endif
+// Whether the x pass without the divide takes the folded kernel: lengths with a
+// folded radix schedule, one butterfly per lane of 256 (two of radix 8).
+constexpr bool rows_fused_ok(int logl, int rows) {
+    return PINT_ROWS_FUSED && fused_r0(logl) != 0 && rows * ((1 << logl) / fused_r0(logl)) >= 64 &&
+           rows * ((1 << logl) / fused_r0(logl)) <= (fused_r0(logl) == 16 ? 256 : 512);
+}
+
 template <typename R, int LOGL, int ROWS, bool SOLVE>
 hipError_t rows_run(const SpaceArgs& a, hipStream_t st) {
     constexpr int NT = kNT;
     const long long nlines = (long long)a.nP * a.my * a.mz;
     const long long groups = (nlines + ROWS - 1) / ROWS;
-    const long long grid = std::min<long long>(groups, persistent_blocks(reinterpret_cast<const void*>(
-                                                           &k_dst_rows<R, LOGL, ROWS, NT, SOLVE>), NT));
-    PINT_LAUNCH((k_dst_rows<R, LOGL, ROWS, NT, SOLVE>), dim3((unsigned)grid), dim3(NT), 0, st, a, nlines);
+    auto kern = []() {
+        if constexpr (!SOLVE && rows_fused_ok(LOGL, ROWS)) return &k_dst_rowsf<R, LOGL, ROWS, NT>;
+        else return &k_dst_rows<R, LOGL, ROWS, NT, SOLVE>;
+    };
+    const long long grid =
+        std::min<long long>(groups, persistent_blocks(reinterpret_cast<const void*>(kern()), NT));
+    PINT_LAUNCH(kern(), dim3((unsigned)grid), dim3(NT), 0, st, a, nlines);
     return hipGetLastError();
 }
 

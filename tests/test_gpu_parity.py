@@ -82,6 +82,13 @@ SMALL = [
     (2, (6, 1023), 8, 2, 1.0, 1e-2),
     (3, (5, 255, 3), 8, 2, 1.0, 1e-2),
     (3, (3, 7, 255), 8, 2, 1.0, 1e-2),
+    # x passes with the folded odd extension (rows of 127..1023 points, row groups cut
+    # by the number of lines)
+    (2, (127, 3), 8, 2, 1.0, 1e-2),
+    (2, (255, 5), 16, 3, 0.5, 1e-2),
+    (2, (511, 3), 8, 2, 1.0, 1e-2),
+    (2, (1023, 3), 8, 2, 1.0, 1e-2),
+    (3, (127, 3, 3), 8, 2, 1.0, 1e-2),
 ]
 
 
