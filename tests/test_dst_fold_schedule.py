@@ -1,9 +1,11 @@
-"""CPU model of the index scheme of the y/z sine pass with the odd extension
-folded into the first and last FFT stages (k_dst_colsf): the same butterfly,
-partner and position formulas, applied with plain numpy DFTs, must give the raw
-sine transform -2i S x (S_kt = sin(pi k t/(m+1))) and, for the solve pass, the
-raw transform of the divided transform.  This pins the folding arithmetic
-(which half of which butterfly feeds which stage) independently of the GPU."""
+"""CPU model of the index scheme of the sine passes with the odd extension
+folded into the first and last FFT stages (k_dst_colsf for y/z columns,
+k_dst_rowsf for x rows; they differ only in the LDS layout of a line): the same
+butterfly, partner and position formulas, applied with plain numpy DFTs, must
+give the raw sine transform -2i S x (S_kt = sin(pi k t/(m+1))) and, for the
+solve pass, the raw transform of the divided transform.  This pins the folding
+arithmetic (which half of which butterfly feeds which stage) independently of
+the GPU."""
 import numpy as np
 import pytest
 
