@@ -2128,16 +2128,19 @@ __global__ __launch_bounds__(NT) void k_dst_rowsf(SpaceArgs a, long long nlines)
         const __amdgpu_buffer_rsrc_t rs = buf_rsrc(S + o0, sbytes - (unsigned long long)o0 * sizeof(T));
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
-            const int b = task_b(i), j = task_j(i);
+            // lanes without a butterfly read row 0 (in range) and store nothing; the
+            // row index is selected, not the loaded value (a select of the complex
+            // value itself is lowered through scratch memory)
+            const int b = task_on(i) ? task_b(i) : 0, j = task_j(i);
             T v[R0];
 #pragma unroll
-            for (int r = 0; r < R0; ++r) v[r] = task_on(i) ? sm[ix(b, j + Q * r)] : zero;
+            for (int r = 0; r < R0; ++r) v[r] = sm[ix(b, j + Q * r)];
             apply_twiddles<R0, false, T>(v, tw, j);
             SmallDft<R0, false, T>::run(v);
 #pragma unroll
             for (int r = 0; r < HR; ++r) {
                 const int t = j + Q * r;
-                buf_st(rs, lane_off(slot, o0, task_on(i) ? b : 0, t - 1, task_on(i) && t >= 1 && t <= m), v[r]);
+                buf_st(rs, lane_off(slot, o0, b, t - 1, task_on(i) && t >= 1 && t <= m), v[r]);
             }
         }
         __syncthreads();
@@ -2581,9 +2584,29 @@ hipError_t tri1d_dispatch(const SpaceArgs& a, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
-// Rows per workgroup of the x pass: the built-in count, or half of it (var_rows = 1).
-template <typename R> constexpr int rows_alt(int logl) {
+#ifndef PINT_ROWS_FUSED
+#define PINT_ROWS_FUSED 1
+#endif
+// Whether the x pass without the divide takes the folded kernel: lengths with a
+// folded radix schedule, one butterfly for each of the 256 lanes (two of radix 8);
+// with fewer butterflies than lanes the compiler's register use doubles.
+constexpr bool rows_fused_ok(int logl, int rows) {
+    return PINT_ROWS_FUSED && fused_r0(logl) != 0 && rows * ((1 << logl) / fused_r0(logl)) >= 256 &&
+           rows * ((1 << logl) / fused_r0(logl)) <= (fused_r0(logl) == 16 ? 256 : 512);
+}
+// Rows per workgroup of the x pass: the LDS-sized count, lowered for the
+// transform-only pass until the folded kernel takes it (faster than the plain
+// kernel with twice the rows on every measured grid).
+template <typename R, bool SOLVE> constexpr int rows_default(int logl) {
     const int r = rows_per_block<R>(logl);
+    if (SOLVE || fused_r0(logl) == 0) return r;
+    for (int c = r; c >= 1; c /= 2)
+        if (rows_fused_ok(logl, c)) return c;
+    return r;
+}
+// The built-in count, or half of it (var_rows = 1).
+template <typename R, bool SOLVE> constexpr int rows_alt(int logl) {
+    const int r = rows_default<R, SOLVE>(logl);
     return r >= 2 ? r / 2 : r;
 }
 #ifndef PINT_COLS_FUSED
@@ -2613,16 +2636,6 @@ template <typename R, bool SOLVE> constexpr int cols_alt(int logl) {
     const int w = cols_default<R, SOLVE>(logl);
     if (2 * w <= 32 && (1 << logl) * 2 * w * (int)sizeof(cx<R>) <= 131072) return 2 * w;
     return w >= 2 ? w / 2 : w;
-}
-
-#ifndef PINT_ROWS_FUSED
-#define PINT_ROWS_FUSED 1
-#endif
-// Whether the x pass without the divide takes the folded kernel: lengths with a
-// folded radix schedule, one butterfly per lane of 256 (two of radix 8).
-constexpr bool rows_fused_ok(int logl, int rows) {
-    return PINT_ROWS_FUSED && fused_r0(logl) != 0 && rows * ((1 << logl) / fused_r0(logl)) >= 64 &&
-           rows * ((1 << logl) / fused_r0(logl)) <= (fused_r0(logl) == 16 ? 256 : 512);
 }
 
 template <typename R, int LOGL, int ROWS, bool SOLVE>
@@ -2663,9 +2676,9 @@ hipError_t cols_run(const SpaceArgs& a, int axis, hipStream_t st) {
 
 template <typename R, int LOGL, bool SOLVE>
 hipError_t rows_one(const SpaceArgs& a, hipStream_t st) {
-    if (a.var_rows == 1 && rows_alt<R>(LOGL) != rows_per_block<R>(LOGL))
-        return rows_run<R, LOGL, rows_alt<R>(LOGL), SOLVE>(a, st);
-    return rows_run<R, LOGL, rows_per_block<R>(LOGL), SOLVE>(a, st);
+    if (a.var_rows == 1 && rows_alt<R, SOLVE>(LOGL) != rows_default<R, SOLVE>(LOGL))
+        return rows_run<R, LOGL, rows_alt<R, SOLVE>(LOGL), SOLVE>(a, st);
+    return rows_run<R, LOGL, rows_default<R, SOLVE>(LOGL), SOLVE>(a, st);
 }
 
 template <typename R, int LOGL, bool SOLVE>
@@ -2856,16 +2869,10 @@ int fwd_kind_of(const FwdArgs& a, bool cq) {
     }
 }
 template <typename R>
-bool rows_distinct(int logl) {
+bool rows_distinct(int logl, bool solve) {
     if (logl < kMinLogL || logl > kMaxLogL) return false;
-    static const bool d[] = {false, false,
-                             rows_alt<R>(2) != rows_per_block<R>(2), rows_alt<R>(3) != rows_per_block<R>(3),
-                             rows_alt<R>(4) != rows_per_block<R>(4), rows_alt<R>(5) != rows_per_block<R>(5),
-                             rows_alt<R>(6) != rows_per_block<R>(6), rows_alt<R>(7) != rows_per_block<R>(7),
-                             rows_alt<R>(8) != rows_per_block<R>(8), rows_alt<R>(9) != rows_per_block<R>(9),
-                             rows_alt<R>(10) != rows_per_block<R>(10), rows_alt<R>(11) != rows_per_block<R>(11),
-                             rows_alt<R>(12) != rows_per_block<R>(12)};
-    return d[logl];
+    return solve ? rows_alt<R, true>(logl) != rows_default<R, true>(logl)
+                 : rows_alt<R, false>(logl) != rows_default<R, false>(logl);
 }
 template <typename R>
 bool cols_distinct(int logl, bool solve) {
@@ -2888,7 +2895,8 @@ bool rows_variant_distinct(const SpaceArgs& a, bool mixed) {
     const bool has_rows = a.dim == 1 ? dst1d(a) : a.logP[0] == 0;
     if (!has_rows) return false;
     const int logl = log2_of_pow2(2u * (unsigned)(a.mx + 1));
-    return mixed ? rows_distinct<float>(logl) : rows_distinct<double>(logl);
+    const bool solve = a.dim == 1;   // the 1D pass carries the divide
+    return mixed ? rows_distinct<float>(logl, solve) : rows_distinct<double>(logl, solve);
 }
 
 bool cols_variant_distinct(const SpaceArgs& a, bool mixed) {
