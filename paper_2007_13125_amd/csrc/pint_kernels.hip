@@ -1387,14 +1387,35 @@ __global__ __launch_bounds__(NT, PINT_INV_WAVES) void k_inv(InvArgs a) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_norm_reduce(const double* __restrict__ partial, int nb, double hd,
-                                                     double* __restrict__ out) {
-    __shared__ double red[2][4];
+// One workgroup of 1024 lanes; each lane has eight partial pairs in flight
+// before it uses any (a loop of dependent loads made the reduction of the
+// 64K partials of a 3D sweep take 0.2 ms).  Fixed order: per lane, then across
+// a wave by butterfly, then across waves, so the result is deterministic.
+constexpr int kNormNT = 1024;
+__global__ __launch_bounds__(kNormNT) void k_norm_reduce(const double* __restrict__ partial, int nb, double hd,
+                                                         double* __restrict__ out) {
+    __shared__ double red[2][kNormNT / 64];
     const int tid = threadIdx.x;
+    const double2* p2 = reinterpret_cast<const double2*>(partial);   // (max |delta|, sum delta^2) pairs
     double mx = 0.0, s2 = 0.0;
-    for (int i = tid; i < nb; i += 256) {
-        mx = nanmax(mx, partial[2 * i]);
-        s2 += partial[2 * i + 1];
+    for (int base = 0; base < nb; base += 8 * kNormNT) {
+        double vx[8], vy[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = base + k * kNormNT + tid;
+            vx[k] = 0.0;
+            vy[k] = 0.0;
+            if (i < nb) {
+                const double2 t = p2[i];
+                vx[k] = t.x;
+                vy[k] = t.y;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            mx = nanmax(mx, vx[k]);
+            s2 += vy[k];
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -1408,7 +1429,7 @@ __global__ __launch_bounds__(256) void k_norm_reduce(const double* __restrict__ 
     __syncthreads();
     if (tid == 0) {
         double m0 = red[0][0], t0 = red[1][0];
-        for (int i = 1; i < 4; ++i) {
+        for (int i = 1; i < kNormNT / 64; ++i) {
             m0 = nanmax(m0, red[0][i]);
             t0 += red[1][i];
         }
@@ -2848,7 +2869,7 @@ hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st) {
 void set_prepare_only(bool on) { g_prepare_only = on; }
 
 hipError_t launch_norm_reduce(const double* partial, int nb, double hd, double* out, hipStream_t st) {
-    PINT_LAUNCH(k_norm_reduce, dim3(1), dim3(256), 0, st, partial, nb, hd, out);
+    PINT_LAUNCH(k_norm_reduce, dim3(1), dim3(kNormNT), 0, st, partial, nb, hd, out);
     return hipGetLastError();
 }
 
