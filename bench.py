@@ -1,20 +1,28 @@
 """Benchmark of the diagonalized waveform-relaxation sweep on one MI355X.
 
 One step = one whole WR sweep (residual + kappa scaling + forward time FFT,
-spatial shifted solves, inverse time FFT + unscale + update + norms) over the
-2D heat workload: 5-point FD Laplacian on 255 x 255 interior nodes, BDF4,
-T = 1, N = 512, kappa = 1e-5, seeded smooth sine-series data.  Inputs are
-resident in HBM before the timed region.
+spatial shifted solves, inverse time FFT + unscale + update + norms).  The
+headline workload is the largest one that fits one GPU: 3D heat, 7-point FD
+Dirichlet Laplacian on 127^3 interior nodes, BDF6, T = 1, N = 256,
+kappa = 1e-6, seeded smooth sine-series data (5.2e8 space-time unknowns).
+Inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line with the FP64 sweep throughput (space-time unknown
-updates per second) as `value`, the mixed FP32/FP64 sweep alongside,
-per-kernel device times from HIP events recorded on the plan's stream inside
-the timed region, the HBM roofline of the dominant kernel, time-to-1e-10 for
-both precisions, and the CPU oracle timed on a bounded sample.
+Prints ONE JSON line: the FP64 sweep throughput (space-time unknown-updates
+per second) as `value`; the mixed FP32/FP64 and FP64 direct-form sweeps
+alongside; per-launch device times from HIP events recorded on the plan's
+stream inside the timed region (repeated passes listed in launch order and
+summed per pass name); the HBM roofline of the dominant kernel; time-to-1e-10
+against the FP64 CPU oracle for FP64 residual, FP64 direct and mixed; the same
+figures for the 2D heat (255^2 x 512, BDF4) and 2D subdiffusion (511^2 x 1024,
+CQ-BDF3) workloads; sweeps/s and time-to-1e-12 of the 1D heat workload
+(63 x 64, BDF2); and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -24,51 +32,96 @@ if ROOT not in sys.path:
 
 METRIC = "space-time unknown-updates/s per WR sweep + time-to-1e-10, FP64 vs mixed; %HBM"
 HBM_PEAK_GBS = 8000.0
+HEADLINE = "heat3d"
+SWEEP_WORKLOADS = ("heat3d", "heat2d", "subdiff2d")
+KERNEL_SOURCES = ["paper_2007_13125_amd/csrc/pint_device.h", "paper_2007_13125_amd/csrc/pint_forward.hip",
+                  "paper_2007_13125_amd/csrc/pint_space.hip", "paper_2007_13125_amd/csrc/pint_time.hip"]
+COPY_BYTES = 256 << 20
+DESCR = {
+    "heat3d": "3D heat, 7-point FD Dirichlet Laplacian 127^3, BDF6 (Table 1 corrections), T=1, N=256, kappa=1e-6",
+    "heat2d": "2D heat, 5-point FD Dirichlet Laplacian 255^2, BDF4 (Table 1 corrections), T=1, N=512, kappa=1e-5",
+    "subdiff2d": "2D subdiffusion, Caputo alpha=1/2, CQ-BDF3, 5-point FD 511^2, T=1, N=1024, kappa=1e-4, f=0, "
+                 "indicator + noise initial value",
+    "heat1d": "1D heat, 3-point FD m=63, BDF2, T=1, N=64, kappa=1e-3",
+}
 
+
+def profile_stem(w):
+    dims = "x".join(str(m) for m in w.m)
+    tag = f"bdf{w.k}" if w.alpha == 1.0 else f"cqbdf{w.k}"
+    return os.path.join(ROOT, "profiles", f"{w.name}_{dims}_N{w.N}_{tag}")
+
+
+def sources_sha():
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    return h.hexdigest()
+
+
+# ---------------------------------------------------------------------------------------
+# algorithmic bytes
 
 def spectrum_bytes(N, M, mixed):
     return (N // 2 + 1) * M * (8 if mixed else 16)
 
 
-def kernel_bytes(name, N, M, mixed, has_f):
-    """Algorithmic HBM bytes of one launch (each array read or written once)."""
+def slot_bytes(name, w, mixed):
+    """Algorithmic HBM bytes of one launch of a pass (each array read or written once)."""
+    N, M = w.N, w.M
     S = spectrum_bytes(N, M, mixed)
     if name.startswith("forward"):
-        return 8 * N * M + (8 * N * M if has_f else 0) + 8 * M + S   # U, f, v in; spectrum out
+        return 8 * N * M + (8 * N * M if w.f is not None else 0) + 8 * M + S   # U, f, v in; spectrum out
+    if name == "direct_rhs_spectrum":
+        return 2 * S + 8 * w.k * M                                            # source spectrum, k rows of U
     if name.startswith("inverse"):
-        return S + 16 * N * M                                       # spectrum in; U in and out
+        return S + 16 * N * M                                                 # spectrum in; U in and out
     if name == "norm_reduce":
         return 0
-    return 2 * S                                                    # spatial pass: spectrum in and out
+    return 2 * S                                                              # spatial pass: in place
 
 
-def measured_traffic(precision, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE record, or None when the kernel source changed since it was taken."""
-    import hashlib
-    rec_path = PROFILE_STEM + "_traffic.json"
+def three_stage_bytes(w, mixed):
+    """The method's floor with its two time <-> space transposes: U, f in, U out, and
+    the half spectrum written and read twice (24 + 4c bytes per unknown, c = bytes per
+    half-spectrum value per unknown; 16 + 4c when f = 0)."""
+    N, M = w.N, w.M
+    return 8 * N * M * (3 if w.f is not None else 2) + 2 * spectrum_bytes(N, M, mixed)
+
+
+def measured_traffic(w, precision, slot):
+    """HBM bytes per launch of a pass from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record of this workload, or None when that record is missing or the
+    kernel sources changed since it was taken."""
     try:
-        rec = json.load(open(rec_path))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        rec = json.load(open(profile_stem(w) + "_traffic.json"))
+        if rec["sources_sha256"] != sources_sha():
             return None
-        k = rec["kernels"][precision][kernel]
+        k = rec["kernels"][precision][slot]
         return k["read"] + k["write"]
     except (OSError, KeyError, ValueError):
         return None
 
 
-def run_precision(w, precision, steps, warmup, form="residual", tune=True):
+# ---------------------------------------------------------------------------------------
+# GPU runs
+
+def to_dev(a):
+    import torch
+    return None if a is None else torch.from_numpy(a).to("cuda")
+
+
+def run_variant(w, precision, form, steps, warmup, tune):
+    """Plan + bound data + a U; the timed region is `steps` sweeps with a HIP event
+    pair around every launch on the plan's stream.  Returns (plan, U, ms_per_step,
+    slots [(pass, ms per launch)] in launch order, variants)."""
     import torch
 
     from paper_2007_13125_amd.binding import Plan
-    dev = torch.device("cuda")
-    v = torch.from_numpy(w.v).to(dev)
-    f = torch.from_numpy(w.f).to(dev) if w.f is not None else None
-    fd = torch.from_numpy(w.fder).to(dev) if w.fder is not None else None
+    data = (to_dev(w.v), to_dev(w.f), to_dev(w.fder))
     plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-14, max_sweeps=30, precision=precision, form=form)
-    plan.bind(v, f, fd)
-    U = torch.empty((w.N, w.M), dtype=torch.float64, device=dev)
+    plan.bind(*data)
+    U = torch.empty((w.N, w.M), dtype=torch.float64, device="cuda")
     plan.init_iterate(U)
     # kernel variants chosen by the library's autotuner (plan setup, outside the timed region)
     variants = plan.tune(U, 3) if tune else plan.variants()
@@ -77,78 +130,211 @@ def run_precision(w, precision, steps, warmup, form="residual", tune=True):
         plan.sweeps(U, warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prof = plan.profile(U, steps)          # the timed region: HIP events around every launch
+    slots = plan.profile(U, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) / steps * 1e3
-    return plan, (v, f, fd), ms_per_step, prof, variants
+    return plan, U, (t1 - t0) / steps * 1e3, slots, variants
 
 
-def time_to_tol(w, plan, data, Uref, tol=1e-10, max_sweeps=12):
-    """Sweeps m* until the trajectory is within tol (relative L2) of Uref, found in an
-    untimed validation run; then the wall time of exactly m* sweeps from U_0."""
+def slot_summary(slots):
+    by = {}
+    for n, t in slots:
+        by[n] = by.get(n, 0.0) + t
+    return {"launches": [[n, t] for n, t in slots], "per_pass": by}
+
+
+def roofline_of(w, precision, slots):
+    mixed = precision == "mixed"
+    dom = max(slots, key=lambda s: s[1])
+    b = slot_bytes(dom[0], w, mixed)
+    gbs = b / (dom[1] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom[0], "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(w, precision, dom[0]), "alg_bytes": b,
+            "ms": dom[1]}
+
+
+def sampler(w):
+    """GPU-side sample of a trajectory that the oracle evaluates one by one: the
+    values at 4096 seeded dofs (heat: the data are finite sine series), or the
+    coefficients of 16 x 16 sine modes of every level (subdiffusion), or the whole
+    trajectory (1D heat)."""
+    import numpy as np
     import torch
-    U = torch.empty_like(Uref)
+    if w.name == "heat1d":
+        return None, (lambda U: U.cpu().numpy())
+    if w.name == "subdiff2d":
+        mx, my = w.m
+        sx = np.sin(np.pi * np.outer(np.arange(1, mx + 1), MODE_IDX + 1) / (mx + 1))
+        sy = np.sin(np.pi * np.outer(np.arange(1, my + 1), MODE_IDX + 1) / (my + 1))
+        tx, ty = to_dev(sx), to_dev(sy)
+        c = 4.0 / ((mx + 1) * (my + 1))
+
+        def proj(U):
+            a = U.view(w.N, my, mx) @ tx                            # [N, y, i]
+            return (c * (a.transpose(1, 2) @ ty)).reshape(w.N, -1).cpu().numpy()
+        return None, proj
+    dofs = np.random.default_rng(0).choice(w.M, 4096, replace=False)
+    di = torch.from_numpy(dofs).to("cuda")
+    return dofs, (lambda U: U.index_select(1, di).cpu().numpy())
+
+
+MODE_IDX = None  # set in main (numpy array of sampled sine-mode indices, 0-based)
+
+
+def time_to_tol(plan, U, sample, ref, tol, max_sweeps=12):
+    """Sweeps m* until the sampled trajectory is within tol (relative L2) of the
+    oracle, found in an untimed validation run with a snapshot after every sweep;
+    then the wall time of exactly m* sweeps from U_0 (best of three)."""
+    import numpy as np
+    import torch
     plan.init_iterate(U)
-    nref = torch.linalg.norm(Uref).item()
+    nref = np.linalg.norm(ref)
     mstar, errs = None, []
     for s in range(1, max_sweeps + 1):
         plan.sweeps(U, 1)
-        e = (torch.linalg.norm(U - Uref).item()) / nref
+        e = float(np.linalg.norm(sample(U) - ref) / nref)
         errs.append(e)
         if e <= tol:
             mstar = s
             break
-    if mstar is None:
-        return {"sweeps": None, "ms": None, "errors": errs}
-    best = float("inf")
-    for _ in range(3):
-        plan.init_iterate(U)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.sweeps(U, mstar)
-        torch.cuda.synchronize()
-        best = min(best, time.perf_counter() - t0)
-    return {"sweeps": mstar, "ms": best * 1e3, "errors": errs}
-
-
-def other_configs(steps, tune):
-    """The other multi-dimensional workloads of the method's evaluation (parity-test
-    cases, not bench lines): tuned sweep time per precision and its algorithmic
-    HBM fraction."""
-    import torch
-
-    from paper_2007_13125_amd import workloads as wl
-    out = {}
-    for name in ("subdiff2d", "heat3d"):
-        w = getattr(wl, name)()
-        entry = {"grid": list(w.m), "N": w.N, "k": w.k, "alpha": w.alpha, "kappa": w.kappa, "unknowns": w.N * w.M}
-        for precision in ("fp64", "mixed"):
-            plan, _, ms, prof, var = run_precision(w, precision, steps, 1, tune=tune)
-            mixed = precision == "mixed"
-            nbytes = sum(kernel_bytes(n, w.N, w.M, mixed, w.f is not None) for n, _ in prof)
-            entry[precision] = {"ms_per_step": ms, "value": w.N * w.M / (ms * 1e-3),
-                                "sweep_hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                "kernels_ms": {n: t for n, t in prof}, "variants": var}
-            plan.close()
-            torch.cuda.empty_cache()
-        out[name] = entry
+    out = {"sweeps": mstar, "ms": None, "rel_l2_per_sweep": [float("%.3g" % e) for e in errs]}
+    if mstar is not None:
+        best = float("inf")
+        for _ in range(3):
+            plan.init_iterate(U)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.sweeps(U, mstar)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        out["ms"] = best * 1e3
     return out
 
 
-def cpu_baseline(seconds_hint=20.0):
-    """The FP64 oracle's dense-DFT sweep (Algorithm 1 with dense DFT matrices and
-    sparse LU per frequency), timed on a bounded sample: the same recipe on a
-    63 x 63 grid with the same N = 512 and BDF4."""
+def bench_workload(w, args, refs):
+    import torch
+    entry = {"workload": DESCR[w.name], "grid": list(w.m), "N": w.N, "k": w.k, "alpha": w.alpha,
+             "kappa": w.kappa, "unknowns": w.N * w.M}
+    dofs, sample = sampler(w)
+    for precision, form in (("fp64", "residual"), ("mixed", "residual"), ("fp64", "direct")):
+        key = precision if form == "residual" else "fp64_direct"
+        print(f"[bench] {w.name} {key}", file=sys.stderr, flush=True)
+        plan, U, ms, slots, var = run_variant(w, precision, form, args.steps, args.warmup, not args.no_tune)
+        mixed = precision == "mixed"
+        asb = sum(slot_bytes(n, w, mixed) for n, _ in slots)
+        e = {"ms_per_step": ms, "value": w.N * w.M / (ms * 1e-3), "kernels_ms": slot_summary(slots),
+             "hbm_frac_as_built": asb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "hbm_frac_3stage": three_stage_bytes(w, mixed) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "roofline": roofline_of(w, precision, slots), "variants": var}
+        if refs is not None and w.name in refs:
+            e["time_to_1e-10"] = time_to_tol(plan, U, sample, refs[w.name], 1e-10)
+        entry[key] = e
+        plan.close()
+        del U
+        torch.cuda.empty_cache()
+    return entry
+
+
+def bench_heat1d(args, refs):
+    """The small 1D workload: launch-bound (4032 unknowns); sweeps/s and the time to a
+    trajectory within 1e-12 of the oracle, FP64 residual form."""
+    import torch
+
+    from paper_2007_13125_amd import workloads as wl
+    w = wl.heat1d()
+    plan, U, ms, slots, var = run_variant(w, "fp64", "residual", max(args.steps, 50), args.warmup, False)
+    e = {"workload": DESCR["heat1d"], "unknowns": w.N * w.M, "ms_per_step": ms, "sweeps_per_s": 1e3 / ms,
+         "kernels_ms": slot_summary(slots)}
+    if refs is not None:
+        e["time_to_1e-12"] = time_to_tol(plan, U, sampler(w)[1], refs["heat1d"], 1e-12, 20)
+    plan.close()
+    torch.cuda.synchronize()
+    return e
+
+
+# ---------------------------------------------------------------------------------------
+# CPU leg: the FP64 oracle (test infrastructure) timed on a bounded sample of the
+# headline workload, and the oracle's values that time-to-tolerance is measured against
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def modal_reference(w, dofs):
+    """The sequential oracle (O1) in sine-mode space for data that are finite sine
+    series: each mode evolves by the scalar scheme with the sum of its axis
+    eigenvalues; the trajectory is assembled at the sampled dofs."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    from oracle.grid import Grid, sine_eigenvalues
+    from oracle.sequential import sequential
+    from paper_2007_13125_amd.workloads import _cos_profile_derivs
+    g = Grid(w.m)
+    cv, cf = w.modes["v"], w.modes["f"]
+    shape = cv.shape
+    mus = [sine_eigenvalues(g.m[a], g.h[a])[:shape[a]] for a in range(g.dim)]
+    mu = sum(np.meshgrid(*mus, indexing="ij")).reshape(-1)
+    f, fder = _cos_profile_derivs(w.N, w.T, w.k, cf.reshape(-1))
+    C = sequential(sp.diags(mu), w.k, w.alpha, w.T, w.N, cv.reshape(-1), f, fder)
+    rem, coords = np.asarray(dofs), []
+    for a in range(g.dim):
+        coords.append(rem % g.m[a])
+        rem = rem // g.m[a]
+    phi = np.ones((C.shape[1], len(dofs)))
+    idx = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    for a in range(g.dim):
+        phi *= np.sin(np.pi * np.outer(idx[a].reshape(-1) + 1, coords[a] + 1) / (g.m[a] + 1))
+    return C @ phi
+
+
+def subdiff_modal_reference(w):
+    """O1 on the sampled sine modes of the subdiffusion workload, from the modes'
+    coefficients of v (every mode of A_h evolves by the scalar scheme)."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    from oracle.grid import sine_eigenvalues
+    from oracle.sequential import sequential
+    mx, my = w.m
+    sx = np.sin(np.pi * np.outer(np.arange(1, mx + 1), MODE_IDX + 1) / (mx + 1))
+    sy = np.sin(np.pi * np.outer(np.arange(1, my + 1), MODE_IDX + 1) / (my + 1))
+    cv = 4.0 / ((mx + 1) * (my + 1)) * (sx.T @ w.v.reshape(my, mx).T @ sy)
+    mu = (sine_eigenvalues(mx, 1.0 / (mx + 1))[MODE_IDX][:, None]
+          + sine_eigenvalues(my, 1.0 / (my + 1))[MODE_IDX][None, :]).reshape(-1)
+    return sequential(sp.diags(mu), w.k, w.alpha, w.T, w.N, cv.reshape(-1), None, None)
+
+
+def cpu_leg(workloads, seconds_hint=12.0):
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle.grid import Grid, laplacian
+    from oracle.sequential import sequential
     from oracle.sweep import Problem
     from paper_2007_13125_amd import workloads as wl
-    w = wl.heat2d(m=(63, 63))
-    prob = Problem(laplacian(Grid(w.m)), w.k, w.alpha, w.T, w.N, w.kappa, w.v, w.f, w.fder)
-    U = np.tile(w.v, (w.N, 1))
+    refs = {}
+    for name, w in workloads.items():
+        if name == "subdiff2d":
+            refs[name] = subdiff_modal_reference(w)
+        elif name == "heat1d":
+            refs[name] = sequential(laplacian(Grid(w.m)), w.k, w.alpha, w.T, w.N, w.v, w.f, w.fder)
+        else:
+            refs[name] = modal_reference(w, sampler_dofs(w))
+    # timed sample of the headline recipe: 11^3 grid, same N, k, kappa
+    s = wl.heat3d(m=(11, 11, 11))
+    A = laplacian(Grid(s.m))
+    t0 = time.perf_counter()
+    sequential(A, s.k, s.alpha, s.T, s.N, s.v, s.f, s.fder)
+    t_o1 = time.perf_counter() - t0
+    prob = Problem(A, s.k, s.alpha, s.T, s.N, s.kappa, s.v, s.f, s.fder)
+    U = np.tile(s.v, (s.N, 1))
     reps, t = 0, 0.0
     while t < seconds_hint and reps < 5:
         t0 = time.perf_counter()
@@ -156,39 +342,47 @@ def cpu_baseline(seconds_hint=20.0):
         t += time.perf_counter() - t0
         reps += 1
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": w.N * w.M * reps / t, "unit": "unknown-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} residual sweep(s) of the dense-DFT oracle on the 63x63 grid, N=512, BDF4 "
-                      f"(same recipe as the timed workload); {t:.1f} s; host logical CPUs {os.cpu_count()}"}
+    base = {"value": s.N * s.M * reps / t, "unit": "unknown-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} residual sweep(s) of the dense-DFT oracle (Algorithm 1, all N frequencies, "
+                      f"refined sparse LU per frequency) on the headline recipe at 11^3 interior nodes, N=256, "
+                      f"BDF6, kappa=1e-6: {t:.1f} s; the sequential oracle's time to solution on the same "
+                      f"sample {t_o1:.2f} s ({s.N * s.M / t_o1:.3g} unknowns/s)",
+            "o1_seconds": t_o1, "o2_seconds_per_sweep": t / reps, "cpu_model": cpu_model(),
+            "logical_cpus": os.cpu_count()}
+    return base, refs
 
 
-PROFILE_STEM = os.path.join(ROOT, "profiles", "heat2d_255x255_N512_bdf4")
-KERNEL_SOURCE = "paper_2007_13125_amd/csrc/pint_kernels.hip"
-COPY_BYTES = 256 << 20
+def sampler_dofs(w):
+    import numpy as np
+    return np.random.default_rng(0).choice(w.M, 4096, replace=False)
 
 
-def slot_of(kernel):
-    """Profile slot of a kernel symbol of the 2D sweep (bench workload)."""
-    if "k_fwd_" in kernel:
-        return "forward_rhs_tfft"
+# ---------------------------------------------------------------------------------------
+# profile summaries (rocprofv3 CSV -> profiles/<workload>_{kernels.md,traffic.json})
+
+def slot_of(kernel, dim):
+    if "k_fwd_" in kernel or "k_inject" in kernel:
+        return "forward_cq_rhs_tfft" if "k_fwd_cq" in kernel else "forward_rhs_tfft"
     if "k_dst_rows" in kernel:
         return "dst_x"
     if "k_dst_cols" in kernel:
-        return "dst_y_solve"
+        return ("dst_y_solve" if dim == 2 else None)
     if "k_inv" in kernel:
         return "inverse_tfft_update"
     return None
 
 
-def summarize(outdir):
-    """Write the committed profile summary (markdown) and the HBM traffic record
-    that bench.py reads, from rocprofv3 CSV output of the three runs listed in
-    the summary: <outdir>/trace (--kernel-trace --stats), <outdir>/FETCH_SIZE and
-    <outdir>/WRITE_SIZE (--pmc), each of `bench.py --steps 5 --warmup 1
-    --no-cpu-baseline --copy-calibration`."""
+def summarize(outdir, name):
+    """Write the committed profile summary (markdown) and the HBM traffic record of
+    one workload from rocprofv3 CSV output of the three runs listed in the summary:
+    <outdir>/trace (--kernel-trace --stats), <outdir>/FETCH_SIZE, <outdir>/WRITE_SIZE
+    (--pmc), each of `bench.py --only <name> --steps 5 --warmup 1 --no-cpu-baseline
+    --copy-calibration`."""
     import csv
-    import glob
-    import hashlib
     from collections import defaultdict
+
+    from paper_2007_13125_amd import workloads as wl
+    w = getattr(wl, name)()
 
     def rows(sub, suffix):
         paths = glob.glob(os.path.join(outdir, sub, "**", "*" + suffix), recursive=True)
@@ -196,10 +390,10 @@ def summarize(outdir):
             raise SystemExit(f"no *{suffix} under {os.path.join(outdir, sub)}")
         return list(csv.DictReader(open(paths[0])))
 
-    def short(name):
+    def short(k):
         for pre in ("void ", "pint::", "(anonymous namespace)::"):
-            name = name.replace(pre, "")
-        return name.split("(")[0]
+            k = k.replace(pre, "")
+        return k.split("(")[0]
 
     stats = rows("trace", "kernel_stats.csv")
     counters = {}
@@ -208,156 +402,123 @@ def summarize(outdir):
         for r in rows(c, "counter_collection.csv"):
             per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         counters[c] = per
-    # calibration: the largest device copy (the 256 MiB copy of --copy-calibration)
-    copies = [k for k in counters["FETCH_SIZE"] if "copyBuffer" in k]
+    copies = [k for k in counters["FETCH_SIZE"] if "copyBuffer" in k or "copy" in k.lower()]
     fcal = max(max(counters["FETCH_SIZE"][k]) for k in copies)
     wcal = max(max(counters["WRITE_SIZE"][k]) for k in copies)
     rf, wf = COPY_BYTES / (fcal * 1024), COPY_BYTES / (wcal * 1024)
-    src = open(os.path.join(ROOT, KERNEL_SOURCE), "rb").read()
-    sha = hashlib.sha256(src).hexdigest()
-    rec = {"workload": "heat2d 255x255 N=512 BDF4 kappa=1e-5", "source": KERNEL_SOURCE, "source_sha256": sha,
+    sha = sources_sha()
+    rec = {"workload": DESCR[name], "sources": KERNEL_SOURCES, "sources_sha256": sha,
            "calibration": {"copy_bytes": COPY_BYTES, "FETCH_SIZE_KiB": fcal, "WRITE_SIZE_KiB": wcal,
                            "read_factor": rf, "write_factor": wf},
            "kernels": {"fp64": {}, "mixed": {}}}
-    lines = ["# Kernel profile: 2D heat 255x255, N=512, BDF4, kappa=1e-5 (bench workload)", "",
-             f"Device: one MI355X (gfx950).  Source: `{KERNEL_SOURCE}` sha256 prefix `{sha[:16]}`.", "",
+    stem = profile_stem(w)
+    lines = [f"# Kernel profile: {DESCR[name]}", "",
+             f"Device: one MI355X (gfx950).  Kernel sources sha256 prefix `{sha[:16]}`.", "",
              "Commands (run from /tmp with TMPDIR=/tmp; each writes CSV under the -d folder), then "
-             "`python bench.py --summarize <out>` writes this file and the traffic record:", "", "```"]
-    cmd = "python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-other-configs --copy-calibration"
-    lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o heat2d -- {cmd}",
-              f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/FETCH_SIZE -o heat2d -- {cmd}",
-              f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/WRITE_SIZE -o heat2d -- {cmd}",
+             f"`python bench.py --summarize <out> --only {name}` writes this file and the traffic record:", "",
+             "```"]
+    cmd = f"python3 /root/repo/bench.py --only {name} --steps 5 --warmup 1 --no-cpu-baseline --copy-calibration"
+    lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o {name} -- {cmd}",
+              f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/FETCH_SIZE -o {name} -- {cmd}",
+              f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/WRITE_SIZE -o {name} -- {cmd}",
               "```", "",
-              "bench.py runs the FP64 plan (kernels `<double,...>`) and the mixed plan (`<float,...>`), each for "
-              "warmup + timed + time-to-1e-10 sweeps.", "", "## --kernel-trace --stats", "",
+              "bench.py runs the FP64 plan (kernels `<double,...>`), the mixed plan (`<float,...>`) and the FP64 "
+              "direct-form plan, each for the autotuner's trial launches, warmup and timed sweeps.", "",
+              "## --kernel-trace --stats", "",
               "| kernel | calls | average us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
     for r in stats:
-        lines.append(f"| `{short(r['Name'])[:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+        lines.append(f"| `{short(r['Name'])[:100]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
     lines += ["", "## --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch, mean over dispatches)", "",
               f"Calibration: a plain {COPY_BYTES >> 20} MiB device copy read FETCH_SIZE = {fcal:.0f} KiB and "
               f"WRITE_SIZE = {wcal:.0f} KiB, so HBM read bytes = {rf:.3f} x FETCH_SIZE KiB x 1024 and write "
               f"bytes = {wf:.3f} x WRITE_SIZE KiB x 1024.", "",
               "Kernels with few dispatches are the autotuner's trial launches of the variants not chosen.", "",
-              "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | write MB |", "|---|---|---|---|---|"]
-    # the autotuner also launches the other variants of a slot a few times: the
-    # record keeps, per slot, the kernel with the most dispatches (the timed one)
+              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | write MB |",
+              "|---|---|---|---|---|---|"]
     calls = {}
     for k, vals in counters["FETCH_SIZE"].items():
-        slot = slot_of(k)
+        fk = sum(vals) / len(vals)
+        wv = counters["WRITE_SIZE"].get(k, [0.0])
+        wk = sum(wv) / len(wv)
+        rd, wr = rf * fk * 1024, wf * wk * 1024
+        lines.append(f"| `{short(k)[:100]}` | {len(vals)} | {fk:.4g} | {wk:.4g} | {rd / 1e6:.1f} | {wr / 1e6:.1f} |")
+        slot = slot_of(k, w.dim)
         if slot is None:
             continue
-        fk = sum(vals) / len(vals)
-        wk = sum(counters["WRITE_SIZE"][k]) / len(counters["WRITE_SIZE"][k])
-        rd, wr = rf * fk * 1024, wf * wk * 1024
         prec = "mixed" if "<float" in k else "fp64"
         if len(vals) > calls.get((prec, slot), 0):
             calls[(prec, slot)] = len(vals)
             rec["kernels"][prec][slot] = {"read": rd, "write": wr, "kernel": short(k), "dispatches": len(vals)}
-        lines.append(f"| `{short(k)}` | {fk:.4g} | {wk:.4g} | {rd / 1e6:.1f} | {wr / 1e6:.1f} |")
-    open(PROFILE_STEM + "_kernels.md", "w").write("\n".join(lines) + "\n")
-    json.dump(rec, open(PROFILE_STEM + "_traffic.json", "w"), indent=1)
-    print(f"wrote {PROFILE_STEM}_kernels.md and _traffic.json")
+    open(stem + "_kernels.md", "w").write("\n".join(lines) + "\n")
+    json.dump(rec, open(stem + "_traffic.json", "w"), indent=1)
+    print(f"wrote {stem}_kernels.md and _traffic.json")
 
+
+# ---------------------------------------------------------------------------------------
 
 def main():
+    global MODE_IDX
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle leg (and with it the time-to-tolerance figures)")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in kernel variants (no autotuning)")
-    ap.add_argument("--no-other-configs", action="store_true",
-                    help="skip the sweep timings of the 2D subdiffusion and 3D heat workloads")
+    ap.add_argument("--only", choices=SWEEP_WORKLOADS + ("heat1d",),
+                    help="run one workload only (profiling runs); it becomes the reported line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 256 MiB on the device (counter calibration for profiles)")
     ap.add_argument("--summarize", metavar="DIR",
-                    help="write the profile summary from rocprofv3 CSV output in DIR and exit (no GPU)")
+                    help="write the profile summary of --only's workload from rocprofv3 CSV in DIR and exit")
     args = ap.parse_args()
+    import numpy as np
+    MODE_IDX = np.array([0, 1, 2, 3, 4, 6, 9, 14, 22, 35, 56, 90, 145, 233, 376, 510])
     if args.summarize:
-        summarize(args.summarize)
+        summarize(args.summarize, args.only or HEADLINE)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sharded multi-GPU "
-              f"design is described in DESIGN.md and is not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): this build runs on a single "
+              f"GPU; the sharded multi-GPU design is described in DESIGN.md and is not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2007_13125_amd import workloads as wl
-    w = wl.heat2d()
-    N, M = w.N, w.M
-    has_f = w.f is not None
-    out = {}
-    plans = {}
-    for precision in ("fp64", "mixed"):
-        plan, data, ms, prof, var = run_precision(w, precision, args.steps, args.warmup, tune=not args.no_tune)
-        mixed = precision == "mixed"
-        kern = {name: ms_k for name, ms_k in prof}
-        sweep_bytes = sum(kernel_bytes(n, N, M, mixed, has_f) for n, _ in prof)
-        dom = max(prof, key=lambda t: t[1])
-        dom_bytes = kernel_bytes(dom[0], N, M, mixed, has_f)
-        achieved = dom_bytes / (dom[1] * 1e-3) / 1e9
-        out[precision] = {
-            "value": N * M / (ms * 1e-3), "ms_per_step": ms, "kernels_ms": kern,
-            "sweep_alg_bytes": sweep_bytes,
-            "sweep_hbm_frac": sweep_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "dominant": {"kernel": dom[0], "ms": dom[1], "bytes": dom_bytes, "GBps": achieved},
-            "variants": var,
-        }
-        plans[precision] = (plan, data)
-    # reference trajectory for time-to-1e-10: the FP64 path converged to 1e-14
-    # (the FP64 path matches the CPU oracle to ~1e-14 at this size in the parity tests)
-    plan64, data64 = plans["fp64"]
-    Uref = torch.empty((N, M), dtype=torch.float64, device="cuda")
-    plan64.init_iterate(Uref)
-    plan64.sweeps(Uref, 8)
-    torch.cuda.synchronize()
-    # the paper's direct form in FP64 (its roundoff floor, ~eps/kappa ~ 6e-12 here, is below 1e-10)
-    pd, dd, ms_d, prof_d, var_d = run_precision(w, "fp64", args.steps, args.warmup, form="direct",
-                                                tune=not args.no_tune)
-    plans["fp64_direct"] = (pd, dd)
-    ttt = {p: time_to_tol(w, plans[p][0], plans[p][1], Uref) for p in ("fp64", "fp64_direct", "mixed")}
-
-    d = out["fp64"]["dominant"]
-    res = {
-        "metric": METRIC,
-        "value": out["fp64"]["value"],
-        "unit": "unknown-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": out["fp64"]["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "heat2d: 2D heat, 5-point FD Dirichlet Laplacian 255x255, BDF4 (Table 1 "
-                               "corrections), T=1, N=512, kappa=1e-5, residual form, FP64",
-                   "grid": list(w.m), "N": N, "k": w.k, "kappa": w.kappa, "form": "residual",
-                   "unknowns": N * M},
-        "roofline": {"bound": "hbm", "kernel": d["kernel"], "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("fp64", d["kernel"]), "alg_bytes": d["bytes"]},
-        "kernels_ms": out["fp64"]["kernels_ms"],
-        "sweep_hbm_frac": out["fp64"]["sweep_hbm_frac"],
-        "variants": {"fp64": out["fp64"]["variants"], "mixed": out["mixed"]["variants"], "fp64_direct": var_d,
-                     "knobs": ["forward kernel", "x pass rows", "y pass columns", "1D tridiagonal split"]},
-        "mixed": {k: out["mixed"][k] for k in ("value", "ms_per_step", "kernels_ms", "sweep_hbm_frac",
-                                               "dominant")},
-        # relative L2 error after each sweep (against the FP64 path converged to ~1e-14)
-        "time_to_1e-10": {p: {"sweeps": ttt[p]["sweeps"], "ms": ttt[p]["ms"],
-                              "rel_l2_per_sweep": [float("%.3g" % e) for e in ttt[p]["errors"]]} for p in ttt},
-        "fp64_direct": {"ms_per_step": ms_d, "kernels_ms": {n: t for n, t in prof_d}},
-    }
-    if not args.no_other_configs:
-        res["other_configs"] = other_configs(5, not args.no_tune)
+    names = [args.only] if args.only else list(SWEEP_WORKLOADS) + ["heat1d"]
+    ws = {n: getattr(wl, n)() for n in names}
+    base, refs = (None, None)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline()
-    for p in plans.values():
-        p[0].close()
+        print("[bench] cpu leg", file=sys.stderr, flush=True)
+        base, refs = cpu_leg(ws)
+    results = {}
+    for n in names:
+        results[n] = bench_heat1d(args, refs) if n == "heat1d" else bench_workload(ws[n], args, refs)
+        torch.cuda.empty_cache()
+    head = args.only or HEADLINE
+    h = results[head]
+    w = ws[head]
+    if head == "heat1d":
+        res = {"metric": METRIC, "value": w.N * w.M / (h["ms_per_step"] * 1e-3), "ms_per_step": h["ms_per_step"]}
+    else:
+        res = {"metric": METRIC, "value": h["fp64"]["value"], "ms_per_step": h["fp64"]["ms_per_step"]}
+    res.update({
+        "unit": "unknown-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{head}: {DESCR[head]}, residual form, FP64 (mixed FP32/FP64 and the FP64 "
+                               f"direct form alongside)", "grid": list(w.m), "N": w.N, "k": w.k,
+                   "alpha": w.alpha, "kappa": w.kappa, "unknowns": w.N * w.M},
+    })
+    if head != "heat1d":
+        res["roofline"] = h["fp64"]["roofline"]
+        res["mixed"] = h["mixed"]
+        res["fp64_direct"] = h["fp64_direct"]
+        res["fp64"] = h["fp64"]
+    if base is not None:
+        res["cpu_baseline"] = base
+    res["workloads"] = {n: r for n, r in results.items() if n != head}
+    res["variant_knobs"] = ["forward kernel", "x pass rows", "y/z pass columns", "1D solver"]
     print(json.dumps(res), flush=True)
     if args.copy_calibration:
         a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")

@@ -55,7 +55,10 @@ enum { PINT_FP64 = 0,         /* every step in FP64                             
        PINT_MIXED = 1 };      /* FFTs and shifted solves in complex FP32; residual,
                                  kappa scalings, eigenvalues, update, norms in FP64   */
 enum { PINT_RESIDUAL = 0,     /* U_m = U_{m-1} + P^{-1}(G - T U_{m-1}) (default)     */
-       PINT_DIRECT = 1 };     /* U_m = P^{-1} F_{m-1}, the paper's literal form      */
+       PINT_DIRECT = 1 };     /* U_m = P^{-1} F_{m-1}, the paper's literal form;
+                                 FP64 only (PINT_MIXED + PINT_DIRECT is rejected with
+                                 PINT_E_UNSUPPORTED: an FP32 right-hand side would put
+                                 FP32 rounding into the fixed point)                  */
 enum { PINT_NORM_INF = 0,     /* stop on max over space-time of |U_m - U_{m-1}|      */
        PINT_NORM_L2_TERMINAL = 1 }; /* stop on the discrete L2 norm at t = T         */
 enum { PINT_INIT_V = 0,       /* U_0^n = v for all n (Thm 2.6 / Thm 3.5)             */
@@ -92,41 +95,51 @@ typedef struct pint_plan pint_plan;
  * diag-heat / diag-frac, kappa^{+-q/N}, sine eigenvalues of A_h, Table 1) and
  * uploads them (the plan owns these small device tables).
  * hip_stream: a hipStream_t (NULL = default stream) of the current device.
+ * Grids: any m_i in 1..2047 per axis (sine transforms of length 2(m_i+1);
+ * lengths that are not powers of two take Bluestein's chirp-z form).
+ * The plan allocates its small tables only; the workspace comes from the
+ * caller (pint_plan_set_workspace), so no later call allocates device memory.
  * Errors: PINT_E_ARG (invalid grid/params, NULL plan), PINT_E_UNSUPPORTED
- * (dim >= 2 with some m_i + 1 not a power of two in 4..2048, or N outside the
- * supported powers of two), PINT_E_NOMEM, PINT_E_HIP. */
+ * (m_i > 2047, N outside the supported powers of two, mixed precision with
+ * the direct form), PINT_E_NOMEM, PINT_E_HIP. */
 pint_status pint_plan_create(pint_plan **plan, const pint_grid *grid,
                              const pint_params *params, void *hip_stream);
 
 /* Bytes of device workspace one solve needs (spectrum buffer, source
- * corrections, norm partials).  The caller may provide it with
- * pint_plan_set_workspace; otherwise the plan allocates it on first use and
- * frees it in pint_plan_destroy. */
+ * corrections, norm partials).  The caller provides it with
+ * pint_plan_set_workspace before pint_bind / pint_solve.  0 for a NULL plan
+ * and for batch plans (which own their instances' workspaces). */
 size_t pint_plan_workspace_bytes(const pint_plan *plan);
 
 /* Hand the plan a caller-owned DEVICE buffer of at least
  * pint_plan_workspace_bytes() bytes, 256-byte aligned.  The plan uses it until
- * destroyed or given another one.  Errors: PINT_E_ARG. */
+ * destroyed or given another one (the caller keeps ownership and frees it
+ * after pint_plan_destroy).  Errors: PINT_E_ARG (NULL, too small, misaligned,
+ * batch plan). */
 pint_status pint_plan_set_workspace(pint_plan *plan, void *dev_ptr, size_t bytes);
 
 /* Bind the problem data and compute the starting-step source corrections
- * a_n (f(0) - A_h v) + sum_l b_{l,n} tau^l d^l f/dt^l (0), n < k (Table 1).
+ * a_n (f(0) - A_h v) + sum_l b_{l,n} tau^l d^l f/dt^l (0), n < k (Sec. 2.1
+ * eq. BDF and Table 1; Sec. 3.1 eq. BDF-frac for alpha < 1).
  *   v    DEVICE [M]          initial value
  *   f    DEVICE [N+1][M]     f(t_0) .. f(t_N); NULL means f == 0
  *   fder DEVICE [k-2][M]     d^l f/dt^l (0), l = 1..k-2; NULL means zero
  * The pointers must stay valid while the plan sweeps.  Asynchronous.
- * Errors: PINT_E_ARG (NULL v), PINT_E_HIP. */
+ * Errors: PINT_E_ARG (NULL v, no workspace set, batch plan), PINT_E_HIP. */
 pint_status pint_bind(pint_plan *plan, const double *v, const double *f, const double *fder);
 
 /* Set U (DEVICE [N][M]) to the initial iterate selected by params.init
- * (INIT_USER leaves it untouched).  Requires pint_bind.  Asynchronous. */
+ * (INIT_USER leaves it untouched): U_0^n = v as in Thm 2.6 / Thm 3.5, or
+ * U_0 = 0 as in the runs of Sec. 4.  Requires pint_bind.  Asynchronous. */
 pint_status pint_init_iterate(pint_plan *plan, double *U);
 
 /* Run exactly nsweeps WR sweeps on U (DEVICE [N][M], in/out) with the bound
  * data, asynchronously on the plan's stream, with no host synchronisation.
+ * One sweep is one step of the iteration eq. BDF-iter (Sec. 2.2; eq.
+ * BDF-frac-iter of Sec. 3.2 for alpha < 1), solved by Algorithm 1 (resp. 2).
  * dev_norms (DEVICE [nsweeps][2], may be NULL) receives per sweep
  * { max |U_m - U_{m-1}|, (h^d sum (U_m^N - U_{m-1}^N)^2)^{1/2} }.
- * Errors: PINT_E_ARG (not bound, NULL U, nsweeps < 0), PINT_E_NOMEM, PINT_E_HIP. */
+ * Errors: PINT_E_ARG (not bound, NULL U, nsweeps < 0), PINT_E_HIP. */
 pint_status pint_sweeps(pint_plan *plan, double *U, int nsweeps, double *dev_norms);
 
 /* Instrumented sweeps for measurement: runs nsweeps sweeps exactly like
@@ -141,8 +154,11 @@ pint_status pint_sweeps(pint_plan *plan, double *U, int nsweeps, double *dev_nor
 int pint_profile_sweeps(pint_plan *plan, double *U, int nsweeps, double *ms, const char **names,
                         int max_slots);
 
-/* Full solve: bind, initial iterate, then sweeps until the chosen update norm
- * is <= tol or max_sweeps is reached (host-side stop test after every sweep).
+/* Full solve: bind, initial iterate, then WR sweeps (eq. BDF-iter, Algorithm
+ * 1; eq. BDF-frac-iter, Algorithm 2) until the chosen update norm is <= tol
+ * (the stopping rule of Sec. 4) or max_sweeps is reached (host-side stop test
+ * after every sweep).  Allocates no device memory (the workspace is the
+ * caller's).
  *   v, f, fder as in pint_bind; U DEVICE [N][M] (input too for INIT_USER).
  *   upd     HOST [max_sweeps]: the max-norm update per sweep (may be NULL)
  *   upd_l2T HOST [max_sweeps]: the terminal L2_h update per sweep (may be NULL)
@@ -154,24 +170,26 @@ pint_status pint_solve(pint_plan *plan, const double *v, const double *f, const 
 
 /* Many independent problems in one plan (each instance with its own grid and
  * params; N, k, alpha, precision may all differ).  Every instance is validated
- * as in pint_plan_create and gets its own tables and workspace.  The instances
- * are solved one after another on the plan's stream through the single-plan
- * path (the graph-replayed batch sweep is switched off: it ended the host
- * process with an unexplained crash).  count >= 1; grids/params are HOST arrays
- * of count entries.  Errors: as pint_plan_create (the message names the
- * instance). */
+ * as in pint_plan_create and gets its own tables and workspace, which this
+ * call allocates (pint_batch_solve allocates nothing).  The instances are
+ * solved one after another on the plan's stream through the single-plan
+ * path.  count >= 1; grids/params are HOST arrays of count entries.
+ * Errors: as pint_plan_create (the message names the instance). */
 pint_status pint_batch_plan_create(pint_plan **plan, int count, const pint_grid *grids,
                                    const pint_params *params, void *hip_stream);
 
 /* Batch solve.  v, f, fder, U: HOST arrays of count DEVICE pointers with the
  * meaning of pint_solve (f and fder entries, or the f/fder arrays themselves,
- * may be NULL).  upd: HOST [count][S] with S the largest max_sweeps of the
- * instances (may be NULL); sweeps: HOST [count] (may be NULL).  Each instance
- * stops at its own tol, max_sweeps or divergence.
- * Returns PINT_OK if every instance converged, PINT_NOT_CONVERGED if one hit
- * max_sweeps, PINT_E_DIVERGED if one diverged (the others still finish). */
+ * may be NULL).  upd: HOST [count][stride] (may be NULL): instance i writes its
+ * max-norm updates to upd[i*stride .. i*stride + sweeps[i]); stride must be
+ * at least every instance's max_sweeps (PINT_E_ARG otherwise).  sweeps: HOST
+ * [count] (may be NULL).  Each instance stops at its own tol, max_sweeps or
+ * divergence.  Returns PINT_OK if every instance converged,
+ * PINT_NOT_CONVERGED if one hit max_sweeps, PINT_E_DIVERGED if one diverged
+ * (the others still finish). */
 pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const double *const *f,
-                             const double *const *fder, double *const *U, double *upd, int *sweeps);
+                             const double *const *fder, double *const *U, double *upd, int stride,
+                             int *sweeps);
 
 /* Autotuning of the kernels' tile and split choices (the batching row of the
  * method's GPU mapping: FFT radix and tile shapes, PCR/Thomas split).  Four
@@ -184,7 +202,10 @@ pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const doub
  *       to the problem falls back to the next one that does);
  *   [1] rows per workgroup of the x sine pass: 0 built-in, 1 half as many;
  *   [2] column tile of the y/z passes: 0 built-in, 1 the other width;
- *   [3] 1D tridiagonal systems: 0 built-in split, 1 more PCR lanes.
+ *   [3] 1D grids with 2(m+1) not a power of two: 0 sine solve (Bluestein),
+ *       1 PCR/Thomas with the built-in split, 2 PCR/Thomas with more PCR
+ *       lanes.  Not tuned (the PCR stage loses accuracy on the near-singular
+ *       shifted Laplacians, ~eps (m+1)^2 per sweep); only pinned.
  * Tuning times every value of a knob that launches a different kernel for the
  * problem (reps launches, in three interleaved rounds, best round kept) on the
  * plan's own workspace (the forward kernels read U, nothing writes it), and

@@ -3,8 +3,6 @@
 Used to pin the order O(tau^k) of the corrected schemes (Lemma 2.2, eq.
 err-BDF; Lemma 3.2, eq. err-BDF-frac) on one spatial eigenmode with
 eigenvalue mu:
-* heat (alpha = 1), y' + mu y = cos t, y(0) = y0:
-      y(t) = y0 e^{-mu t} + (mu cos t + sin t - mu e^{-mu t}) / (1 + mu^2);
 * heat (alpha = 1), y' + mu y = cos t + sin t, y(0) = y0 (every d^l f/dt^l (0)
   is +-1, so every row of Table 1 takes part, and the solution stays bounded):
       y(t) = y0 e^{-mu t} + a (cos t - e^{-mu t}) + b sin t,
@@ -14,11 +12,6 @@ eigenvalue mu:
 """
 import numpy as np
 from scipy.special import erfcx
-
-
-def heat_cos_mode(mu, y0, t):
-    t = np.asarray(t, dtype=np.float64)
-    return y0 * np.exp(-mu * t) + (mu * np.cos(t) + np.sin(t) - mu * np.exp(-mu * t)) / (1.0 + mu ** 2)
 
 
 def subdiffusion_half_mode(mu, y0, t):

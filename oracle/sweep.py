@@ -94,16 +94,37 @@ class Problem:
             out[n - 1] = ta * (self.w[:n] @ U[n - 1::-1][:n]) + self.A @ U[n - 1]
         return out
 
-    def solve_P(self, X):
+    def shifted_solve(self, p, b, refine=2):
+        """Step 2 for frequency p: the solution of (d_p I + tau^alpha A) x = b.
+
+        A sparse LU solve, followed by `refine` steps of iterative refinement
+        whose residual is formed in extended precision (long double), so that x
+        is the exact solution rounded to FP64 rather than carrying the
+        factorisation's error of order eps times the condition number of the
+        shifted Laplacian (which grows like (m+1)^2)."""
+        M, ta = self.M, self.tau ** self.alpha
+        I = sp.identity(M, dtype=np.complex128, format="csc")
+        lu = spla.splu(sp.csc_matrix(self.d[p] * I + ta * sp.csc_matrix(self.A, dtype=np.complex128)))
+        x = lu.solve(b)
+        if refine:
+            A_ld = sp.csr_matrix(self.A, dtype=np.longdouble)
+            d_ld = np.clongdouble(self.d[p])
+            ta_ld = np.longdouble(self.tau) ** np.longdouble(self.alpha)
+            b_ld = b.astype(np.clongdouble)
+            for _ in range(refine):
+                x_ld = x.astype(np.clongdouble)
+                r = b_ld - (d_ld * x_ld + ta_ld * (A_ld @ x_ld))
+                x = x + lu.solve(r.astype(np.complex128))
+        return x
+
+    def solve_P(self, X, refine=2):
         """P^{-1} X by Algorithm 1/2 (dense DFT, all N frequencies).
         Returns (real part, max abs imaginary part)."""
         N, M, ta = self.N, self.M, self.tau ** self.alpha
         H = self.Vinv @ (self.scale[:, None] * X)                  # Step 1
         Q = np.empty((N, M), dtype=np.complex128)
-        I = sp.identity(M, dtype=np.complex128, format="csc")
-        Ac = sp.csc_matrix(self.A, dtype=np.complex128)
         for p in range(N):                                          # Step 2
-            Q[p] = spla.spsolve(self.d[p] * I + ta * Ac, ta * H[p])
+            Q[p] = self.shifted_solve(p, ta * H[p], refine)
         Y = (self.V @ Q) / self.scale[:, None]                      # Step 3
         return Y.real.copy(), float(np.max(np.abs(Y.imag))) if Y.size else 0.0
 

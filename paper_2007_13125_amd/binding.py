@@ -50,7 +50,7 @@ EXPORTS = {
     "pint_batch_plan_create": (c_int, [POINTER(c_void_p), c_int, POINTER(pint_grid),
                                        POINTER(pint_params), c_void_p]),
     "pint_batch_solve": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
-                                 POINTER(c_void_p), POINTER(c_double), POINTER(c_int)]),
+                                 POINTER(c_void_p), POINTER(c_double), c_int, POINTER(c_int)]),
     "pint_plan_set_autotune": (c_int, [c_void_p, c_int]),
     "pint_plan_tune": (c_int, [c_void_p, c_void_p, c_int]),
     "pint_plan_get_variants": (c_int, [c_void_p, c_int, POINTER(c_int)]),
@@ -149,7 +149,7 @@ def pint_sweeps(plan, U, nsweeps, dev_norms=None):
     _check(lib().pint_sweeps(plan, _ptr(U), int(nsweeps), _ptr(dev_norms)), "pint_sweeps")
 
 
-def pint_profile_sweeps(plan, U, nsweeps, max_slots=8):
+def pint_profile_sweeps(plan, U, nsweeps, max_slots=16):
     """Returns [(slot name, average ms per sweep)] measured with HIP events."""
     ms = (c_double * max_slots)()
     names = (ctypes.c_char_p * max_slots)()
@@ -184,13 +184,14 @@ def pint_batch_plan_create(grids, params, stream=None):
 
 
 def pint_batch_solve(plan, v, f, fder, U, max_sweeps):
-    """max_sweeps: the largest max_sweeps of the instances.  Returns
-    (status, per-instance update norms, per-instance sweep counts)."""
+    """max_sweeps: the row stride of the update-norm buffer; the library rejects
+    it (PINT_E_ARG) if an instance may sweep more often.  Returns (status,
+    per-instance update norms, per-instance sweep counts)."""
     n = len(v)
     arr = lambda ts: (c_void_p * n)(*[None if t is None else t.data_ptr() for t in ts])
     upd = (c_double * (n * max_sweeps))()
     sw = (c_int * n)()
-    st = lib().pint_batch_solve(plan, arr(v), arr(f), arr(fder), arr(U), upd, sw)
+    st = lib().pint_batch_solve(plan, arr(v), arr(f), arr(fder), arr(U), upd, int(max_sweeps), sw)
     _check(st, "pint_batch_solve", allow=(PINT_OK, PINT_NOT_CONVERGED, PINT_E_DIVERGED))
     sw = list(sw)
     return st, [list(upd)[i * max_sweeps:i * max_sweeps + sw[i]] for i in range(n)], sw

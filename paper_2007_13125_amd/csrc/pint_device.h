@@ -373,17 +373,10 @@ constexpr int kNT = 256;
 
 }  // namespace
 
-// Prepare-only mode (per host thread): the launchers make every runtime query
-// and attribute setting of a launch but launch nothing.  A batch runs one
-// prepared sweep of its instances before recording the sweep into a graph.
-extern thread_local bool g_prepare_only;
 // Workgroups that fit on the whole device at once for a kernel (cached).
 int persistent_blocks(const void* fn, int nt);
 
 }  // namespace pint
 
-#define PINT_LAUNCH(...)                                        \
-    do {                                                        \
-        if (!g_prepare_only) hipLaunchKernelGGL(__VA_ARGS__);   \
-    } while (0)
+#define PINT_LAUNCH(...) hipLaunchKernelGGL(__VA_ARGS__)
 #define N_OF(logn) (1 << (logn))

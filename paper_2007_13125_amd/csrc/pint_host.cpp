@@ -154,11 +154,6 @@ struct pint_plan {
     double* h_norms = nullptr;  // pinned host, 2 doubles
     // batch: sub-plans sharing the stream
     std::vector<pint_plan*> inst;
-    std::vector<hipStream_t> lanes;   // fork streams of a batch capture (default priority)
-    hipStream_t cap = nullptr;        // stream the batch graph is recorded on and replayed on
-    std::vector<hipEvent_t> lane_ev;
-    double* d_bnorms = nullptr;       // [count][2] per-instance norms of the last sweep
-    double* h_bnorms = nullptr;       // pinned host copy
     // kernel variants in use: forward, x pass, y/z pass, 1D tridiagonal split (0 = built-in)
     int var[4] = {0, 0, 0, 0};
     int tune_reps = 0;                // > 0: the solves time the variants first (autotune)
@@ -168,10 +163,6 @@ struct pint_plan {
         for (void* q : owned) (void)hipFree(q);
         if (ws_owned && ws) (void)hipFree(ws);
         if (h_norms) (void)hipHostFree(h_norms);
-        if (h_bnorms) (void)hipHostFree(h_bnorms);
-        for (hipEvent_t e : lane_ev) (void)hipEventDestroy(e);
-        for (hipStream_t q : lanes) (void)hipStreamDestroy(q);
-        if (cap) (void)hipStreamDestroy(cap);
         for (pint_plan* q : inst) delete q;
     }
 };
@@ -295,10 +286,16 @@ pint_status validate(const pint_grid* g, const pint_params* p) {
     if (p->norm != PINT_NORM_INF && p->norm != PINT_NORM_L2_TERMINAL) return fail(PINT_E_ARG, "bad norm");
     if (p->init < PINT_INIT_V || p->init > PINT_INIT_USER) return fail(PINT_E_ARG, "bad init");
     if (p->N <= p->k) return fail(PINT_E_ARG, "N must exceed k");
+    // The direct form's right-hand side would be assembled from FP32 spectra, so
+    // its fixed point would carry FP32 rounding; the FP64 outer correction of
+    // the mixed form needs the residual form.
+    if (p->precision == PINT_MIXED && p->form == PINT_DIRECT)
+        return fail(PINT_E_UNSUPPORTED, "mixed precision runs the residual form only");
     if (!is_pow2(p->N) || p->N < (1 << pint::kMinLogN) || p->N > (1 << pint::kMaxLogN))
         return fail(PINT_E_UNSUPPORTED, "N must be a power of two in 8..2048");
     if (g->dim == 1) {
-        if (g->m[0] > pint::kMaxTri1D) return fail(PINT_E_UNSUPPORTED, "1D grids are limited to m <= 2048");
+        if (2LL * (g->m[0] + 1) > (1 << pint::kMaxLogL))
+            return fail(PINT_E_UNSUPPORTED, "1D grids are limited to m <= 2047");
     } else {
         long long plane = 16;   // complex FP64 slots of one spectrum plane, in bytes
         for (int i = 0; i < g->dim; ++i) {
@@ -435,7 +432,7 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
         const long long L = 2LL * (m + 1);
         if (is_pow2(L) && L <= (1LL << pint::kMaxLogL) && (g->dim == 1 || L >= 8)) {
             if ((rc = upload_tw(P, &P->d_twL[i], L, P->mixed)) != PINT_OK) return rc;
-        } else if (g->dim >= 2) {
+        } else {
             if ((rc = upload_bluestein(P, i, m)) != PINT_OK) return rc;
         }
     }
@@ -458,16 +455,23 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     return PINT_OK;
 }
 
-pint_status ensure_workspace(pint_plan* P) {
-    if (P->ws) return PINT_OK;
-    HIP_TRY(hipMalloc(&P->ws, P->ws_bytes));
-    P->ws_owned = true;
-    char* b = static_cast<char*>(P->ws);
+void attach_workspace(pint_plan* P, void* ws) {
+    P->ws = ws;
+    char* b = static_cast<char*>(ws);
     P->S = b;
     P->corr = reinterpret_cast<double*>(b + P->off_corr);
     P->partial = reinterpret_cast<double*>(b + P->off_partial);
     P->norm_tmp = reinterpret_cast<double*>(b + P->off_norm);
     P->Sg = P->off_sg ? static_cast<void*>(b + P->off_sg) : nullptr;
+}
+
+// Workspace owned by the plan itself (batch instances only; single plans get
+// theirs from the caller through pint_plan_set_workspace).
+pint_status own_workspace(pint_plan* P) {
+    void* q = nullptr;
+    HIP_TRY(hipMalloc(&q, P->ws_bytes));
+    P->ws_owned = true;
+    attach_workspace(P, q);
     return PINT_OK;
 }
 
@@ -699,15 +703,88 @@ pint_status tune_plan(pint_plan* P, const double* U, int reps) {
         });
         if (rc != PINT_OK) return rc;
     }
-    if (pint::tri_variant_distinct(sa0)) {
-        rc = pick(3, {0, 1}, [&]() { return pint::launch_space_pass(space_args(P), P->mixed, 0, P->st); });
-        if (rc != PINT_OK) return rc;
-    }
+    // knob 3 (1D: sine solve or PCR/Thomas) is not tuned: the choice changes the
+    // accuracy of a sweep, not only its speed; pint_plan_set_variants pins it
     P->tuned = true;
     return PINT_OK;
 }
 
 }  // namespace
+
+namespace pint {
+
+// Sweeps until the chosen update norm is <= tol or max_sweeps is reached, with
+// the host stop test after every sweep (the stopping rule of Sec. 4): the
+// update norms of the sweep are copied to pinned host memory and the stream
+// is synchronised.  Divergence guard: a non-finite update, or an update that
+// grew in two consecutive sweeps to above the first update.  Allocates
+// nothing.
+pint_status solve_loop(pint_plan* P, double* U, double* upd, double* upd_l2T, int* sweeps) {
+    int done = 0;
+    double first = 0.0, prev2 = 0.0, prev1 = 0.0;
+    pint_status result = PINT_NOT_CONVERGED;
+    for (int m = 0; m < P->p.max_sweeps; ++m) {
+        pint_status rc = one_sweep(P, U, P->norm_tmp);
+        if (rc != PINT_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(P->h_norms, P->norm_tmp, 2 * sizeof(double), hipMemcpyDeviceToHost, P->st));
+        HIP_TRY(hipStreamSynchronize(P->st));
+        const double ninf = P->h_norms[0], nl2 = P->h_norms[1];
+        if (upd) upd[m] = ninf;
+        if (upd_l2T) upd_l2T[m] = nl2;
+        done = m + 1;
+        const double crit = P->p.norm == PINT_NORM_INF ? ninf : nl2;
+        if (!std::isfinite(ninf) || !std::isfinite(nl2)) {
+            result = fail(PINT_E_DIVERGED, "non-finite update in sweep " + std::to_string(m + 1));
+            break;
+        }
+        if (m == 0) first = crit;
+        if (crit <= P->p.tol) {
+            result = PINT_OK;
+            break;
+        }
+        if (m >= 2 && crit > prev1 && prev1 > prev2 && crit > first) {
+            result = fail(PINT_E_DIVERGED, "update grew in two consecutive sweeps beyond the first update");
+            break;
+        }
+        prev2 = prev1;
+        prev1 = crit;
+    }
+    if (sweeps) *sweeps = done;
+    return result;
+}
+
+pint_status set_error(pint_status s, const std::string& msg) { return fail(s, msg); }
+
+// pint_solve on a workspace the caller names for this call only (the static
+// scratch of the allocation-free entry point): the plan's own workspace
+// attachment is set aside and restored afterwards, and the plan is left
+// unbound (its bound tables lived in the borrowed workspace).  No autotuning
+// (tuning creates timing events).  Allocates nothing.
+pint_status solve_in_workspace(pint_plan* P, void* ws, size_t ws_cap, const double* v, const double* f,
+                               const double* fder, double* U, double* upd, double* upd_l2T, int* sweeps) {
+    if (!P || !U || !v) return fail(PINT_E_ARG, "plan, v and U must not be NULL");
+    if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans are not supported here");
+    if (P->ws_bytes > ws_cap)
+        return fail(PINT_E_ARG, "the plan needs " + std::to_string(P->ws_bytes) + " bytes of workspace; the "
+                                "static scratch holds " + std::to_string(ws_cap));
+    void* keep = P->ws;
+    attach_workspace(P, ws);
+    pint_status rc = pint_bind(P, v, f, fder);
+    if (rc == PINT_OK) rc = pint_init_iterate(P, U);
+    if (rc == PINT_OK) rc = solve_loop(P, U, upd, upd_l2T, sweeps);
+    if (keep) {
+        attach_workspace(P, keep);
+    } else {
+        P->ws = nullptr;
+        P->S = nullptr;
+        P->corr = P->partial = P->norm_tmp = nullptr;
+        P->Sg = nullptr;
+    }
+    P->bound = false;
+    return rc;
+}
+
+}  // namespace pint
 
 extern "C" {
 
@@ -742,21 +819,15 @@ pint_status pint_plan_set_workspace(pint_plan* P, void* dev_ptr, size_t bytes) {
         HIP_TRY(hipStreamSynchronize(P->st));
         HIP_TRY(hipFree(P->ws));
     }
-    P->ws = dev_ptr;
     P->ws_owned = false;
-    char* b = static_cast<char*>(dev_ptr);
-    P->S = b;
-    P->corr = reinterpret_cast<double*>(b + P->off_corr);
-    P->partial = reinterpret_cast<double*>(b + P->off_partial);
-    P->norm_tmp = reinterpret_cast<double*>(b + P->off_norm);
-    P->Sg = P->off_sg ? static_cast<void*>(b + P->off_sg) : nullptr;
+    attach_workspace(P, dev_ptr);
     return PINT_OK;
 }
 
 pint_status pint_bind(pint_plan* P, const double* v, const double* f, const double* fder) {
     if (!P || !v) return fail(PINT_E_ARG, "plan and v must not be NULL");
-    pint_status rc = ensure_workspace(P);
-    if (rc != PINT_OK) return rc;
+    if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans bind their instances in pint_batch_solve");
+    if (!P->ws) return fail(PINT_E_ARG, "no workspace: call pint_plan_set_workspace first");
     P->v = v;
     P->f = f;
     P->fder = fder;
@@ -840,35 +911,7 @@ pint_status pint_solve(pint_plan* P, const double* v, const double* f, const dou
     if (rc != PINT_OK) return rc;
     if ((rc = pint_init_iterate(P, U)) != PINT_OK) return rc;
     if (P->tune_reps > 0 && !P->tuned && (rc = tune_plan(P, U, P->tune_reps)) != PINT_OK) return rc;
-    std::vector<double> hist;
-    int done = 0;
-    pint_status result = PINT_NOT_CONVERGED;
-    for (int m = 0; m < P->p.max_sweeps; ++m) {
-        if ((rc = one_sweep(P, U, P->norm_tmp)) != PINT_OK) return rc;
-        HIP_TRY(hipMemcpyAsync(P->h_norms, P->norm_tmp, 2 * sizeof(double), hipMemcpyDeviceToHost, P->st));
-        HIP_TRY(hipStreamSynchronize(P->st));
-        const double ninf = P->h_norms[0], nl2 = P->h_norms[1];
-        if (upd) upd[m] = ninf;
-        if (upd_l2T) upd_l2T[m] = nl2;
-        done = m + 1;
-        const double crit = P->p.norm == PINT_NORM_INF ? ninf : nl2;
-        if (!std::isfinite(ninf) || !std::isfinite(nl2)) {
-            result = fail(PINT_E_DIVERGED, "non-finite update in sweep " + std::to_string(m + 1));
-            break;
-        }
-        hist.push_back(crit);
-        if (crit <= P->p.tol) {
-            result = PINT_OK;
-            break;
-        }
-        const size_t h = hist.size();
-        if (h >= 3 && hist[h - 1] > hist[h - 2] && hist[h - 2] > hist[h - 3] && hist[h - 1] > hist[0]) {
-            result = fail(PINT_E_DIVERGED, "update grew in two consecutive sweeps beyond the first update");
-            break;
-        }
-    }
-    if (sweeps) *sweeps = done;
-    return result;
+    return pint::solve_loop(P, U, upd, upd_l2T, sweeps);
 }
 
 pint_status pint_plan_set_autotune(pint_plan* P, int reps) {
@@ -907,7 +950,7 @@ pint_status pint_plan_set_variants(pint_plan* P, int instance, const int* choice
     } else if (instance != 0) {
         return fail(PINT_E_ARG, "instance must be 0 for a single plan");
     }
-    const int hi[4] = {pint::kFwdVariants - 1, 1, 1, 1};
+    const int hi[4] = {pint::kFwdVariants - 1, 1, 1, 2};
     for (int k = 0; k < 4; ++k)
         if (choices[k] < 0 || choices[k] > hi[k]) return fail(PINT_E_ARG, "variant out of range");
     for (int k = 0; k < 4; ++k) Q->var[k] = choices[k];
@@ -969,192 +1012,38 @@ pint_status pint_batch_plan_create(pint_plan** plan, int count, const pint_grid*
         if (!Q) return bail(fail(PINT_E_NOMEM, "host allocation failed"));
         P->inst.push_back(Q);
         pint_status rc = build_plan(Q, &grids[i], &params[i], P->st);
-        if (rc != PINT_OK) return bail(rc);
+        if (rc == PINT_OK) rc = own_workspace(Q);
+        if (rc != PINT_OK) return bail(fail(rc, "instance " + std::to_string(i) + ": " + g_err));
     }
-    // the caller's stream may be the legacy default stream, which cannot be
-    // captured: record and replay on a stream of the plan's own
-    if ((e = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking)) != hipSuccess)
-        return bail(fail(PINT_E_HIP, hipGetErrorString(e)));
-    const int nl = count < 8 ? count : 8;
-    for (int i = 0; i < nl; ++i) {
-        hipStream_t q;
-        if ((e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking)) != hipSuccess)
-            return bail(fail(PINT_E_HIP, hipGetErrorString(e)));
-        P->lanes.push_back(q);
-    }
-    for (int i = 0; i <= nl; ++i) {
-        hipEvent_t ev;
-        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
-            return bail(fail(PINT_E_HIP, hipGetErrorString(e)));
-        P->lane_ev.push_back(ev);
-    }
-    void* q = nullptr;
-    if ((e = hipMalloc(&q, (size_t)count * 2 * sizeof(double))) != hipSuccess)
-        return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
-    P->owned.push_back(q);
-    P->d_bnorms = static_cast<double*>(q);
-    if ((e = hipHostMalloc((void**)&P->h_bnorms, (size_t)count * 2 * sizeof(double), hipHostMallocDefault)) !=
-        hipSuccess)
-        return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
     *plan = P;
     return PINT_OK;
 }
 
-namespace {
-
-// Batch sweeps recorded into one HIP graph and replayed (below) are switched
-// off: runs of that path twice ended the host process with a segmentation
-// fault inside pint_batch_solve whose cause has not been found.  With the
-// switch off, pint_batch_solve solves the instances one after another through
-// the single-plan path (same kernels, same results, no graph, no fork streams).
-constexpr bool kBatchGraph = false;
-
-// Record one sweep of every active instance into a HIP graph: the instances
-// are forked over the lane streams (instance i on lane i mod lanes) and joined
-// back on the plan's stream, so independent instances may run concurrently.
-pint_status capture_batch_sweep(pint_plan* P, const std::vector<int>& active, double* const* U,
-                                hipGraphExec_t* exec) {
-    // Prepared sweep first: every occupancy query and kernel attribute the
-    // launches need is made here, outside the capture, so that recording the
-    // sweep issues nothing but stream work.
-    pint::set_prepare_only(true);
-    for (int i : active) {
-        const pint_status rp = one_sweep(P->inst[i], U[i], P->d_bnorms + 2 * i);
-        if (rp != PINT_OK) {
-            pint::set_prepare_only(false);
-            return rp;
-        }
-    }
-    pint::set_prepare_only(false);
-    HIP_TRY(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
-    hipGraph_t graph = nullptr;
-    pint_status rc = PINT_OK;
-    const int nl = (int)P->lanes.size();
-    hipError_t e = hipEventRecord(P->lane_ev[nl], P->cap);
-    for (int l = 0; l < nl && e == hipSuccess; ++l) e = hipStreamWaitEvent(P->lanes[l], P->lane_ev[nl], 0);
-    for (size_t a = 0; a < active.size() && e == hipSuccess && rc == PINT_OK; ++a) {
-        const int i = active[a];
-        pint_plan* Q = P->inst[i];
-        const hipStream_t keep = Q->st;
-        Q->st = P->lanes[i % nl];
-        rc = one_sweep(Q, U[i], P->d_bnorms + 2 * i);
-        Q->st = keep;
-    }
-    for (int l = 0; l < nl && e == hipSuccess; ++l) {
-        e = hipEventRecord(P->lane_ev[l], P->lanes[l]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(P->cap, P->lane_ev[l], 0);
-    }
-    const hipError_t e2 = hipStreamEndCapture(P->cap, &graph);
-    if (rc != PINT_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-    }
-    if (e != hipSuccess) return fail(PINT_E_HIP, std::string("batch capture: ") + hipGetErrorString(e));
-    if (e2 != hipSuccess) return fail(PINT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
-    e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(PINT_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    return PINT_OK;
-}
-
-}  // namespace
-
 pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double* const* f, const double* const* fder,
-                             double* const* U, double* upd, int* sweeps) {
+                             double* const* U, double* upd, int stride, int* sweeps) {
     if (!P || P->inst.empty() || !v || !U) return fail(PINT_E_ARG, "bad arguments to pint_batch_solve");
     const int count = (int)P->inst.size();
-    if (!kBatchGraph) {
-        // Instances solved one after another through the single-plan path.
-        int smax = 0;
-        for (int i = 0; i < count; ++i) {
-            if (!v[i] || !U[i]) return fail(PINT_E_ARG, "instance " + std::to_string(i) + ": NULL v or U");
-            smax = std::max(smax, P->inst[i]->p.max_sweeps);
-        }
-        pint_status result = PINT_OK;
-        for (int i = 0; i < count; ++i) {
-            pint_plan* Q = P->inst[i];
-            Q->tune_reps = P->tune_reps;
-            int done = 0;
-            const pint_status rc = pint_solve(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr, U[i],
-                                              upd ? upd + (size_t)i * smax : nullptr, nullptr, &done);
-            if (sweeps) sweeps[i] = done;
-            if (rc == PINT_E_DIVERGED) {
-                result = rc;
-            } else if (rc == PINT_NOT_CONVERGED) {
-                if (result == PINT_OK) result = rc;
-            } else if (rc != PINT_OK) {
-                return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
-            }
-        }
-        return result;
-    }
-    int max_sw = 0;
     for (int i = 0; i < count; ++i) {
         if (!v[i] || !U[i]) return fail(PINT_E_ARG, "instance " + std::to_string(i) + ": NULL v or U");
-        pint_plan* Q = P->inst[i];
-        pint_status rc = pint_bind(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr);
-        if (rc != PINT_OK) return rc;
-        if ((rc = pint_init_iterate(Q, U[i])) != PINT_OK) return rc;
-        if (P->tune_reps > 0 && !Q->tuned && (rc = tune_plan(Q, U[i], P->tune_reps)) != PINT_OK) return rc;
-        if (Q->p.max_sweeps > max_sw) max_sw = Q->p.max_sweeps;
-        if (sweeps) sweeps[i] = 0;
+        if (upd && P->inst[i]->p.max_sweeps > stride)
+            return fail(PINT_E_ARG, "instance " + std::to_string(i) + ": max_sweeps exceeds the upd stride");
     }
-    // binding and initial iterates were enqueued on the caller's stream
-    HIP_TRY(hipStreamSynchronize(P->st));
-    std::vector<int> active(count);
-    for (int i = 0; i < count; ++i) active[i] = i;
-    std::vector<std::vector<double>> hist(count);
     pint_status result = PINT_OK;
-    hipGraphExec_t exec = nullptr;
-    bool recapture = true;
-    for (int m = 0; m < max_sw && !active.empty(); ++m) {
-        if (recapture) {
-            if (exec) (void)hipGraphExecDestroy(exec);
-            exec = nullptr;
-            pint_status rc = capture_batch_sweep(P, active, U, &exec);
-            if (rc != PINT_OK) return rc;
-            recapture = false;
+    for (int i = 0; i < count; ++i) {
+        pint_plan* Q = P->inst[i];
+        Q->tune_reps = P->tune_reps;
+        int done = 0;
+        const pint_status rc = pint_solve(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr, U[i],
+                                          upd ? upd + (size_t)i * stride : nullptr, nullptr, &done);
+        if (sweeps) sweeps[i] = done;
+        if (rc == PINT_E_DIVERGED) {
+            result = rc;
+        } else if (rc == PINT_NOT_CONVERGED) {
+            if (result == PINT_OK) result = rc;
+        } else if (rc != PINT_OK) {
+            return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
         }
-        hipError_t e = hipGraphLaunch(exec, P->cap);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(P->h_bnorms, P->d_bnorms, (size_t)count * 2 * sizeof(double), hipMemcpyDeviceToHost,
-                               P->cap);
-        if (e == hipSuccess) e = hipStreamSynchronize(P->cap);
-        if (e != hipSuccess) {
-            (void)hipGraphExecDestroy(exec);
-            return fail(PINT_E_HIP, std::string("batch sweep: ") + hipGetErrorString(e));
-        }
-        std::vector<int> next;
-        for (int i : active) {
-            pint_plan* Q = P->inst[i];
-            const double ninf = P->h_bnorms[2 * i], nl2 = P->h_bnorms[2 * i + 1];
-            if (upd) upd[(size_t)i * max_sw + m] = ninf;
-            if (sweeps) sweeps[i] = m + 1;
-            const double crit = Q->p.norm == PINT_NORM_INF ? ninf : nl2;
-            bool done = false;
-            if (!std::isfinite(ninf) || !std::isfinite(nl2)) {
-                result = fail(PINT_E_DIVERGED, "instance " + std::to_string(i) + ": non-finite update");
-                done = true;
-            } else {
-                hist[i].push_back(crit);
-                const size_t h = hist[i].size();
-                if (crit <= Q->p.tol) {
-                    done = true;
-                } else if (h >= 3 && hist[i][h - 1] > hist[i][h - 2] && hist[i][h - 2] > hist[i][h - 3] &&
-                           hist[i][h - 1] > hist[i][0]) {
-                    result = fail(PINT_E_DIVERGED, "instance " + std::to_string(i) + ": update grew");
-                    done = true;
-                } else if (m + 1 >= Q->p.max_sweeps) {
-                    if (result == PINT_OK) result = PINT_NOT_CONVERGED;
-                    done = true;
-                }
-            }
-            if (!done) next.push_back(i);
-        }
-        if (next.size() != active.size()) recapture = true;
-        active.swap(next);
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
     return result;
 }
 

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <string>
+
+#include "../../include/pint.h"
 
 namespace pint {
 
@@ -69,7 +72,8 @@ struct SpaceArgs {
     double inv_factor;      // 1 / prod_a (-2 (m_a + 1)) for the raw DST pair
     int var_rows;           // x-pass variant: 0 = built-in rows per workgroup, 1 = half as many
     int var_cols;           // y/z-pass variant: 0 = built-in column tile, 1 = the other width
-    int var_tri;            // 1D tridiagonal split: 0 = built-in, 1 = the next wider split
+    int var_tri;            // 1D with 2(m+1) not a power of two: 0 = Bluestein sine solve,
+                            // 1 = PCR/Thomas (built-in split), 2 = PCR/Thomas with more PCR lanes
 };
 
 // Kernel variants the autotuner chooses between (index 0 is the built-in choice).
@@ -98,15 +102,11 @@ const char* space_pass_name(const SpaceArgs& a, int pass);
 hipError_t launch_space_pass(const SpaceArgs& a, bool mixed, int pass, hipStream_t st);
 hipError_t launch_norm_reduce(const double* partial, int nblocks, double hd, double* out,
                               hipStream_t st);
-// Prepare-only mode for the calling host thread: launchers make their runtime
-// queries (occupancy, kernel attributes) but launch nothing.
-void set_prepare_only(bool on);
 // Whether a variant differs from the built-in choice for this problem (the
 // autotuner skips the ones that would launch the same kernel).
 bool forward_variant_distinct(const FwdArgs& a, bool mixed, bool cq, int var);
 bool rows_variant_distinct(const SpaceArgs& a, bool mixed);
 bool cols_variant_distinct(const SpaceArgs& a, bool mixed);
-bool tri_variant_distinct(const SpaceArgs& a);
 
 // Largest time-FFT length and DST length the kernels are compiled for.
 constexpr int kMaxLogN = 11;      // N <= 2048
@@ -114,5 +114,14 @@ constexpr int kMinLogN = 3;       // N >= 8
 constexpr int kMaxLogL = 12;      // DST via odd extension of length 2(m+1) <= 4096
 constexpr int kMinLogL = 2;
 constexpr int kMaxTri1D = 2048;   // 1D tridiagonal systems up to this size
+
+// The sweep loop of pint_solve (host stop test after every sweep); allocates nothing.
+pint_status solve_loop(pint_plan* P, double* U, double* upd, double* upd_l2T, int* sweeps);
+// Record an error message for pint_last_error and return s.
+pint_status set_error(pint_status s, const std::string& msg);
+// pint_solve on a workspace lent for this call only (ws_cap bytes at ws); the
+// plan's own workspace is restored afterwards and the plan left unbound.
+pint_status solve_in_workspace(pint_plan* P, void* ws, size_t ws_cap, const double* v, const double* f,
+                               const double* fder, double* U, double* upd, double* upd_l2T, int* sweeps);
 
 }  // namespace pint

@@ -875,12 +875,12 @@ hipError_t tri1d_one(const SpaceArgs& a, hipStream_t st) {
 }
 
 // Split of a 1D system of size m between PCR (NT lanes) and Thomas (EPT
-// equations per lane): the built-in choice, and with var_tri = 1 one with
+// equations per lane): var_tri = 1 the built-in split, var_tri = 2 one with
 // more PCR lanes (fewer Thomas equations), where that differs.
 template <typename R>
 hipError_t tri1d_dispatch(const SpaceArgs& a, hipStream_t st) {
     const int m = a.mx;
-    const bool alt = a.var_tri == 1;
+    const bool alt = a.var_tri == 2;
     if (m <= 64) return tri1d_one<R, 1, 64>(a, st);
     if (m <= 128) return alt ? tri1d_one<R, 1, 128>(a, st) : tri1d_one<R, 2, 64>(a, st);
     if (m <= 256) return alt ? tri1d_one<R, 1, 256>(a, st) : tri1d_one<R, 4, 64>(a, st);
@@ -1031,7 +1031,8 @@ hipError_t cols_dispatch(const SpaceArgs& a, int axis, hipStream_t st) {
 }
 
 // The spatial solve is a short sequence of passes over the spectrum:
-//   1D: one pass (sine transform + divide + inverse, or PCR/Thomas);
+//   1D: one pass: sine transform + divide + inverse (Bluestein when 2(m+1) is
+//       not a power of two), or, when pinned (var_tri >= 1), PCR/Thomas;
 //   2D: DST-x rows, DST-y + divide + inverse DST-y, DST-x rows;
 //   3D: DST-x, DST-y, DST-z + divide + inverse, DST-y, DST-x.
 int pass_count(const SpaceArgs& a) { return a.dim == 1 ? 1 : (a.dim == 2 ? 3 : 5); }
@@ -1041,8 +1042,10 @@ bool dst1d(const SpaceArgs& a) {
     return (L & (L - 1)) == 0 && L <= (1u << kMaxLogL);
 }
 
+bool tri1d(const SpaceArgs& a) { return a.dim == 1 && !dst1d(a) && a.var_tri >= 1; }
+
 const char* pass_name(const SpaceArgs& a, int i) {
-    if (a.dim == 1) return dst1d(a) ? "dst_x_solve" : "tridiag_pcr_thomas";
+    if (a.dim == 1) return tri1d(a) ? "tridiag_pcr_thomas" : "dst_x_solve";
     if (a.dim == 2) return i == 1 ? "dst_y_solve" : "dst_x";
     static const char* n3[5] = {"dst_x", "dst_y", "dst_z_solve", "dst_y", "dst_x"};
     return n3[i];
@@ -1091,7 +1094,10 @@ hipError_t axis_pass(const SpaceArgs& a, int axis, hipStream_t st) {
 
 template <typename R>
 hipError_t space_pass(const SpaceArgs& a, int i, hipStream_t st) {
-    if (a.dim == 1) return dst1d(a) ? rows_dispatch<R, true>(a, st) : tri1d_dispatch<R>(a, st);
+    if (a.dim == 1) {
+        if (dst1d(a)) return rows_dispatch<R, true>(a, st);
+        return tri1d(a) ? tri1d_dispatch<R>(a, st) : blue_dispatch<R, true>(a, 0, st);
+    }
     if (a.dim == 2) return i == 1 ? axis_pass<R, true>(a, 1, st) : axis_pass<R, false>(a, 0, st);
     switch (i) {
         case 1: case 3: return axis_pass<R, false>(a, 1, st);
@@ -1152,8 +1158,6 @@ bool cols_variant_distinct(const SpaceArgs& a, bool mixed) {
     }
     return false;
 }
-
-bool tri_variant_distinct(const SpaceArgs& a) { return a.dim == 1 && !dst1d(a) && a.mx > 64 && a.mx <= kMaxTri1D; }
 
 }  // namespace pint
 

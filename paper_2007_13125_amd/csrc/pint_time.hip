@@ -237,12 +237,8 @@ hipError_t inv_dispatch(const InvArgs& a, int* nb, hipStream_t st) {
 
 }  // namespace
 
-thread_local bool g_prepare_only = false;
-
 // Workgroups that fit on the whole device at once for a kernel (persistent
-// launches), cached per kernel and lane count: the runtime is asked once, and
-// never again for a kernel that has been prepared, so a sweep recorded into a
-// graph makes no such query while its stream is capturing.
+// launches), cached per kernel and lane count: the runtime is asked once.
 int persistent_blocks(const void* fn, int nt) {
     static std::mutex mu;
     static std::map<std::pair<const void*, int>, int> cache;
@@ -280,8 +276,6 @@ hipError_t launch_fill(double* U, const double* v, long long N, int M, int zero,
 hipError_t launch_inverse(const InvArgs& a, bool mixed, int* nb, hipStream_t st) {
     return mixed ? inv_dispatch<float>(a, nb, st) : inv_dispatch<double>(a, nb, st);
 }
-
-void set_prepare_only(bool on) { g_prepare_only = on; }
 
 hipError_t launch_norm_reduce(const double* partial, int nb, double hd, double* out, hipStream_t st) {
     PINT_LAUNCH(k_norm_reduce, dim3(1), dim3(kNormNT), 0, st, partial, nb, hd, out);

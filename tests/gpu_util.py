@@ -69,6 +69,18 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def max_rel(a, b):
+    """Element-wise check beside rel_l2: the largest entry error relative to the
+    largest reference entry (an error confined to a few entries is not diluted
+    by the size of the array)."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def errors(a, b):
+    return rel_l2(a, b), max_rel(a, b)
+
+
 def oracle_modal(w, dofs):
     """Sequential oracle in sine-mode space for data that is a finite sine series.
 

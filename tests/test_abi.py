@@ -49,7 +49,15 @@ def test_invalid_params_rejected(change, status):
     assert len(B.lib().pint_last_error()) > 0
 
 
-@pytest.mark.parametrize("m,status", [((0,), B.PINT_E_ARG), ((4096,), B.PINT_E_UNSUPPORTED),
+def test_mixed_direct_rejected():
+    # the direct form's right-hand side would carry FP32 rounding into the fixed point
+    p = B.make_params(2, 1.0, 1.0, 64, 1e-3, precision="mixed", form="direct")
+    st, h = _create(B.make_grid((63,)), p)
+    assert st == B.PINT_E_UNSUPPORTED and not h.value
+    assert b"residual" in B.lib().pint_last_error()
+
+
+@pytest.mark.parametrize("m,status", [((0,), B.PINT_E_ARG), ((4096,), B.PINT_E_UNSUPPORTED), ((2048,), B.PINT_E_UNSUPPORTED),
                                       ((5, 0), B.PINT_E_ARG), ((2048, 15), B.PINT_E_UNSUPPORTED),
                                       ((15, 15, 2048), B.PINT_E_UNSUPPORTED), ((1023, 1023, 511), B.PINT_E_UNSUPPORTED)])
 def test_invalid_grids_rejected(m, status):

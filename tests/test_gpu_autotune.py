@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2007_13125_amd import workloads as wl
-from tests.gpu_util import oracle_solution, rel_l2, to_dev
+from tests.gpu_util import errors, oracle_solution, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -17,10 +17,11 @@ CASES = [
     (3, (15, 7, 3), 256, 3, 1.0, 1e-3),  # 3D march along z / one tile; y and z passes
     (3, (15, 3, 5), 512, 2, 1.0, 1e-3),  # 3D at N = 512 (the wide tile is not used there)
     (2, (61, 9), 256, 3, 0.5, 1e-3),     # CQ: y-march radix 8 / radix 16 / persistent one tile
-    (1, (200,), 16, 2, 1.0, 1e-2),       # 1D PCR/Thomas split
+    (1, (200,), 16, 2, 1.0, 1e-2),       # 1D: Bluestein sine solve / PCR-Thomas, two splits
+    (1, (600,), 64, 4, 0.5, 1e-3),       # the same on a longer line (CQ)
     (1, (255,), 64, 2, 1.0, 1e-3),       # 1D sine-transform solve: rows per workgroup
 ]
-KNOB_VALUES = [(0, 1), (0, 2), (0, 3), (1, 1), (2, 1), (3, 1)]
+KNOB_VALUES = [(0, 1), (0, 2), (0, 3), (1, 1), (2, 1), (3, 1), (3, 2)]
 
 
 def _case(dim, m, N, k, alpha, kappa):
@@ -62,8 +63,8 @@ def test_every_variant_matches_oracle(case, knob, value):
     v[knob] = value
     U, info, chosen = _solve(w, "fp64", variants=v)
     assert chosen == v
-    err = rel_l2(U, ref)
-    assert info["status"] == 0 and err <= 1e-11, (err, info)
+    err = errors(U, ref)
+    assert info["status"] == 0 and max(err) <= 1e-11, (err, info)
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -72,10 +73,12 @@ def test_autotuned_solve_matches_oracle(case, precision):
     w = _case(*case)
     ref = oracle_solution(w)
     U, info, chosen = _solve(w, precision, autotune=2)
-    assert len(chosen) == 4 and 0 <= chosen[0] <= 3 and all(c in (0, 1) for c in chosen[1:]), chosen
-    err = rel_l2(U, ref)
+    # knob 3 (1D sine solve or PCR/Thomas) changes accuracy, so the tuner leaves it at 0
+    assert len(chosen) == 4 and 0 <= chosen[0] <= 3 and chosen[1] in (0, 1) and chosen[2] in (0, 1), chosen
+    assert chosen[3] == 0, chosen
+    err = errors(U, ref)
     bar = 1e-11 if precision == "fp64" else 1e-10
-    assert info["status"] == 0 and err <= bar, (err, info, chosen)
+    assert info["status"] == 0 and max(err) <= bar, (err, info, chosen)
 
 
 def test_tune_after_bind_and_variant_errors():
@@ -95,16 +98,17 @@ def test_tune_after_bind_and_variant_errors():
         plan.set_variants([4, 0, 0, 0])
     with pytest.raises(PintError):
         plan.set_variants([0, 2, 0, 0])
+    with pytest.raises(PintError):
+        plan.set_variants([0, 0, 0, 3])
     plan.sweeps(U, 3)                        # tuned plan sweeps normally
     torch.cuda.synchronize()
     assert np.isfinite(U.cpu().numpy()).all()
     plan.close()
 
 
-@pytest.mark.skip(reason="a batch solve ended the host process with a segmentation fault inside "
-                         "pint_batch_solve (graph-replayed batch sweeps), also after the occupancy "
-                         "queries were moved out of the capture; the cause is not found, the graph path "
-                         "is switched off and batch cases stay off the GPU until it is")
+@pytest.mark.skip(reason="a batch solve once ended the host process with a segmentation fault (then "
+                         "through graph-replayed batch sweeps, since removed); the cause was never shown, "
+                         "so these batch cases stay off the GPU")
 def test_batch_autotune_each_instance():
     import torch
 
@@ -124,6 +128,6 @@ def test_batch_autotune_each_instance():
     for i, w in enumerate(ws):
         chosen = B.pint_plan_get_variants(h, i)
         assert 0 <= chosen[0] <= 3 and all(c in (0, 1) for c in chosen[1:]), chosen
-        err = rel_l2(Us[i].cpu().numpy(), oracle_solution(w))
-        assert err <= 1e-11, (i, err)
+        err = errors(Us[i].cpu().numpy(), oracle_solution(w))
+        assert max(err) <= 1e-11, (i, err)
     B.pint_plan_destroy(h)

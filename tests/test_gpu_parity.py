@@ -3,32 +3,20 @@ at sizes the oracle finishes in seconds that span several tiles and ragged
 tails, and the edge cases of the method (m = 1, smallest and largest N,
 k = 1 and 6, alpha < 1, 1D/2D/3D).
 
-Bars: converged trajectory within 1e-11 relative L2 of the sequential oracle
-in FP64 and 1e-10 in mixed precision; individual sweeps within a bound that
-scales like eps/kappa (the conditioning of the kappa scaling, Sec. 2.2
-roundoff paragraph) of the oracle's dense-DFT sweep."""
+Bars: converged trajectory within 1e-11 of the sequential oracle in FP64 and
+1e-10 in mixed precision, both as relative L2 over the trajectory and as the
+largest entry error relative to the largest entry; individual sweeps within a
+bound that scales like eps/kappa (the conditioning of the kappa scaling, Sec.
+2.2 roundoff paragraph) of the oracle's dense-DFT sweep, whose shifted solves
+are exact to FP64 rounding."""
 import numpy as np
 import pytest
 
 from paper_2007_13125_amd import workloads as wl
-from tests.gpu_util import gpu_iterates, gpu_solve, oracle_iterates, oracle_solution, rel_l2
+from tests.gpu_util import errors, gpu_iterates, gpu_solve, max_rel, oracle_iterates, oracle_solution
 
 pytestmark = pytest.mark.gpu
 EPS = np.finfo(float).eps
-
-
-def _is_pow2(x):
-    return x > 0 and (x & (x - 1)) == 0
-
-
-def solver_bound(m):
-    """Extra per-sweep error of the 1D PCR/Thomas solver (used when m + 1 is not a
-    power of two): parallel cyclic reduction loses accuracy in proportion to the
-    condition number ~ (m+1)^2 of the shifted Laplacian.  Sine-transform solves
-    (every other case) have no such term."""
-    if len(m) == 1 and not _is_pow2(m[0] + 1):
-        return 5 * EPS * (m[0] + 1) ** 2
-    return 0.0
 
 
 def _case(dim, m, N, k, alpha, kappa, seed=0):
@@ -98,9 +86,9 @@ def test_converged_matches_sequential_oracle(dim, m, N, k, alpha, kappa, precisi
     w = _case(dim, m, N, k, alpha, kappa)
     U, info = gpu_solve(w, precision=precision, tol=1e-14, max_sweeps=40)
     ref = oracle_solution(w)
-    err = rel_l2(U, ref)
+    err = errors(U, ref)
     bar = 1e-11 if precision == "fp64" else 1e-10
-    assert err <= bar, (err, info)
+    assert max(err) <= bar, (err, info)
 
 
 @pytest.mark.parametrize("dim,m,N,k,alpha,kappa", [c for c in SMALL if c[5] >= 1e-3])
@@ -108,7 +96,8 @@ def test_direct_form_matches_sequential_oracle(dim, m, N, k, alpha, kappa):
     w = _case(dim, m, N, k, alpha, kappa)
     U, info = gpu_solve(w, form="direct", tol=1e-12, max_sweeps=25)
     ref = oracle_solution(w)
-    assert rel_l2(U, ref) <= max(1e-11, 10 * solver_bound(m)), info
+    err = errors(U, ref)
+    assert max(err) <= 1e-11, (err, info)
 
 
 @pytest.mark.parametrize("dim,m,N,k,alpha,kappa", [c for c in SMALL if np.prod(c[1]) * c[2] <= 70000])
@@ -118,15 +107,20 @@ def test_each_sweep_matches_dense_dft_sweep(dim, m, N, k, alpha, kappa, form, in
     w = _case(dim, m, N, k, alpha, kappa)
     got, norms = gpu_iterates(w, 3, form=form, init=init)
     ref = oracle_iterates(w, 3, form=form, init=init)
-    # The oracle solves Step 2 by sparse LU, whose forward error in FP64 is ~eps times
-    # the condition number ~ 4 (m+1)^2 / pi^2 of the shifted Laplacian; the kappa^{-q/N}
-    # unscaling amplifies it by up to 1/kappa.  (An extended-precision sweep agrees with
-    # the sine-transform solves of the GPU path to well below this bound.)
-    cond = 4.0 * max(m) ** 2 / np.pi ** 2
-    bound = max(1e-12, 10 * EPS * np.log2(N) / kappa, 0.2 * EPS * cond / kappa, solver_bound(m))
+    # Both sides solve Step 2 to FP64 rounding (sine transforms with an exact per-mode
+    # divide on the GPU; refined LU in the oracle); what remains is the rounding of the
+    # transforms, amplified by up to 1/kappa by the kappa^{-q/N} unscaling, and in the
+    # residual form the rounding of the FP64 residual G - T U itself: each side forms
+    # A_h U, whose terms are ~|A_h| |U|, in its own summation order, and P^{-1} passes
+    # the low-mode part of that rounding on with a gain up to cond(A_h) =
+    # mu_max / mu_min (the direct form's right-hand side has no A_h U term).
+    mu = [(4.0 * (mi + 1) ** 2) * np.sin(np.pi * np.array([1, mi]) / (2.0 * (mi + 1))) ** 2 for mi in m]
+    cond = sum(x[1] for x in mu) / sum(x[0] for x in mu)
+    bound = max(1e-12, 10 * EPS * np.log2(N) / kappa, EPS * cond if form == "residual" else 0.0)
     for s in range(1, 4):
         scale = max(np.linalg.norm(ref[s]), 1e-300)
         assert np.linalg.norm(got[s] - ref[s]) / scale <= bound, (s, np.linalg.norm(got[s] - ref[s]) / scale)
+        assert max_rel(got[s], ref[s]) <= bound, (s, max_rel(got[s], ref[s]))
         upd = np.max(np.abs(ref[s] - ref[s - 1]))
         assert abs(norms[s - 1, 0] - upd) <= bound * max(upd, np.max(np.abs(ref[s]))) + 1e-300
 
@@ -138,9 +132,9 @@ def test_heat1d_workload_full():
     for precision in ("fp64", "mixed"):
         U, info = gpu_solve(w, precision=precision, tol=1e-12)
         assert info["status"] == 0
-        assert rel_l2(U, ref) <= (1e-11 if precision == "fp64" else 1e-10)
+        assert max(errors(U, ref)) <= (1e-11 if precision == "fp64" else 1e-10)
     U, info = gpu_solve(w, form="direct", tol=1e-12)
-    assert rel_l2(U, ref) <= 1e-11
+    assert max(errors(U, ref)) <= 1e-11
 
 
 def test_zero_data_gives_zero():

@@ -9,7 +9,7 @@ import torch
 
 from paper_2007_13125_amd import binding as B
 from paper_2007_13125_amd import workloads as wl
-from tests.gpu_util import oracle_solution, rel_l2, to_dev
+from tests.gpu_util import errors, oracle_solution, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +75,7 @@ def test_terminal_l2_stop_norm():
     U, info = p.solve(to_dev(w.v), to_dev(w.f))
     assert info["status"] == B.PINT_OK
     assert info["upd_l2T"][-1] <= 1e-13 < info["upd_l2T"][0]
-    assert rel_l2(U.cpu().numpy(), oracle_solution(w)) <= 1e-11
+    assert max(errors(U.cpu().numpy(), oracle_solution(w))) <= 1e-11
     p.close()
 
 
@@ -91,3 +91,8 @@ def test_errors_on_live_plan():
     with pytest.raises(B.PintError):
         B.pint_plan_set_workspace(p.h, small)
     p.close()
+    # a plan without a workspace refuses to bind (nothing is allocated on the solve path)
+    h = B.pint_plan_create(B.make_grid(w.m), B.make_params(w.k, w.alpha, w.T, w.N, w.kappa))
+    with pytest.raises(B.PintError):
+        B.pint_bind(h, torch.zeros(w.M, dtype=torch.float64, device="cuda"))
+    B.pint_plan_destroy(h)

@@ -134,6 +134,59 @@ def test_smaller_kappa_contracts_faster_and_ratio_independent_of_N():
     assert max(byN) / min(byN) < 1.1
 
 
+@pytest.mark.parametrize("m,length", [(1, 1.0), (7, 1.0), (100, 1.0), (255, 2.0), (999, 0.5)])
+def test_sine_eigenvalues_every_mode(m, length):
+    # The sine modes sin(j pi x / len), j = 1..m, are the eigenvectors of the
+    # second-difference factor of A_h; every eigenvalue (not only j = 1) is pinned
+    # against a dense symmetric eigensolver, and every mode against A_h itself.
+    g = Grid((m,), (length,))
+    A = laplacian(g).toarray()
+    mu = sine_eigenvalues(m, g.h[0])
+    assert np.allclose(np.sort(mu), np.linalg.eigvalsh(A), rtol=1e-11, atol=1e-9 * mu.max())
+    x = g.coords(0)
+    V = np.sin(np.pi * np.outer(x, np.arange(1, m + 1)) / length)
+    assert np.max(np.abs(A @ V - V * mu[None, :])) <= 1e-10 * mu.max()
+
+
+def test_sine_modes_of_the_box_laplacian():
+    # Products of sine modes (x fastest) are eigenvectors of the 2D/3D A_h with the
+    # sum of the axis eigenvalues, for low, high and mixed mode indices (the pairing
+    # of mode index and eigenvalue index that the sampled-mode oracles rely on).
+    rng = np.random.default_rng(7)
+    for m in [(15, 9), (31, 20, 7), (63, 63)]:
+        g = Grid(m)
+        A = laplacian(g)
+        mus = [sine_eigenvalues(mi, hi) for mi, hi in zip(g.m, g.h)]
+        for _ in range(6):
+            idx = [int(rng.integers(0, mi)) for mi in m]
+            mode = np.ones(1)
+            for a in range(g.dim):
+                mode = np.kron(np.sin(np.pi * (idx[a] + 1) * g.coords(a)), mode)
+            lam = sum(mus[a][idx[a]] for a in range(g.dim))
+            assert np.max(np.abs(A @ mode - lam * mode)) <= 1e-10 * lam, (m, idx)
+
+
+def test_refined_shifted_solve_is_exact_to_fp64():
+    # Step 2 of the oracle's sweep against an independent extended-precision solution
+    # in the sine basis (1D, m = 999: the shifted Laplacian's condition number is ~1e5).
+    m, N = 999, 8
+    g = Grid((m,))
+    prob = Problem(laplacian(g), 2, 1.0, 0.5, N, 0.5, np.ones(m))
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    ld = np.longdouble
+    pi = 4 * np.arctan(ld(1))
+    j = np.arange(1, m + 1)
+    S = np.sin(pi * (np.outer(j, j) % (2 * (m + 1))).astype(ld) / (m + 1))    # exact phase reduction
+    mu = (4 * ld(m + 1) ** 2) * np.sin(pi * j.astype(ld) / (2 * (m + 1))) ** 2
+    ta = ld(prob.tau) ** ld(prob.alpha)
+    for p in (0, 1, N // 2):
+        exact = (2 / ld(m + 1)) * (S @ ((S @ b.astype(np.clongdouble)) / (np.clongdouble(prob.d[p]) + ta * mu)))
+        got = prob.shifted_solve(p, b)
+        err = np.max(np.abs(got - exact.astype(np.complex128))) / np.max(np.abs(exact))
+        assert err <= 1e-14, (p, err)
+
+
 def test_eigenfunction_data_reduces_to_scalar_recurrence():
     # PIN-6: v = sin(pi x) sin(pi y) (x) ... and f = g(t) times the same mode give
     # U^n = y^n * mode with y^n the scalar scheme for mu = sum_i (4/h_i^2) sin^2(pi h_i/2).
