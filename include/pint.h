@@ -168,6 +168,44 @@ int pint_profile_sweeps(pint_plan *plan, double *U, int nsweeps, double *ms, con
 pint_status pint_solve(pint_plan *plan, const double *v, const double *f, const double *fder,
                        double *U, double *upd, double *upd_l2T, int *sweeps);
 
+/* The sequential-in-time solver: the corrected BDF-k / CQ-BDF-k scheme of
+ * the plan (Sec. 2.1 eq. BDF; Sec. 3.1 eq. BDF-frac; the stepping of the
+ * cost paragraph of Sec. 3.2) stepped one level after another, each step one
+ * shifted spatial solve (omega_0 tau^{-alpha} + A_h) U^n = rhs_n by the sweep's
+ * spatial passes.  This is the trajectory every WR sweep converges to, and
+ * the in-GPU baseline of the parallel-in-time method: O(k M N) history work
+ * for BDF-k, O(M N^2) for CQ-BDF-k, N dependent steps.  v, f, fder as in
+ * pint_bind (DEVICE); U DEVICE [N][M] out.  FP64 plans only
+ * (PINT_E_UNSUPPORTED for mixed).  Asynchronous on the plan's stream; uses
+ * the plan's workspace.  Errors: PINT_E_ARG (NULL, batch plan, no
+ * workspace), PINT_E_HIP. */
+pint_status pint_sequential_solve(pint_plan *plan, const double *v, const double *f, const double *fder,
+                                  double *U);
+
+/* Semilinear problems d_t^alpha u + A u + g(u) = f, u(0) = v, with the cubic
+ * g(u) = c3 u^3 + c1 u (Example 4's Allen-Cahn term for c3 = 1/eps^2,
+ * c1 = -1/eps^2), by Algorithm 3 of Sec. 4 (extension to nonlinear problems):
+ * the scheme of eq. BDF-CQ-m-r (the plan's k, alpha, N, T, with the Table 1
+ * rows carrying f(0) - A_h v - g(v)) is solved by the modified Newton
+ * iteration of eq. BDF-CQ-m-r-N, U_l = U_{l-1} + W_l from U_0^n = v, whose
+ * linearised system uses the time-averaged Jacobian g'(Ubar_{l-1}) (Ubar the
+ * mean of U_{l-1} over the N levels) and is solved by the WR sweeps of eq.
+ * BDF-CQ-m-r-N-w from W_{l,0} = 0, each by Algorithm 1/2 with the spatial
+ * operator A_h + diag(g'(Ubar)) (PCR/Thomas per frequency), until
+ * max |W_{l,m} - W_{l,m-1}| < params.tol or params.max_sweeps sweeps.
+ * 1D grids, FP64, residual form (the plan's params; PINT_E_UNSUPPORTED
+ * otherwise).  v, f, fder as in pint_bind (DEVICE); U DEVICE [N][M] out.
+ *   newton_steps  >= 1: Newton steps at most; stops early once max |W_l| <= newton_tol
+ *   inner_sweeps  HOST [newton_steps] (may be NULL): WR sweeps of each step
+ *   newton_upd    HOST [newton_steps] (may be NULL): max |W_l| of each step
+ *   steps_done    HOST (may be NULL)
+ * Returns PINT_OK when max |W_l| <= newton_tol, PINT_NOT_CONVERGED when the
+ * step budget (or an inner budget) ran out with valid outputs, PINT_E_DIVERGED
+ * on a non-finite update.  The workspace is the plan's (no allocation). */
+pint_status pint_nonlinear_solve(pint_plan *plan, double c3, double c1, const double *v, const double *f,
+                                 const double *fder, double *U, int newton_steps, double newton_tol,
+                                 int *inner_sweeps, double *newton_upd, int *steps_done);
+
 /* Many independent problems in one plan (each instance with its own grid and
  * params; N, k, alpha, precision may all differ).  Every instance is validated
  * as in pint_plan_create and gets its own tables and workspace, which this
@@ -196,10 +234,12 @@ pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const doub
  * knobs, each 0 = the built-in choice:
  *   [0] forward kernel: BDF-k residual 2D/3D sweeps 0 wide-tile march along
  *       the outer axis, 1 march with the time-FFT tile, 2 one workgroup per
- *       tile, 3 half-width wide-tile march with two workgroups per CU; CQ sweeps
- *       0 y-march with radix <= 8 transforms, 1 y-march with radix <= 16,
- *       2 (and 3) persistent one-tile-at-a-time kernel (a choice that does not apply
- *       to the problem falls back to the next one that does);
+ *       tile, 3 half-width wide-tile march with two workgroups per CU, 4 split
+ *       (a residual kernel marching along time, then a time-FFT kernel); CQ
+ *       sweeps 0 y-march with radix <= 8 transforms, 1 y-march with radix <= 16,
+ *       2 (3, 4) persistent one-tile-at-a-time kernel (a choice that does not
+ *       apply to the problem falls back to the next one that does; sweeps whose
+ *       time axis is not a power of two have one forward path);
  *   [1] rows per workgroup of the x sine pass: 0 built-in, 1 half as many;
  *   [2] column tile of the y/z passes: 0 built-in, 1 the other width;
  *   [3] 1D grids with 2(m+1) not a power of two: 0 sine solve (Bluestein),

@@ -47,6 +47,9 @@ EXPORTS = {
                                     POINTER(ctypes.c_char_p), c_int]),
     "pint_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                            POINTER(c_double), POINTER(c_double), POINTER(c_int)]),
+    "pint_sequential_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "pint_nonlinear_solve": (c_int, [c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                     c_double, POINTER(c_int), POINTER(c_double), POINTER(c_int)]),
     "pint_batch_plan_create": (c_int, [POINTER(c_void_p), c_int, POINTER(pint_grid),
                                        POINTER(pint_params), c_void_p]),
     "pint_batch_solve": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -168,6 +171,22 @@ def pint_solve(plan, v, f, fder, U, max_sweeps):
     _check(st, "pint_solve", allow=(PINT_OK, PINT_NOT_CONVERGED, PINT_E_DIVERGED))
     n = nsw.value
     return st, list(upd)[:n], list(upd2)[:n], n
+
+
+def pint_sequential_solve(plan, v, f, fder, U):
+    _check(lib().pint_sequential_solve(plan, _ptr(v), _ptr(f), _ptr(fder), _ptr(U)), "pint_sequential_solve")
+
+
+def pint_nonlinear_solve(plan, c3, c1, v, f, fder, U, newton_steps, newton_tol=0.0):
+    """Algorithm 3 for d^alpha u + A u + c3 u^3 + c1 u = f.  Returns (status,
+    inner sweep counts, max |W_l| per Newton step)."""
+    inner = (c_int * newton_steps)()
+    upd = (c_double * newton_steps)()
+    n = c_int(0)
+    st = lib().pint_nonlinear_solve(plan, float(c3), float(c1), _ptr(v), _ptr(f), _ptr(fder), _ptr(U),
+                                    int(newton_steps), float(newton_tol), inner, upd, ctypes.byref(n))
+    _check(st, "pint_nonlinear_solve", allow=(PINT_OK, PINT_NOT_CONVERGED))
+    return st, list(inner)[:n.value], list(upd)[:n.value]
 
 
 def pint_batch_plan_create(grids, params, stream=None):

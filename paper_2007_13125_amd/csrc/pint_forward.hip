@@ -945,6 +945,181 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
     }
 }
 
+// ---------------------------------------------------------------------------
+// Forward pass in two kernels (BDF-k residual form, 2D/3D).
+// k_resid: each workgroup owns PT x 256 consecutive spectrum slots and marches
+// along time, q = 0..N-1: it reads U at its slots once per row (the time
+// stencil's earlier rows stay in registers; the space neighbours are read
+// where they lie, mostly from cache) and writes the kappa^{q/N}-scaled residual
+// r~_q = kappa^{q/N} (f(t_{q+1}) + corrections + tau^{-1} s_q v
+//                     - tau^{-1} sum_{j<=min(q,k)} w_j U_{q-j} - A_h U_q)
+// to Rb[q][slot] in the spectrum's real type (zero in padding slots).
+// k_tfft: the time FFT of Rb, a tile of W slots x N rows in LDS, stored as the
+// half spectrum.
+constexpr int kResidNT = 256;
+template <typename RT, int PT>
+__global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc) {
+    constexpr int NT = kResidNT;
+    constexpr int TS = NT * PT;
+    const int ntiles = (a.Mp + TS - 1) / TS;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    // rows [q0, q1) of this workgroup (blockIdx.y-th chunk of qc rows); the
+    // time stencil's earlier rows q0-6..q0-1 are read once more to start it
+    const int q0 = blockIdx.y * qc, q1 = min(a.N, q0 + qc);
+    const int tid = threadIdx.x;
+    const size_t M = a.M;
+    const size_t sy = (size_t)a.mx, sz = (size_t)a.mx * a.my;
+    const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
+    const auto rU = buf_rsrc(a.U, (size_t)a.N * M * 8);
+    const auto rF = buf_rsrc(a.f ? a.f + M : a.U, (size_t)a.N * M * 8);
+    const auto rC = buf_rsrc(a.ncorr > 0 ? a.corr : a.U, (size_t)(a.ncorr > 0 ? a.ncorr : 1) * M * 8);
+    const double cf = a.f ? 1.0 : 0.0;
+    unsigned lu[PT], lxm[PT], lxp[PT], lym[PT], lyp[PT], lzm[PT], lzp[PT];
+    double vt[PT], hist[7][PT];
+    bool valid[PT];
+    int slot[PT];
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+        slot[e] = tile * TS + e * NT + tid;
+        const int d = slot_dof(slot[e], a.mx, a.mxp, a.Mp);
+        valid[e] = d >= 0;
+        const int dd = valid[e] ? d : 0;
+        const int x = dd % a.mx, rr = dd / a.mx, y = rr % a.my, z = rr / a.my;
+        lu[e] = valid[e] ? (unsigned)dd * 8u : kNoLane;
+        lxm[e] = (valid[e] && x > 0) ? lu[e] - 8u : kNoLane;
+        lxp[e] = (valid[e] && x < a.mx - 1) ? lu[e] + 8u : kNoLane;
+        lym[e] = (valid[e] && y > 0) ? lu[e] - 8u * (unsigned)sy : kNoLane;
+        lyp[e] = (valid[e] && y < a.my - 1) ? lu[e] + 8u * (unsigned)sy : kNoLane;
+        lzm[e] = (valid[e] && z > 0) ? lu[e] - 8u * (unsigned)sz : kNoLane;
+        lzp[e] = (valid[e] && z < a.mz - 1) ? lu[e] + 8u * (unsigned)sz : kNoLane;
+        vt[e] = valid[e] ? a.ta * a.v[dd] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) hist[j][e] = 0.0;
+    }
+    double wk[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) wk[j] = a.wk[j];
+    RT* __restrict__ out = reinterpret_cast<RT*>(a.Rb);
+    // The loads of row q+1 are issued before row q is combined and stored, so
+    // each lane has a whole row's loads in flight while it works.
+    double u[PT], fq[PT], cq[PT], nv[6][PT];
+    auto load_row = [&](int q, double (&uu)[PT], double (&ff)[PT], double (&cc)[PT], double (&nn)[6][PT]) {
+        const unsigned rq = (unsigned)q * (unsigned)M * 8u;   // row offset (the plan bounds N M 8 < 2^32)
+        auto off = [&](unsigned l) { return l == kNoLane ? kNoLane : rq + l; };
+#pragma unroll
+        for (int e = 0; e < PT; ++e) {
+            uu[e] = buf_ld(rU, off(lu[e]), 0.0);
+            ff[e] = buf_ld(rF, off(lu[e]), 0.0);
+            cc[e] = buf_ld(rC, q < a.ncorr ? off(lu[e]) : kNoLane, 0.0);
+            nn[0][e] = buf_ld(rU, off(lxm[e]), 0.0);
+            nn[1][e] = buf_ld(rU, off(lxp[e]), 0.0);
+            nn[2][e] = buf_ld(rU, off(lym[e]), 0.0);
+            nn[3][e] = buf_ld(rU, off(lyp[e]), 0.0);
+            nn[4][e] = buf_ld(rU, off(lzm[e]), 0.0);
+            nn[5][e] = buf_ld(rU, off(lzp[e]), 0.0);
+        }
+    };
+    auto emit = [&](int q) {
+        const double sq = a.s[q], sc = a.scale[q];
+#pragma unroll
+        for (int e = 0; e < PT; ++e) {
+#pragma unroll
+            for (int j = 6; j > 0; --j) hist[j][e] = hist[j - 1][e];
+            hist[0][e] = u[e];
+            double ts = 0.0;
+#pragma unroll
+            for (int j = 0; j < 7; ++j) ts += wk[j] * hist[j][e];
+            const double nb = a.ihx2 * (nv[0][e] + nv[1][e]) + a.ihy2 * (nv[2][e] + nv[3][e]) +
+                              a.ihz2 * (nv[4][e] + nv[5][e]);
+            const double r = vt[e] * sq + cf * fq[e] + cq[e] - a.ta * ts - (diag * u[e] - nb);
+            // slots past the last one (the final tile's tail) belong to no row
+            if (slot[e] < a.Mp) out[(size_t)q * a.Mp + slot[e]] = valid[e] ? (RT)(r * sc) : (RT)0;
+        }
+    };
+    // history rows q0-6..q0-1 (absent rows stay zero); hist[j] holds U_{q0-1-j+1}
+    // after the loop, i.e. the row before q0 in hist[0]
+#pragma unroll
+    for (int j = 6; j >= 1; --j) {
+        const int qh = q0 - j;
+        if (qh >= 0) {
+            const unsigned rq = (unsigned)qh * (unsigned)M * 8u;
+#pragma unroll
+            for (int e = 0; e < PT; ++e) {
+#pragma unroll
+                for (int i = 6; i > 0; --i) hist[i][e] = hist[i - 1][e];
+                hist[0][e] = buf_ld(rU, lu[e] == kNoLane ? kNoLane : rq + lu[e], 0.0);
+            }
+        }
+    }
+    load_row(q0, u, fq, cq, nv);
+    for (int q = q0; q + 1 < q1; ++q) {
+        double u2[PT], f2[PT], c2[PT], n2[6][PT];
+        load_row(q + 1, u2, f2, c2, n2);
+        emit(q);
+#pragma unroll
+        for (int e = 0; e < PT; ++e) {
+            u[e] = u2[e];
+            fq[e] = f2[e];
+            cq[e] = c2[e];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) nv[j][e] = n2[j][e];
+        }
+    }
+    emit(q1 - 1);
+}
+
+template <typename R, int LOGN, int W, int NT>
+__global__ __launch_bounds__(NT) void k_tfft(FwdArgs a) {
+    constexpr int N = 1 << LOGN;
+    constexpr int B = W / 2;
+    constexpr int PER = N * W / NT;
+    static_assert(PER * NT == N * W, "tile shape");
+    __shared__ cx<R> sm[N * B];
+    __shared__ cx<R> stw[N / 2];
+    R* smr = reinterpret_cast<R*>(sm);
+    const int ntiles = (a.Mp + W - 1) / W;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int tid = threadIdx.x;
+    const int s0 = tile * W;
+    const R* rb = reinterpret_cast<const R*>(a.Rb);
+    R v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = tid + i * NT;
+        const int q = idx / W, l = idx % W;
+        v[i] = s0 + l < a.Mp ? rb[(size_t)q * a.Mp + s0 + l] : (R)0;
+    }
+    for (int j = tid; j < N / 2; j += NT) stw[j] = reinterpret_cast<const cx<R>*>(a.tw)[j];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) smr[tid + i * NT] = v[i];
+    __syncthreads();
+    lds_fft<R, LOGN, B, NT, false, true, 0>(sm, stw);
+    store_half_spectrum<R, N, B, NT>(sm, reinterpret_cast<cx<R>*>(a.S), a.ldS, s0, a.Mp);
+}
+
+template <typename R, int LOGN>
+hipError_t fwd_split(const FwdArgs& a, int* nb, hipStream_t st) {
+    constexpr int PT = 2;
+    constexpr int TS = kResidNT * PT;
+    const int nres = ((a.Mp + TS - 1) / TS + 7) / 8 * 8;
+    constexpr int QC = 32;   // time rows per workgroup (6 history rows re-read per chunk)
+    const int nq = (a.N + QC - 1) / QC;
+    PINT_LAUNCH((k_resid<R, PT>), dim3(nres, nq), dim3(kResidNT), 0, st, a, QC);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // 128-byte row segments where the N x W tile fits 64 KB of LDS
+    constexpr int WL = 65536 / (N_OF(LOGN) * (int)sizeof(R));
+    constexpr int W0 = sizeof(R) == 8 ? 16 : 32;
+    constexpr int W = WL < W0 ? (WL < 2 ? 2 : WL) : W0;
+    constexpr int NT = N_OF(LOGN) * W >= 512 ? 512 : N_OF(LOGN) * W;
+    const int ntiles = ((a.Mp + W - 1) / W + 7) / 8 * 8;
+    if (nb) *nb = ntiles;
+    PINT_LAUNCH((k_tfft<R, LOGN, W, NT>), dim3(ntiles), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
 // Lanes of the CQ forward kernel (512: the register budget of two waves per SIMD
 // holds a radix-16 FP64 butterfly beside the per-element partial sums).
 #ifndef PINT_CQ_NT
@@ -1002,6 +1177,8 @@ int fwd_kind(const FwdArgs& a, bool cq) {
         return 2;
     }
     if (a.form != 0 || a.my == 1 || var == 2) return 2;
+    // split residual + time FFT (needs the slot-layout buffer and 32-bit row offsets)
+    if (var == 4 && a.Rb && (long long)a.N * a.M * 8 < (long long)kNoLane) return 5;
     constexpr int W = fwd_tile(LOGN);
     constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
     constexpr int NTM = (N_OF(LOGN) * W >= PINT_MARCH_NT) ? PINT_MARCH_NT : NT;
@@ -1075,6 +1252,7 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
         return hipErrorInvalidValue;
     }
     if (kind == 1) return fwd_march<R, LOGN, W, NTM, false>(a, nb, st);
+    if (kind == 5) return fwd_split<R, LOGN>(a, nb, st);
     const int ntiles = (a.Mp + W - 1) / W;
     const int grid = ((ntiles + 7) / 8) * 8;
     if (nb) *nb = grid;

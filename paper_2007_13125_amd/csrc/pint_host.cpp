@@ -16,6 +16,7 @@
 #include <vector>
 
 using pint::FwdArgs;
+using pint::GenArgs;
 using pint::InvArgs;
 using pint::SpaceArgs;
 
@@ -138,6 +139,18 @@ struct pint_plan {
     int logP[3] = {0, 0, 0};
     void *d_chirp[3] = {nullptr, nullptr, nullptr}, *d_bh[3] = {nullptr, nullptr, nullptr};
     void *d_twP[3] = {nullptr, nullptr, nullptr};
+    // time axis that is not a power of two >= 8: residual buffer + Bluestein DFT tables
+    bool gn = false;
+    int logPt = 0;
+    void *d_chirpT = nullptr, *d_bhT = nullptr, *d_twPT = nullptr;
+    double* Rb = nullptr;
+    size_t off_r = 0;
+    // 1D plans: buffers of the semilinear solve (Newton correction W, Newton
+    // residual R, Jacobian diagonal g'(Ubar))
+    double *nlW = nullptr, *nlR = nullptr, *nlD = nullptr;
+    size_t off_nl = 0;
+    int max_partials = 0;
+    double2* d_sigma_seq = nullptr;   // {omega_0 tau^{-alpha}, 0}: the shift of the sequential stepper
     double wk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double inv_factor = 1.0;
     // workspace
@@ -236,12 +249,13 @@ pint_status upload_cld(pint_plan* P, void** dst, const std::vector<cld>& v) {
     return s;
 }
 
-// Tables of the Bluestein sine transform of an axis with m interior nodes:
-// L = 2(m+1), chirp c_t = e^{-pi i t^2/L} (t < L, argument reduced mod 2L),
-// Bh = FFT_P(b)/P with b_l = conj(c_|l|) for |l| < L wrapped mod P, P >= 2L-1.
-pint_status upload_bluestein(pint_plan* P, int axis, int m) {
-    const long long L = 2LL * (m + 1);
-    int logp = 4;   // P >= 16, the smallest transform the kernels are built for
+// Bluestein tables of a length-L DFT: chirp c_t = e^{-pi i t^2/L} (t < L,
+// argument reduced mod 2L), Bh = FFT_P(b)/P with b_l = conj(c_|l|) for |l| < L
+// wrapped mod P, P >= max(2L-1, 2^min_logp); twiddles of length P.  Tables in
+// the spectrum precision.
+pint_status upload_bluestein_tables(pint_plan* P, long long L, int min_logp, void** chirp, void** bh, void** twP,
+                                    int* logp_out) {
+    int logp = min_logp;
     while ((1LL << logp) < 2 * L - 1) ++logp;
     const long long Pn = 1LL << logp;
     std::vector<cld> c(L), b(Pn, cld(0, 0));
@@ -254,15 +268,23 @@ pint_status upload_bluestein(pint_plan* P, int axis, int m) {
     for (auto& z : b) z /= (long double)Pn;
     pint_status rc;
     if (P->mixed) {
-        if ((rc = upload_cld<float2>(P, &P->d_chirp[axis], c)) != PINT_OK) return rc;
-        if ((rc = upload_cld<float2>(P, &P->d_bh[axis], b)) != PINT_OK) return rc;
+        if ((rc = upload_cld<float2>(P, chirp, c)) != PINT_OK) return rc;
+        if ((rc = upload_cld<float2>(P, bh, b)) != PINT_OK) return rc;
     } else {
-        if ((rc = upload_cld<double2>(P, &P->d_chirp[axis], c)) != PINT_OK) return rc;
-        if ((rc = upload_cld<double2>(P, &P->d_bh[axis], b)) != PINT_OK) return rc;
+        if ((rc = upload_cld<double2>(P, chirp, c)) != PINT_OK) return rc;
+        if ((rc = upload_cld<double2>(P, bh, b)) != PINT_OK) return rc;
     }
-    if ((rc = upload_tw(P, &P->d_twP[axis], Pn, P->mixed)) != PINT_OK) return rc;
-    P->logP[axis] = logp;
+    if ((rc = upload_tw(P, twP, Pn, P->mixed)) != PINT_OK) return rc;
+    *logp_out = logp;
     return PINT_OK;
+}
+
+// Sine transform of an axis with m interior nodes whose odd extension has
+// length L = 2(m+1) not a power of two (P >= 16, the smallest transform the
+// Bluestein DST kernels are built for).
+pint_status upload_bluestein(pint_plan* P, int axis, int m) {
+    return upload_bluestein_tables(P, 2LL * (m + 1), 4, &P->d_chirp[axis], &P->d_bh[axis], &P->d_twP[axis],
+                                   &P->logP[axis]);
 }
 
 pint_status validate(const pint_grid* g, const pint_params* p) {
@@ -286,13 +308,13 @@ pint_status validate(const pint_grid* g, const pint_params* p) {
     if (p->norm != PINT_NORM_INF && p->norm != PINT_NORM_L2_TERMINAL) return fail(PINT_E_ARG, "bad norm");
     if (p->init < PINT_INIT_V || p->init > PINT_INIT_USER) return fail(PINT_E_ARG, "bad init");
     if (p->N <= p->k) return fail(PINT_E_ARG, "N must exceed k");
+    if (p->N % 2 != 0) return fail(PINT_E_ARG, "N must be even");
     // The direct form's right-hand side would be assembled from FP32 spectra, so
     // its fixed point would carry FP32 rounding; the FP64 outer correction of
     // the mixed form needs the residual form.
     if (p->precision == PINT_MIXED && p->form == PINT_DIRECT)
         return fail(PINT_E_UNSUPPORTED, "mixed precision runs the residual form only");
-    if (!is_pow2(p->N) || p->N < (1 << pint::kMinLogN) || p->N > (1 << pint::kMaxLogN))
-        return fail(PINT_E_UNSUPPORTED, "N must be a power of two in 8..2048");
+    if (p->N > (1 << pint::kMaxLogN)) return fail(PINT_E_UNSUPPORTED, "N must be at most 2048");
     if (g->dim == 1) {
         if (2LL * (g->m[0] + 1) > (1 << pint::kMaxLogL))
             return fail(PINT_E_UNSUPPORTED, "1D grids are limited to m <= 2047");
@@ -327,6 +349,7 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     P->ldS = (int)((P->Mp + 63) / 64 * 64);
     P->mixed = p->precision == PINT_MIXED;
     P->cq = p->alpha < 1.0;
+    P->gn = !(is_pow2(p->N) && p->N >= (1 << pint::kMinLogN));
     const int N = P->N, k = p->k;
     const long double tau = (long double)p->T / N;
     P->tau = (double)tau;
@@ -390,11 +413,25 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     if ((rc = upload(P, &P->d_unscale, unscale.data(), N)) != PINT_OK) return rc;
     if ((rc = upload(P, &P->d_s, s.data(), N)) != PINT_OK) return rc;
     if ((rc = upload(P, &P->d_sigma, sigma.data(), P->nP)) != PINT_OK) return rc;
+    {
+        double2 s0;
+        s0.x = (double)((long double)P->ta * w[0]);
+        s0.y = 0.0;
+        if ((rc = upload(P, &P->d_sigma_seq, &s0, 1)) != PINT_OK) return rc;
+    }
     if ((rc = upload_tw(P, &P->d_twN, N, P->mixed)) != PINT_OK) return rc;
-    if (P->cq) {
+    {
         std::vector<double> wd(N);
         for (int j = 0; j < N; ++j) wd[j] = (double)w[j];
         if ((rc = upload(P, &P->d_w, wd.data(), N)) != PINT_OK) return rc;
+    }
+    // Bluestein time-DFT tables: sweeps whose time axis is not a power of two,
+    // and every 1D plan (the semilinear solve runs the general-length kernels)
+    if (P->gn || g->dim == 1) {
+        if ((rc = upload_bluestein_tables(P, N, 2, &P->d_chirpT, &P->d_bhT, &P->d_twPT, &P->logPt)) != PINT_OK)
+            return rc;
+    }
+    if (!P->gn && P->cq) {
         // spectrum of (omega, 0) on 2N points, divided by 2N (inverse normalisation)
         const int N2 = 2 * N;
         std::vector<double2> what(N2);
@@ -443,10 +480,22 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     off += align256((size_t)(k > 1 ? k - 1 : 1) * P->M * sizeof(double));
     P->off_partial = off;
     const size_t maxblocks = ((size_t)(P->Mp + 1) / 2 + 8) / 8 * 8 + 8;
+    P->max_partials = (int)maxblocks;
     off += align256(maxblocks * 2 * sizeof(double));
     P->off_norm = off;
     off += 256;
-    if (!P->cq && p->form == PINT_DIRECT) {
+    // residual buffer: [N][M] FP64 for a time axis that is not a power of two, or
+    // [N][Mp] (spectrum-slot layout, spectrum real type) for the split forward
+    // variant of BDF-k residual sweeps on 2D/3D grids
+    if (P->gn || g->dim == 1 || (!P->cq && p->form == PINT_RESIDUAL && g->dim >= 2)) {
+        P->off_r = off;
+        off += align256((size_t)N * P->Mp * sizeof(double));
+    }
+    if (g->dim == 1) {
+        P->off_nl = off;
+        off += 2 * align256((size_t)N * P->M * sizeof(double)) + align256((size_t)P->M * sizeof(double));
+    }
+    if (!P->cq && !P->gn && p->form == PINT_DIRECT) {
         P->off_sg = off;
         off += align256((size_t)P->nP * P->ldS * cbytes);
     }
@@ -463,6 +512,15 @@ void attach_workspace(pint_plan* P, void* ws) {
     P->partial = reinterpret_cast<double*>(b + P->off_partial);
     P->norm_tmp = reinterpret_cast<double*>(b + P->off_norm);
     P->Sg = P->off_sg ? static_cast<void*>(b + P->off_sg) : nullptr;
+    P->Rb = P->off_r ? reinterpret_cast<double*>(b + P->off_r) : nullptr;
+    if (P->off_nl) {
+        const size_t nm = align256((size_t)P->N * P->M * sizeof(double));
+        P->nlW = reinterpret_cast<double*>(b + P->off_nl);
+        P->nlR = reinterpret_cast<double*>(b + P->off_nl + nm);
+        P->nlD = reinterpret_cast<double*>(b + P->off_nl + 2 * nm);
+    } else {
+        P->nlW = P->nlR = P->nlD = nullptr;
+    }
 }
 
 // Workspace owned by the plan itself (batch instances only; single plans get
@@ -541,6 +599,7 @@ FwdArgs fwd_args(const pint_plan* P, const double* U) {
     fa.form = P->p.form == PINT_DIRECT ? 1 : 0;
     fa.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
     fa.var = P->var[0];
+    fa.Rb = P->Rb;
     return fa;
 }
 
@@ -571,8 +630,74 @@ SpaceArgs space_args(const pint_plan* P) {
     return sa;
 }
 
+GenArgs gen_args(const pint_plan* P, double* U) {
+    GenArgs ga{};
+    ga.U = U;
+    ga.Uw = U;
+    ga.f = P->f;
+    ga.v = P->v;
+    ga.corr = P->p.k > 1 ? P->corr : nullptr;
+    ga.Rb = P->Rb;
+    ga.S = P->S;
+    ga.scale = P->d_scale;
+    ga.unscale = P->d_unscale;
+    ga.s = P->d_s;
+    ga.w = P->d_w;
+    ga.chirp = P->d_chirpT;
+    ga.bh = P->d_bhT;
+    ga.twP = P->d_twPT;
+    ga.partial = P->partial;
+    ga.logP = P->logPt;
+    ga.max_partials = P->max_partials;
+    ga.M = P->M;
+    ga.N = P->N;
+    ga.k = P->p.k;
+    ga.ldS = P->ldS;
+    ga.mxp = P->mxp;
+    ga.Mp = P->Mp;
+    ga.mx = P->mx;
+    ga.my = P->my;
+    ga.mz = P->mz;
+    ga.jmax = P->cq ? P->N - 1 : P->p.k;
+    ga.ihx2 = P->ih2[0];
+    ga.ihy2 = P->ih2[1];
+    ga.ihz2 = P->ih2[2];
+    ga.ta = P->ta;
+    ga.kappa = P->p.kappa;
+    ga.form = P->p.form == PINT_DIRECT ? 1 : 0;
+    ga.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
+    ga.an = P->d_an;
+    return ga;
+}
+
+// One sweep of a plan whose time axis is not a power of two >= 8.
+pint_status one_sweep_gn(pint_plan* P, double* U, double* norms_out, Profiler* prof) {
+    const GenArgs ga = gen_args(P, U);
+    PROF_BEGIN(prof, "residual_rhs");
+    HIP_TRY(pint::launch_gn_resid(ga, P->st));
+    PROF_END(prof);
+    PROF_BEGIN(prof, "forward_tdft");
+    HIP_TRY(pint::launch_gn_forward(ga, P->mixed, P->st));
+    PROF_END(prof);
+    const SpaceArgs sa = space_args(P);
+    for (int i = 0; i < pint::space_pass_count(sa); ++i) {
+        PROF_BEGIN(prof, pint::space_pass_name(sa, i));
+        HIP_TRY(pint::launch_space_pass(sa, P->mixed, i, P->st));
+        PROF_END(prof);
+    }
+    int nb = 0;
+    PROF_BEGIN(prof, "inverse_tdft_update");
+    HIP_TRY(pint::launch_gn_inverse(ga, P->mixed, &nb, P->st));
+    PROF_END(prof);
+    PROF_BEGIN(prof, "norm_reduce");
+    HIP_TRY(pint::launch_norm_reduce(P->partial, nb, P->hd, norms_out, P->st));
+    PROF_END(prof);
+    return PINT_OK;
+}
+
 pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof = nullptr) {
     if (prof) prof->cursor = 0;
+    if (P->gn) return one_sweep_gn(P, U, norms_out, prof);
     FwdArgs fa = fwd_args(P, U);
     if (P->Sg) {
         // direct form, BDF-k: stored source spectrum + the k relaxation rows
@@ -675,7 +800,7 @@ pint_status tune_plan(pint_plan* P, const double* U, int reps) {
         P->var[k] = arg;
         return PINT_OK;
     };
-    if (!P->Sg) {
+    if (!P->Sg && !P->gn) {
         std::vector<int> cand{0};
         const FwdArgs fa0 = fwd_args(P, U);
         for (int v = 1; v < pint::kFwdVariants; ++v)
@@ -754,6 +879,81 @@ pint_status solve_loop(pint_plan* P, double* U, double* upd, double* upd_l2T, in
 }
 
 pint_status set_error(pint_status s, const std::string& msg) { return fail(s, msg); }
+
+// One WR sweep of the linearised system of a Newton step (eq. BDF-CQ-m-r-N-w)
+// on W, residual form: W += P^{-1} (R - T_D W) with T_D the all-at-once
+// operator of the scheme with zero history and the spatial operator
+// A_h + diag(D); time DFTs of general length, PCR/Thomas per frequency.
+pint_status nl_sweep(pint_plan* P, double* norms_out) {
+    GenArgs ga = gen_args(P, P->nlW);
+    ga.f = P->nlR - P->M;            // row q + 1 of f is row q of R
+    ga.v = nullptr;
+    ga.corr = nullptr;
+    ga.ncorr = 0;
+    ga.form = 0;
+    ga.dvar = P->nlD;
+    HIP_TRY(pint::launch_gn_resid(ga, P->st));
+    HIP_TRY(pint::launch_gn_forward(ga, P->mixed, P->st));
+    SpaceArgs sa = space_args(P);
+    sa.dvar = P->nlD;
+    HIP_TRY(pint::launch_space_pass(sa, P->mixed, 0, P->st));
+    int nb = 0;
+    HIP_TRY(pint::launch_gn_inverse(ga, P->mixed, &nb, P->st));
+    HIP_TRY(pint::launch_norm_reduce(P->partial, nb, P->hd, norms_out, P->st));
+    return PINT_OK;
+}
+
+pint_status fetch_norms(pint_plan* P) {
+    HIP_TRY(hipMemcpyAsync(P->h_norms, P->norm_tmp, 2 * sizeof(double), hipMemcpyDeviceToHost, P->st));
+    HIP_TRY(hipStreamSynchronize(P->st));
+    return PINT_OK;
+}
+
+// Algorithm 3 on a bound 1D plan.
+pint_status nonlinear_solve(pint_plan* P, double c3, double c1, double* U, int steps, double newton_tol,
+                            int* inner, double* newton_upd, int* done) {
+    if (done) *done = 0;
+    HIP_TRY(pint::launch_fill(U, P->v, P->N, P->M, 0, P->st));   // U_0^n = v
+    for (int l = 0; l < steps; ++l) {
+        // time-averaged Jacobian g'(Ubar) and the Newton residual
+        HIP_TRY(pint::launch_nl_mean_dg(U, P->nlD, P->N, P->M, c3, c1, P->st));
+        GenArgs ga = gen_args(P, U);
+        ga.form = 0;
+        ga.nl = 1;
+        ga.raw = 1;
+        ga.c3 = c3;
+        ga.c1 = c1;
+        ga.Rb = P->nlR;
+        HIP_TRY(pint::launch_gn_resid(ga, P->st));
+        HIP_TRY(pint::launch_fill(P->nlW, nullptr, P->N, P->M, 1, P->st));   // W_{l,0} = 0
+        int m = 0;
+        bool ok = false;
+        for (m = 1; m <= P->p.max_sweeps; ++m) {
+            pint_status rc = nl_sweep(P, P->norm_tmp);
+            if (rc != PINT_OK) return rc;
+            if ((rc = fetch_norms(P)) != PINT_OK) return rc;
+            const double upd = P->h_norms[0];
+            if (!std::isfinite(upd)) return fail(PINT_E_DIVERGED, "non-finite inner update");
+            if (upd < P->p.tol) {
+                ok = true;
+                break;
+            }
+        }
+        if (inner) inner[l] = ok ? m : P->p.max_sweeps;
+        int nb = 0;
+        HIP_TRY(pint::launch_nl_axpy(U, P->nlW, P->partial, P->N, P->M, P->max_partials, &nb, P->st));
+        HIP_TRY(pint::launch_norm_reduce(P->partial, nb, P->hd, P->norm_tmp, P->st));
+        pint_status rc = fetch_norms(P);
+        if (rc != PINT_OK) return rc;
+        const double wn = P->h_norms[0];
+        if (newton_upd) newton_upd[l] = wn;
+        if (done) *done = l + 1;
+        if (!std::isfinite(wn)) return fail(PINT_E_DIVERGED, "non-finite Newton update");
+        if (!ok) return PINT_NOT_CONVERGED;
+        if (wn <= newton_tol) return PINT_OK;
+    }
+    return PINT_NOT_CONVERGED;
+}
 
 // pint_solve on a workspace the caller names for this call only (the static
 // scratch of the allocation-free entry point): the plan's own workspace
@@ -912,6 +1112,41 @@ pint_status pint_solve(pint_plan* P, const double* v, const double* f, const dou
     if ((rc = pint_init_iterate(P, U)) != PINT_OK) return rc;
     if (P->tune_reps > 0 && !P->tuned && (rc = tune_plan(P, U, P->tune_reps)) != PINT_OK) return rc;
     return pint::solve_loop(P, U, upd, upd_l2T, sweeps);
+}
+
+pint_status pint_sequential_solve(pint_plan* P, const double* v, const double* f, const double* fder, double* U) {
+    if (!P || !U || !v) return fail(PINT_E_ARG, "plan, v and U must not be NULL");
+    if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans are not supported here");
+    if (P->mixed) return fail(PINT_E_UNSUPPORTED, "the sequential solver runs in FP64");
+    pint_status rc = pint_bind(P, v, f, fder);
+    if (rc != PINT_OK) return rc;
+    GenArgs ga = gen_args(P, U);
+    SpaceArgs sa = space_args(P);
+    sa.nP = 1;
+    sa.sigma = P->d_sigma_seq;
+    sa.var_tri = 0;
+    const int passes = pint::space_pass_count(sa);
+    for (int n = 1; n <= P->N; ++n) {
+        HIP_TRY(pint::launch_seq_rhs(ga, n, P->S, P->st));
+        for (int i = 0; i < passes; ++i) HIP_TRY(pint::launch_space_pass(sa, false, i, P->st));
+        HIP_TRY(pint::launch_seq_store(ga, n, P->S, P->st));
+    }
+    return PINT_OK;
+}
+
+pint_status pint_nonlinear_solve(pint_plan* P, double c3, double c1, const double* v, const double* f,
+                                 const double* fder, double* U, int newton_steps, double newton_tol,
+                                 int* inner_sweeps, double* newton_upd, int* steps_done) {
+    if (!P || !U || !v) return fail(PINT_E_ARG, "plan, v and U must not be NULL");
+    if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans are not supported here");
+    if (P->dim != 1 || !P->nlW) return fail(PINT_E_UNSUPPORTED, "the semilinear solve is implemented for 1D grids");
+    if (newton_steps < 1 || !(newton_tol >= 0.0) || !std::isfinite(c3) || !std::isfinite(c1))
+        return fail(PINT_E_ARG, "bad arguments to pint_nonlinear_solve");
+    if (P->p.form != PINT_RESIDUAL || P->p.precision != PINT_FP64)
+        return fail(PINT_E_UNSUPPORTED, "the semilinear solve runs FP64 residual-form sweeps");
+    pint_status rc = pint_bind(P, v, f, fder);
+    if (rc != PINT_OK) return rc;
+    return pint::nonlinear_solve(P, c3, c1, U, newton_steps, newton_tol, inner_sweeps, newton_upd, steps_done);
 }
 
 pint_status pint_plan_set_autotune(pint_plan* P, int reps) {

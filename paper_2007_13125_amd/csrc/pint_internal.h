@@ -40,6 +40,8 @@ struct FwdArgs {
     int form;               // 0 residual, 1 direct, 2 the source part G alone (U not read)
     int ncorr;              // number of correction rows (k-1, or 0)
     int var;                // forward kernel variant (kFwdVariants; 0 = built-in choice)
+    void* Rb;               // [N][Mp] kappa-scaled residual in spectrum-slot layout, in the
+                            // spectrum's real type (split forward variant), or nullptr
 };
 
 // Inverse time FFT + unscale + update + norm partials.
@@ -52,6 +54,42 @@ struct InvArgs {
     int M, N, ldS;
     int mx, mxp, Mp;        // grid row length and the padded spectrum layout
     int form;               // 0 residual (U += delta), 1 direct (U = delta)
+};
+
+// Sweeps whose time axis is not a power of two (pint_gentime.hip): residual /
+// right-hand side into an FP64 buffer, then length-N Bluestein DFTs.
+struct GenArgs {
+    const double* U;        // [N][M] current iterate (residual kernel)
+    double* Uw;             // [N][M] iterate updated in place (inverse kernel)
+    const double* f;        // [N+1][M] or nullptr
+    const double* v;        // [M]
+    const double* corr;     // [k-1][M] starting-step corrections, or nullptr
+    double* Rb;             // [N][M] kappa^{q/N}-scaled residual / right-hand side (FP64)
+    void* S;                // [N/2+1][ldS] complex spectrum (double2 or float2)
+    const double* scale;    // [N] kappa^{q/N}
+    const double* unscale;  // [N] kappa^{-q/N} / N
+    const double* s;        // [N] s_n
+    const double* w;        // [N] time weights omega_0..omega_{N-1} (zero beyond k for BDF-k)
+    const void* chirp;      // [N] e^{-pi i t^2/N}, spectrum precision
+    const void* bh;         // [P] FFT_P of the conjugate chirp wrapped around 0, divided by P
+    const void* twP;        // [P] e^{-2 pi i j/P}
+    double* partial;        // [max_partials][2] norm partials of the inverse kernel
+    int logP;               // P = 2^logP >= 2N - 1
+    int max_partials;
+    int M, N, k, ldS, mxp, Mp, mx, my, mz;
+    int jmax;               // last nonzero weight index (k for BDF-k, N-1 for CQ)
+    double ihx2, ihy2, ihz2, ta, kappa;
+    int form;               // 0 residual, 1 direct
+    int ncorr;
+    // semilinear problems (Algorithm 3): residual of d^alpha u + A u + g(u) = f
+    // with g(u) = c3 u^3 + c1 u when nl = 1 (the Table 1 rows then also carry
+    // -a_n g(v), a_n from an); dvar, when set, adds diag(dvar) to A_h (the
+    // time-averaged Jacobian of the linearised system); raw = 1 writes the
+    // residual unscaled (no kappa^{q/N}).
+    int nl, raw;
+    double c3, c1;
+    const double* an;       // [5] a_n of Table 1
+    const double* dvar;     // [M] or nullptr
 };
 
 // Spatial shifted solves on the spectrum.
@@ -74,15 +112,19 @@ struct SpaceArgs {
     int var_cols;           // y/z-pass variant: 0 = built-in column tile, 1 = the other width
     int var_tri;            // 1D with 2(m+1) not a power of two: 0 = Bluestein sine solve,
                             // 1 = PCR/Thomas (built-in split), 2 = PCR/Thomas with more PCR lanes
+    const double* dvar;     // 1D only: [m] extra diagonal of the shifted operator (sigma_p + A_h +
+                            // diag(dvar)), solved by PCR/Thomas whatever var_tri; or nullptr
 };
 
 // Kernel variants the autotuner chooses between (index 0 is the built-in choice).
 //   forward, BDF-k residual 2D/3D: 0 wide-tile march along the outer axis when
 //     eligible (else 1), 1 march with the time-FFT tile, 2 one workgroup per tile,
 //     3 half-width wide-tile march, two workgroups per CU (N in 64..512);
+//     4 split: a residual kernel that marches along time (one pass over U, the
+//     time stencil in registers) into a slot-layout buffer, then a time-FFT kernel;
 //   forward, CQ: 0 y-march with radix <= 8 transforms when eligible (else 2),
 //     1 y-march with radix <= 16, 2 persistent one-tile-at-a-time kernel.
-constexpr int kFwdVariants = 4;
+constexpr int kFwdVariants = 5;
 
 // Host-side launchers (defined in pint_kernels.hip).  Each returns the
 // hipError_t of the launch; shapes are validated by the caller.
@@ -97,6 +139,19 @@ hipError_t launch_inverse(const InvArgs& a, bool mixed, int* nblocks_out, hipStr
 // spectrum Sg and the last k rows of U (replaces launch_forward).
 hipError_t launch_inject(const FwdArgs& a, const void* Sg, bool mixed, hipStream_t st);
 hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st);
+// General-N sweeps (time axis not a power of two).
+hipError_t launch_gn_resid(const GenArgs& a, hipStream_t st);
+hipError_t launch_gn_forward(const GenArgs& a, bool mixed, hipStream_t st);
+hipError_t launch_gn_inverse(const GenArgs& a, bool mixed, int* nblocks_out, hipStream_t st);
+// Sequential-in-time solver: right-hand side of step n into one complex plane
+// (slot order), and U^n back from the solved plane.
+hipError_t launch_seq_rhs(const GenArgs& a, int n, void* plane, hipStream_t st);
+hipError_t launch_seq_store(const GenArgs& a, int n, const void* plane, hipStream_t st);
+// Semilinear solves: dg[x] = g'(mean over the N levels of U[.][x]); U += W with
+// per-workgroup (max |W|, sum of W^2 at the last level) partials.
+hipError_t launch_nl_mean_dg(const double* U, double* dg, int N, int M, double c3, double c1, hipStream_t st);
+hipError_t launch_nl_axpy(double* U, const double* W, double* partial, int N, int M, int max_partials, int* nb,
+                          hipStream_t st);
 int space_pass_count(const SpaceArgs& a);
 const char* space_pass_name(const SpaceArgs& a, int pass);
 hipError_t launch_space_pass(const SpaceArgs& a, bool mixed, int pass, hipStream_t st);
@@ -109,8 +164,8 @@ bool rows_variant_distinct(const SpaceArgs& a, bool mixed);
 bool cols_variant_distinct(const SpaceArgs& a, bool mixed);
 
 // Largest time-FFT length and DST length the kernels are compiled for.
-constexpr int kMaxLogN = 11;      // N <= 2048
-constexpr int kMinLogN = 3;       // N >= 8
+constexpr int kMaxLogN = 11;      // N <= 2048 (any even N; powers of two >= 8 take the FFT kernels)
+constexpr int kMinLogN = 3;       // smallest power of two the FFT kernels take
 constexpr int kMaxLogL = 12;      // DST via odd extension of length 2(m+1) <= 4096
 constexpr int kMinLogL = 2;
 constexpr int kMaxTri1D = 2048;   // 1D tridiagonal systems up to this size

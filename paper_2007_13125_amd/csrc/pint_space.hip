@@ -33,7 +33,7 @@ __global__ __launch_bounds__(NT) void k_tri1d(SpaceArgs a) {
         if (i < m) {
             ea[e] = i > 0 ? off : zero;
             ec[e] = i < m - 1 ? off : zero;
-            eb[e] = diag;
+            eb[e] = a.dvar ? mk<T>((R)(sg.x + 2.0 * a.ih2[0] + a.dvar[i]), (R)sg.y) : diag;
             ed[e] = X[i];
         } else {
             ea[e] = zero;
@@ -1042,7 +1042,7 @@ bool dst1d(const SpaceArgs& a) {
     return (L & (L - 1)) == 0 && L <= (1u << kMaxLogL);
 }
 
-bool tri1d(const SpaceArgs& a) { return a.dim == 1 && !dst1d(a) && a.var_tri >= 1; }
+bool tri1d(const SpaceArgs& a) { return a.dim == 1 && (a.dvar || (!dst1d(a) && a.var_tri >= 1)); }
 
 const char* pass_name(const SpaceArgs& a, int i) {
     if (a.dim == 1) return tri1d(a) ? "tridiag_pcr_thomas" : "dst_x_solve";
@@ -1095,8 +1095,8 @@ hipError_t axis_pass(const SpaceArgs& a, int axis, hipStream_t st) {
 template <typename R>
 hipError_t space_pass(const SpaceArgs& a, int i, hipStream_t st) {
     if (a.dim == 1) {
-        if (dst1d(a)) return rows_dispatch<R, true>(a, st);
-        return tri1d(a) ? tri1d_dispatch<R>(a, st) : blue_dispatch<R, true>(a, 0, st);
+        if (tri1d(a)) return tri1d_dispatch<R>(a, st);
+        return dst1d(a) ? rows_dispatch<R, true>(a, st) : blue_dispatch<R, true>(a, 0, st);
     }
     if (a.dim == 2) return i == 1 ? axis_pass<R, true>(a, 1, st) : axis_pass<R, false>(a, 0, st);
     switch (i) {

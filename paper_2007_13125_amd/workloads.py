@@ -28,6 +28,9 @@ Workloads (all on boxes with homogeneous Dirichlet data, len = 1):
 * ``example2`` Sec. 4 Example 2: 1D, h = 1/1000, alpha = 0.5, T = 0.1,
                N = 100, kappa = 0.1, v = discrete Dirac at x = 1/2
                (value 1/h at that node), f = 0.
+* ``example4`` Sec. 4 Example 4 (semilinear, Allen-Cahn term): 1D,
+               h = 1/1000, T = 0.4, N = 100, kappa = 0.1, v = 0, f from the
+               manufactured solution t^2/2 sin(2 pi x).
 
 Sizes can be shrunk (``m``, ``N`` keywords) for parity tests at sizes the
 oracle finishes in seconds; the recipe stays the same.
@@ -190,6 +193,23 @@ def example2(k, M=999, N=100):
     v = np.zeros(M)
     v[(M + 1) // 2 - 1] = M + 1.0          # node x = 1/2, value 1/h
     return Workload("example2", (M,), k, 0.5, 0.1, N, 0.1, v, None, None, 1e-12)
+
+
+def example4(k, alpha, M=999, N=100, eps=1.0):
+    """Sec. 4, Example 4 (Table 4): 1D Allen-Cahn term g(u) = (u^3 - u)/eps^2,
+    T = 0.4, kappa = 0.1, v = 0, f such that u = t^2/Gamma(3) sin(2 pi x) solves
+    the continuous problem: f = t^{2-alpha}/Gamma(3-alpha) sin(2 pi x)
+    + (2 pi)^2 u + g(u).  Returns (workload, c3, c1); d^l f/dt^l (0) = 0."""
+    from math import gamma
+    T = 0.4
+    x = _nodes(M)
+    t = T * np.arange(N + 1) / N
+    s = np.sin(2 * np.pi * x)
+    u = (t ** 2 / gamma(3.0))[:, None] * s[None, :]
+    f = (t ** (2 - alpha) / gamma(3.0 - alpha))[:, None] * s[None, :] + (2 * np.pi) ** 2 * u + (u ** 3 - u) / eps ** 2
+    fder = np.zeros((k - 2, M)) if k > 2 else None
+    w = Workload("example4", (M,), k, alpha, T, N, 0.1, np.zeros(M), f, fder, 1e-12)
+    return w, 1.0 / eps ** 2, -1.0 / eps ** 2
 
 
 CONFIGS = {

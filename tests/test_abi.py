@@ -37,7 +37,8 @@ def _create(grid, params):
     (dict(k=0), B.PINT_E_ARG), (dict(k=7), B.PINT_E_ARG), (dict(alpha=0.0), B.PINT_E_ARG),
     (dict(alpha=1.5), B.PINT_E_ARG), (dict(kappa=0.0), B.PINT_E_ARG), (dict(kappa=1.0), B.PINT_E_ARG),
     (dict(T=-1.0), B.PINT_E_ARG), (dict(tol=0.0), B.PINT_E_ARG), (dict(max_sweeps=0), B.PINT_E_ARG),
-    (dict(N=4, k=4), B.PINT_E_ARG), (dict(N=100), B.PINT_E_UNSUPPORTED), (dict(N=4096), B.PINT_E_UNSUPPORTED),
+    (dict(N=4, k=4), B.PINT_E_ARG), (dict(N=101), B.PINT_E_ARG), (dict(N=2050), B.PINT_E_UNSUPPORTED),
+    (dict(N=4096), B.PINT_E_UNSUPPORTED),
 ])
 def test_invalid_params_rejected(change, status):
     base = dict(k=2, alpha=1.0, T=1.0, N=64, kappa=1e-3)

@@ -21,7 +21,7 @@ CASES = [
     (1, (600,), 64, 4, 0.5, 1e-3),       # the same on a longer line (CQ)
     (1, (255,), 64, 2, 1.0, 1e-3),       # 1D sine-transform solve: rows per workgroup
 ]
-KNOB_VALUES = [(0, 1), (0, 2), (0, 3), (1, 1), (2, 1), (3, 1), (3, 2)]
+KNOB_VALUES = [(0, 1), (0, 2), (0, 3), (0, 4), (1, 1), (2, 1), (3, 1), (3, 2)]
 
 
 def _case(dim, m, N, k, alpha, kappa):
@@ -41,7 +41,9 @@ def _solve(w, precision, variants=None, autotune=0):
     from paper_2007_13125_amd.binding import Plan
     print(f"[gpu] autotune case {w.name} m={w.m} N={w.N} alpha={w.alpha} {precision} "
           f"variants={variants} autotune={autotune}", flush=True)
-    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-14, max_sweeps=40, precision=precision)
+    # the update norm levels off near eps cond(A_h) |U|: ~2e-13 on the 600-point line
+    tol = 1e-14 if max(w.m) < 300 else 1e-12
+    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=tol, max_sweeps=40, precision=precision)
     if variants is not None:
         plan.set_variants(variants)
     if autotune:
@@ -74,7 +76,7 @@ def test_autotuned_solve_matches_oracle(case, precision):
     ref = oracle_solution(w)
     U, info, chosen = _solve(w, precision, autotune=2)
     # knob 3 (1D sine solve or PCR/Thomas) changes accuracy, so the tuner leaves it at 0
-    assert len(chosen) == 4 and 0 <= chosen[0] <= 3 and chosen[1] in (0, 1) and chosen[2] in (0, 1), chosen
+    assert len(chosen) == 4 and 0 <= chosen[0] <= 4 and chosen[1] in (0, 1) and chosen[2] in (0, 1), chosen
     assert chosen[3] == 0, chosen
     err = errors(U, ref)
     bar = 1e-11 if precision == "fp64" else 1e-10
@@ -93,9 +95,9 @@ def test_tune_after_bind_and_variant_errors():
     plan.bind(to_dev(w.v), to_dev(w.f), to_dev(w.fder))
     plan.init_iterate(U)
     chosen = plan.tune(U, 2)
-    assert 0 <= chosen[0] <= 3 and all(c in (0, 1) for c in chosen[1:]), chosen
+    assert 0 <= chosen[0] <= 4 and all(c in (0, 1) for c in chosen[1:]), chosen
     with pytest.raises(PintError):
-        plan.set_variants([4, 0, 0, 0])
+        plan.set_variants([5, 0, 0, 0])
     with pytest.raises(PintError):
         plan.set_variants([0, 2, 0, 0])
     with pytest.raises(PintError):
@@ -127,7 +129,7 @@ def test_batch_autotune_each_instance():
     assert st == B.PINT_OK
     for i, w in enumerate(ws):
         chosen = B.pint_plan_get_variants(h, i)
-        assert 0 <= chosen[0] <= 3 and all(c in (0, 1) for c in chosen[1:]), chosen
+        assert 0 <= chosen[0] <= 4 and all(c in (0, 1) for c in chosen[1:]), chosen
         err = errors(Us[i].cpu().numpy(), oracle_solution(w))
         assert max(err) <= 1e-11, (i, err)
     B.pint_plan_destroy(h)

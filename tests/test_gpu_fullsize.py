@@ -41,9 +41,10 @@ def _modal_ref(w, seed):
     return _MODAL[key]
 
 
-# every kernel variant the autotuner may pick for the benchmark workload
-# (forward kernel 1..3, half the rows per x-pass workgroup, the other y-pass tile)
-@pytest.mark.parametrize("variants", [[1, 0, 0, 0], [2, 0, 0, 0], [3, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]])
+# every kernel variant the autotuner may pick for the 2D heat workload
+# (forward kernel 1..4, half the rows per x-pass workgroup, the other y-pass tile)
+@pytest.mark.parametrize("variants", [[1, 0, 0, 0], [2, 0, 0, 0], [3, 0, 0, 0], [4, 0, 0, 0], [0, 1, 0, 0],
+                                      [0, 0, 1, 0]])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_heat2d_full_every_variant(precision, variants):
     w = wl.heat2d()
@@ -54,10 +55,11 @@ def test_heat2d_full_every_variant(precision, variants):
     assert max(err) <= (1e-11 if precision == "fp64" else 1e-10)
 
 
+@pytest.mark.parametrize("variants", [None, [4, 0, 0, 0], [0, 0, 1, 0]])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_heat3d_full(precision):
+def test_heat3d_full(precision, variants):
     w = wl.heat3d()
-    U, info = gpu_solve(w, precision=precision, tol=1e-13, max_sweeps=12)
+    U, info = gpu_solve(w, precision=precision, tol=1e-13, max_sweeps=12, variants=variants)
     dofs = np.random.default_rng(1).choice(w.M, 4096, replace=False)
     ref = oracle_modal(w, dofs)
     err = errors(U[:, dofs], ref)

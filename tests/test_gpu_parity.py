@@ -77,6 +77,18 @@ SMALL = [
     (2, (511, 3), 8, 2, 1.0, 1e-2),
     (2, (1023, 3), 8, 2, 1.0, 1e-2),
     (3, (127, 3, 3), 8, 2, 1.0, 1e-2),
+    # time axes that are not powers of two (Bluestein time DFTs), N = 2 and 4 included
+    (1, (63,), 100, 2, 1.0, 1e-3),
+    (1, (100,), 6, 5, 1.0, 0.1),
+    (1, (31,), 4, 3, 1.0, 1e-2),
+    (1, (15,), 2, 1, 1.0, 0.1),
+    (1, (7,), 2046, 2, 1.0, 1e-2),
+    (1, (40,), 1000, 3, 0.5, 1e-3),
+    (2, (15, 7), 24, 4, 1.0, 1e-4),
+    (2, (31, 31), 60, 3, 0.5, 1e-3),
+    (2, (20, 13), 98, 6, 1.0, 1e-3),
+    (3, (7, 5, 3), 12, 3, 1.0, 1e-3),
+    (3, (6, 9, 5), 20, 2, 0.7, 1e-3),
 ]
 
 
