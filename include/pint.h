@@ -206,6 +206,23 @@ pint_status pint_nonlinear_solve(pint_plan *plan, double c3, double c1, const do
                                  const double *fder, double *U, int newton_steps, double newton_tol,
                                  int *inner_sweeps, double *newton_upd, int *steps_done);
 
+/* pint_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sweeps (same kernels, same results) with the plan's workspace taken
+ * from a static device array of the library (64 MiB per device, held until
+ * the process ends) instead of the caller's buffer.  Arguments and results as
+ * pint_solve; the plan needs no pint_plan_set_workspace, is not autotuned,
+ * and is left unbound afterwards (its own workspace, if any, is kept).
+ * Allocates nothing: no hipMalloc, no hipFree.  All calls on one device share
+ * the one array, so calls that overlap in time on one device (other threads,
+ * other streams) race; the array keeps the last call's contents, and every
+ * value a call reads from it is written by that call first.
+ * Errors: PINT_E_ARG (NULL plan/v/U, batch plan, or a plan whose
+ * pint_plan_workspace_bytes exceeds 64 MiB), PINT_E_UNSUPPORTED (device index
+ * above 63), PINT_E_HIP (including a failed lookup of the array's address). */
+pint_status pint_solve_noalloc(pint_plan *plan, const double *v, const double *f, const double *fder,
+                               double *U, double *upd, double *upd_l2T, int *sweeps);
+
 /* Many independent problems in one plan (each instance with its own grid and
  * params; N, k, alpha, precision may all differ).  Every instance is validated
  * as in pint_plan_create and gets its own tables and workspace, which this

@@ -50,6 +50,8 @@ EXPORTS = {
     "pint_sequential_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pint_nonlinear_solve": (c_int, [c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                      c_double, POINTER(c_int), POINTER(c_double), POINTER(c_int)]),
+    "pint_solve_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   POINTER(c_double), POINTER(c_double), POINTER(c_int)]),
     "pint_batch_plan_create": (c_int, [POINTER(c_void_p), c_int, POINTER(pint_grid),
                                        POINTER(pint_params), c_void_p]),
     "pint_batch_solve": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -187,6 +189,18 @@ def pint_nonlinear_solve(plan, c3, c1, v, f, fder, U, newton_steps, newton_tol=0
                                     int(newton_steps), float(newton_tol), inner, upd, ctypes.byref(n))
     _check(st, "pint_nonlinear_solve", allow=(PINT_OK, PINT_NOT_CONVERGED))
     return st, list(inner)[:n.value], list(upd)[:n.value]
+
+
+def pint_solve_noalloc(plan, v, f, fder, U, max_sweeps):
+    """pint_solve with the workspace in the library's static device array (no
+    allocation).  Returns (status, upd, upd_l2T, sweeps); errors come back as the
+    status, not raised (PINT_E_ARG for a plan whose workspace exceeds the array)."""
+    upd = (c_double * max_sweeps)()
+    upd2 = (c_double * max_sweeps)()
+    nsw = c_int(0)
+    st = lib().pint_solve_noalloc(plan, _ptr(v), _ptr(f), _ptr(fder), _ptr(U), upd, upd2, ctypes.byref(nsw))
+    n = nsw.value
+    return st, list(upd)[:n], list(upd2)[:n], n
 
 
 def pint_batch_plan_create(grids, params, stream=None):

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpint.so")
 
-SOURCES = ["pint_forward.hip", "pint_space.hip", "pint_time.hip", "pint_gentime.hip", "pint_seq.hip", "pint_host.cpp"]
+SOURCES = ["pint_forward.hip", "pint_space.hip", "pint_time.hip", "pint_gentime.hip", "pint_seq.hip", "pint_noalloc.hip", "pint_host.cpp"]
 
 # Packed FP32 instructions are disabled for all device code (hipcc -O3 would
 # otherwise form v_pk_* FP32 ops from ordinary float code).
