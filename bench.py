@@ -12,10 +12,11 @@ per second) as `value`; the mixed FP32/FP64 and FP64 direct-form sweeps
 alongside; per-launch device times from HIP events recorded on the plan's
 stream inside the timed region (repeated passes listed in launch order and
 summed per pass name); the HBM roofline of the dominant kernel; time-to-1e-10
-against the FP64 CPU oracle for FP64 residual, FP64 direct and mixed; the same
-figures for the 2D heat (255^2 x 512, BDF4) and 2D subdiffusion (511^2 x 1024,
-CQ-BDF3) workloads; sweeps/s and time-to-1e-12 of the 1D heat workload
-(63 x 64, BDF2); and the CPU oracle timed on a bounded sample.
+against the FP64 CPU oracle for FP64 residual, FP64 direct and mixed; the
+sequential-in-time GPU solver's time to the same trajectory; the same figures
+for the 2D heat (255^2 x 512, BDF4) and 2D subdiffusion (511^2 x 1024, CQ-BDF3)
+workloads; sweeps/s and time-to-1e-12 of the 1D heat workload (63 x 64, BDF2);
+and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import glob
@@ -232,7 +233,33 @@ def bench_workload(w, args, refs):
         plan.close()
         del U
         torch.cuda.empty_cache()
+    entry["sequential"] = sequential_time(w)
     return entry
+
+
+def sequential_time(w, reps=2):
+    """Wall time of the sequential-in-time GPU solver (the scheme stepped level by
+    level, one shifted spatial solve per step), FP64: the in-GPU baseline the
+    parallel-in-time sweeps are compared with (time to the same trajectory)."""
+    import torch
+
+    from paper_2007_13125_amd import binding as B
+    from paper_2007_13125_amd.binding import Plan
+    data = (to_dev(w.v), to_dev(w.f), to_dev(w.fder))
+    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa)
+    U = torch.empty((w.N, w.M), dtype=torch.float64, device="cuda")
+    B.pint_sequential_solve(plan.h, *data, U)          # warm-up (code objects, caches)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        B.pint_sequential_solve(plan.h, *data, U)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    plan.close()
+    del U
+    torch.cuda.empty_cache()
+    return {"ms": best * 1e3, "steps": w.N, "precision": "fp64"}
 
 
 def bench_heat1d(args, refs):
@@ -515,6 +542,7 @@ def main():
         res["mixed"] = h["mixed"]
         res["fp64_direct"] = h["fp64_direct"]
         res["fp64"] = h["fp64"]
+        res["sequential"] = h["sequential"]
     if base is not None:
         res["cpu_baseline"] = base
     res["workloads"] = {n: r for n, r in results.items() if n != head}

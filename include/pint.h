@@ -168,6 +168,25 @@ int pint_profile_sweeps(pint_plan *plan, double *U, int nsweeps, double *ms, con
 pint_status pint_solve(pint_plan *plan, const double *v, const double *f, const double *fder,
                        double *U, double *upd, double *upd_l2T, int *sweeps);
 
+/* Windowed solve (the time-window remark that closes Sec. 4's Example 4): the
+ * interval (0, nwin T] is cut into nwin windows of the plan's length T and N
+ * steps, solved one after another, each by pint_solve's WR sweeps (parallel
+ * in time inside the window); window w starts from the last level of window
+ * w-1 (from v for w = 0) and the corrected scheme restarts there (its Table 1
+ * rows use f and d^l f/dt^l at the window's start).  For alpha < 1 a restart
+ * also drops the memory of the earlier windows: the windowed scheme is what is
+ * computed.  The space-time state of one window is what must fit the device.
+ *   v      DEVICE [M]
+ *   f      DEVICE [nwin N + 1][M], f(t_0) .. f(t_{nwin N}); NULL => f == 0
+ *   fder   DEVICE [nwin][k-2][M], d^l f/dt^l at each window's start; NULL => 0
+ *   U      DEVICE [nwin N][M] out
+ *   upd    HOST [nwin][max_sweeps] per-window max-norm updates (may be NULL)
+ *   sweeps HOST [nwin] (may be NULL)
+ * Returns PINT_OK, PINT_NOT_CONVERGED (some window hit max_sweeps; all windows
+ * are solved), or the first error. */
+pint_status pint_solve_windows(pint_plan *plan, int nwin, const double *v, const double *f,
+                               const double *fder, double *U, double *upd, int *sweeps);
+
 /* The sequential-in-time solver: the corrected BDF-k / CQ-BDF-k scheme of
  * the plan (Sec. 2.1 eq. BDF; Sec. 3.1 eq. BDF-frac; the stepping of the
  * cost paragraph of Sec. 3.2) stepped one level after another, each step one
@@ -226,10 +245,14 @@ pint_status pint_solve_noalloc(pint_plan *plan, const double *v, const double *f
 /* Many independent problems in one plan (each instance with its own grid and
  * params; N, k, alpha, precision may all differ).  Every instance is validated
  * as in pint_plan_create and gets its own tables and workspace, which this
- * call allocates (pint_batch_solve allocates nothing).  The instances are
- * solved one after another on the plan's stream through the single-plan
- * path.  count >= 1; grids/params are HOST arrays of count entries.
- * Errors: as pint_plan_create (the message names the instance). */
+ * call allocates (pint_batch_solve allocates nothing).  pint_batch_solve runs
+ * the 1D instances in persistent launches, one per class of (precision, time
+ * transform length), one workgroup per instance: each workgroup sweeps its
+ * instance (general-length time DFTs, a Thomas solve per frequency) until its
+ * own stop test, with no host round trip between sweeps; the instances of
+ * dimension 2 and 3 are solved one after another on the plan's stream through
+ * the single-plan path.  count >= 1; grids/params are HOST arrays of count
+ * entries.  Errors: as pint_plan_create (the message names the instance). */
 pint_status pint_batch_plan_create(pint_plan **plan, int count, const pint_grid *grids,
                                    const pint_params *params, void *hip_stream);
 

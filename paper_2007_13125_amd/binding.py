@@ -47,6 +47,8 @@ EXPORTS = {
                                     POINTER(ctypes.c_char_p), c_int]),
     "pint_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                            POINTER(c_double), POINTER(c_double), POINTER(c_int)]),
+    "pint_solve_windows": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                                   POINTER(c_int)]),
     "pint_sequential_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "pint_nonlinear_solve": (c_int, [c_void_p, c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                      c_double, POINTER(c_int), POINTER(c_double), POINTER(c_int)]),
@@ -173,6 +175,16 @@ def pint_solve(plan, v, f, fder, U, max_sweeps):
     _check(st, "pint_solve", allow=(PINT_OK, PINT_NOT_CONVERGED, PINT_E_DIVERGED))
     n = nsw.value
     return st, list(upd)[:n], list(upd2)[:n], n
+
+
+def pint_solve_windows(plan, nwin, v, f, fder, U, max_sweeps):
+    """Returns (status, per-window update norms, per-window sweep counts)."""
+    upd = (c_double * (nwin * max_sweeps))()
+    sw = (c_int * nwin)()
+    st = lib().pint_solve_windows(plan, int(nwin), _ptr(v), _ptr(f), _ptr(fder), _ptr(U), upd, sw)
+    _check(st, "pint_solve_windows", allow=(PINT_OK, PINT_NOT_CONVERGED))
+    sw = list(sw)
+    return st, [list(upd)[i * max_sweeps:i * max_sweeps + sw[i]] for i in range(nwin)], sw
 
 
 def pint_sequential_solve(plan, v, f, fder, U):

@@ -20,8 +20,9 @@ constexpr int kGenNT = 256;
 // Rb [N][M] (FP64).  A workgroup owns W consecutive dofs: their N time levels
 // and the weights w_0..w_{N-1} are staged in LDS, so the history sums read LDS
 // only; stencil neighbours come from global memory (L2).
-__global__ __launch_bounds__(kGenNT) void k_gn_resid(GenArgs a, int W) {
-    extern __shared__ double gl[];
+// Tiles t0, t0 + tstride, ... of the problem (every workgroup of a grid, or one
+// workgroup walking all tiles of its problem); gl: N (W + 1) doubles of LDS.
+__device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, int tstride, double* gl) {
     const int N = a.N;
     const size_t M = a.M;
     double* om = gl;            // [N]
@@ -30,7 +31,7 @@ __global__ __launch_bounds__(kGenNT) void k_gn_resid(GenArgs a, int W) {
     const int ntiles = (a.M + W - 1) / W;
     const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
     for (int j = tid; j < N; j += kGenNT) om[j] = j <= a.jmax ? a.w[j] : 0.0;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int tile = t0; tile < ntiles; tile += tstride) {
         const int d0 = tile * W;
         __syncthreads();   // the previous tile's sums are done with tl
         for (int idx = tid; idx < N * W; idx += kGenNT) {
@@ -72,6 +73,18 @@ __global__ __launch_bounds__(kGenNT) void k_gn_resid(GenArgs a, int W) {
     }
 }
 
+__global__ __launch_bounds__(kGenNT) void k_gn_resid(GenArgs a, int W) {
+    extern __shared__ double gl[];
+    gn_resid_body(a, W, blockIdx.x, gridDim.x, gl);
+}
+
+// Dofs per tile of the residual: the N x W tile and the N weights within 64 KB of LDS.
+__host__ __device__ inline int gn_resid_width(int N) {
+    int W = 16;
+    while (W > 1 && (size_t)N * (W + 1) * sizeof(double) > 65536) W /= 2;
+    return W;
+}
+
 // ---------------------------------------------------------------------------
 // Length-N DFT by Bluestein: with c_t = e^{-pi i t^2/N},
 //   X_p = sum_q x_q e^{-2 pi i p q/N} = c_p sum_q (x_q c_q) conj(c_{p-q}),
@@ -86,12 +99,14 @@ __global__ __launch_bounds__(kGenNT) void k_gn_resid(GenArgs a, int W) {
 //                   delta_q = y_q kappa^{-q/N}/N updates U (residual: U += delta;
 //                   direct: U = delta), and each workgroup leaves its
 //                   (max |U_m - U_{m-1}|, sum at q = N-1 of the update squared).
+// Tiles g0, g0 + gstride, ... of B slots; sm: P B values of LDS, red: 2 x 4
+// doubles of LDS.  INV: on return every lane holds the workgroup's (max |U_m -
+// U_{m-1}|, sum over q = N-1 of the update squared) in mx_out, s2_out.
 template <typename R, int LOGP, int B, bool INV>
-__global__ __launch_bounds__(kGenNT) void k_gn_dft(GenArgs a) {
+__device__ __forceinline__ void gn_dft_body(const GenArgs& a, int g0, int gstride, cx<R>* sm, double (*red)[kGenNT / 64],
+                                            double& mx_out, double& s2_out) {
     using T = cx<R>;
     constexpr int P = 1 << LOGP;
-    __shared__ T sm[P * B];
-    __shared__ double red[2][kGenNT / 64];
     const int tid = threadIdx.x;
     const int N = a.N;
     const size_t M = a.M;
@@ -103,7 +118,7 @@ __global__ __launch_bounds__(kGenNT) void k_gn_dft(GenArgs a) {
     const int ntiles = (a.Mp + B - 1) / B;
     double mx = 0.0, s2 = 0.0;
     bool bad = false;
-    for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
+    for (int g = g0; g < ntiles; g += gstride) {
         const int s0 = g * B;
         for (int idx = tid; idx < P * B; idx += kGenNT) {
             const int t = idx / B, slot = s0 + idx % B;
@@ -165,15 +180,26 @@ __global__ __launch_bounds__(kGenNT) void k_gn_dft(GenArgs a) {
             red[1][tid >> 6] = s2;
         }
         __syncthreads();
-        if (tid == 0) {
-            double m0 = red[0][0], t0 = red[1][0];
-            for (int i = 1; i < kGenNT / 64; ++i) {
-                m0 = nanmax(m0, red[0][i]);
-                t0 += red[1][i];
-            }
-            a.partial[2 * blockIdx.x] = m0;
-            a.partial[2 * blockIdx.x + 1] = t0;
+        double m0 = red[0][0], t0 = red[1][0];
+        for (int i = 1; i < kGenNT / 64; ++i) {
+            m0 = nanmax(m0, red[0][i]);
+            t0 += red[1][i];
         }
+        mx_out = m0;
+        s2_out = t0;
+        __syncthreads();   // red is free again
+    }
+}
+
+template <typename R, int LOGP, int B, bool INV>
+__global__ __launch_bounds__(kGenNT) void k_gn_dft(GenArgs a) {
+    __shared__ cx<R> sm[(1 << LOGP) * B];
+    __shared__ double red[2][kGenNT / 64];
+    double mx = 0.0, s2 = 0.0;
+    gn_dft_body<R, LOGP, B, INV>(a, blockIdx.x, gridDim.x, sm, red, mx, s2);
+    if (INV && threadIdx.x == 0) {
+        a.partial[2 * blockIdx.x] = mx;
+        a.partial[2 * blockIdx.x + 1] = s2;
     }
 }
 
@@ -212,6 +238,119 @@ hipError_t gn_dft_dispatch(const GenArgs& a, int* nb, hipStream_t st) {
         case 12: return gn_dft_one<R, 12, INV>(a, nb, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batch of 1D problems: workgroup i runs the whole solve of problem
+// i, sweep after sweep (residual, forward time DFT, one Thomas solve per
+// retained frequency, inverse time DFT + update + norms), and stops on its own
+// update norm with the rules of the single-problem solve (tolerance, non-finite
+// update, growth in two consecutive sweeps beyond the first).  Problems of one
+// launch share the spectrum precision R and the time Bluestein length 2^LOGP.
+// The Thomas solve of (sigma_p + A_h) Q_p = H_p (diagonal sigma_p + 2/h^2,
+// off-diagonals -1/h^2) runs one frequency per lane, without pivoting (stable
+// on these diagonally dominant shifted systems), on the spectrum row in place
+// with the modified super-diagonal in the scratch.
+template <typename R>
+__device__ __forceinline__ void thomas_rows(const Batch1D& d) {
+    using T = cx<R>;
+    const int m = d.ga.mx, nP = d.ga.N / 2 + 1;
+    T* S = reinterpret_cast<T*>(d.ga.S);
+    T* C = reinterpret_cast<T*>(d.thomas);
+    const R off = (R)(-d.ih2);
+    for (int p = threadIdx.x; p < nP; p += kGenNT) {
+        const double2 sg = d.sigma[p];
+        const T b = mk<T>((R)(sg.x + 2.0 * d.ih2), (R)sg.y);
+        T* X = S + (size_t)p * d.ga.ldS;
+        T* Cp = C + (size_t)p * m;
+        T den = b;
+        T cprev = cdiv(mk<T>(off, (R)0), den);
+        Cp[0] = cprev;
+        T xprev = cdiv(X[0], den);
+        X[0] = xprev;
+        for (int i = 1; i < m; ++i) {
+            den = mk<T>(b.x - off * cprev.x, b.y - off * cprev.y);
+            cprev = cdiv(mk<T>(off, (R)0), den);
+            Cp[i] = cprev;
+            const T xi = X[i];
+            xprev = cdiv(mk<T>(xi.x - off * xprev.x, xi.y - off * xprev.y), den);
+            X[i] = xprev;
+        }
+        for (int i = m - 2; i >= 0; --i) {
+            const T ci = Cp[i];
+            const T xi = X[i];
+            xprev = mk<T>(xi.x - (ci.x * xprev.x - ci.y * xprev.y), xi.y - (ci.x * xprev.y + ci.y * xprev.x));
+            X[i] = xprev;
+        }
+    }
+}
+
+template <typename R, int LOGP>
+__global__ __launch_bounds__(kGenNT) void k_batch1d(const Batch1D* __restrict__ descs, int count) {
+    constexpr int B = gn_slots<R, LOGP>();
+    __shared__ __align__(16) double lds[8192];        // 64 KB: residual tile, then DFT tile
+    __shared__ double red[2][kGenNT / 64];
+    const int i = blockIdx.x;
+    if (i >= count) return;
+    const Batch1D& d = descs[i];
+    const int W = gn_resid_width(d.ga.N);
+    double first = 0.0, prev1 = 0.0, prev2 = 0.0, mx = 0.0, s2 = 0.0;
+    int status = 1, m = 0;
+    while (m < d.max_sweeps) {
+        gn_resid_body(d.ga, W, 0, 1, lds);
+        __syncthreads();
+        gn_dft_body<R, LOGP, B, false>(d.ga, 0, 1, reinterpret_cast<cx<R>*>(lds), red, mx, s2);
+        __syncthreads();
+        thomas_rows<R>(d);
+        __syncthreads();
+        gn_dft_body<R, LOGP, B, true>(d.ga, 0, 1, reinterpret_cast<cx<R>*>(lds), red, mx, s2);
+        const double l2 = sqrt(d.hd * s2);
+        if (threadIdx.x == 0) {
+            d.upd[m] = mx;
+            d.upd_l2[m] = l2;
+        }
+        ++m;
+        const double crit = d.norm == 0 ? mx : l2;
+        if (!(mx <= 1.0e300) || !(l2 <= 1.0e300)) {
+            status = -5;
+            break;
+        }
+        if (m == 1) first = crit;
+        if (crit <= d.tol) {
+            status = 0;
+            break;
+        }
+        if (m >= 3 && crit > prev1 && prev1 > prev2 && crit > first) {
+            status = -5;
+            break;
+        }
+        prev2 = prev1;
+        prev1 = crit;
+    }
+    if (threadIdx.x == 0) {
+        d.result[0] = m;
+        d.result[1] = status;
+    }
+}
+
+template <typename R>
+hipError_t batch1d_dispatch(const Batch1D* descs, int count, int logP, hipStream_t st) {
+    const dim3 g((unsigned)count), b(kGenNT);
+    switch (logP) {
+        case 2: PINT_LAUNCH((k_batch1d<R, 2>), g, b, 0, st, descs, count); break;
+        case 3: PINT_LAUNCH((k_batch1d<R, 3>), g, b, 0, st, descs, count); break;
+        case 4: PINT_LAUNCH((k_batch1d<R, 4>), g, b, 0, st, descs, count); break;
+        case 5: PINT_LAUNCH((k_batch1d<R, 5>), g, b, 0, st, descs, count); break;
+        case 6: PINT_LAUNCH((k_batch1d<R, 6>), g, b, 0, st, descs, count); break;
+        case 7: PINT_LAUNCH((k_batch1d<R, 7>), g, b, 0, st, descs, count); break;
+        case 8: PINT_LAUNCH((k_batch1d<R, 8>), g, b, 0, st, descs, count); break;
+        case 9: PINT_LAUNCH((k_batch1d<R, 9>), g, b, 0, st, descs, count); break;
+        case 10: PINT_LAUNCH((k_batch1d<R, 10>), g, b, 0, st, descs, count); break;
+        case 11: PINT_LAUNCH((k_batch1d<R, 11>), g, b, 0, st, descs, count); break;
+        case 12: PINT_LAUNCH((k_batch1d<R, 12>), g, b, 0, st, descs, count); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // g'(Ubar) with Ubar[x] the mean of U over the N time levels (fixed order).
@@ -266,6 +405,11 @@ __global__ __launch_bounds__(kGenNT) void k_nl_axpy(double* __restrict__ U, cons
 
 }  // namespace
 
+hipError_t launch_batch1d(const Batch1D* descs, int count, bool mixed, int logP, hipStream_t st) {
+    if (count < 1) return hipSuccess;
+    return mixed ? batch1d_dispatch<float>(descs, count, logP, st) : batch1d_dispatch<double>(descs, count, logP, st);
+}
+
 hipError_t launch_nl_mean_dg(const double* U, double* dg, int N, int M, double c3, double c1, hipStream_t st) {
     PINT_LAUNCH(k_nl_mean_dg, dim3((M + kGenNT - 1) / kGenNT), dim3(kGenNT), 0, st, U, dg, N, M, c3, c1);
     return hipGetLastError();
@@ -283,8 +427,7 @@ hipError_t launch_nl_axpy(double* U, const double* W, double* partial, int N, in
 
 hipError_t launch_gn_resid(const GenArgs& a, hipStream_t st) {
     // dofs per workgroup: the N x W tile and the N weights within 64 KB of LDS
-    int W = 16;
-    while (W > 1 && (size_t)a.N * (W + 1) * sizeof(double) > 65536) W /= 2;
+    const int W = gn_resid_width(a.N);
     const size_t lds = (size_t)a.N * (W + 1) * sizeof(double);
     const void* fn = reinterpret_cast<const void*>(&k_gn_resid);
     const long long ntiles = ((long long)a.M + W - 1) / W;

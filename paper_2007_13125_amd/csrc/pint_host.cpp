@@ -167,6 +167,14 @@ struct pint_plan {
     double* h_norms = nullptr;  // pinned host, 2 doubles
     // batch: sub-plans sharing the stream
     std::vector<pint_plan*> inst;
+    // batch of 1D instances in persistent launches: descriptors, results, norms (device)
+    pint::Batch1D* d_batch = nullptr;
+    int* d_bres = nullptr;
+    double* d_bupd = nullptr;
+    int bsmax = 0;
+    // batch 1D instance: Thomas scratch [N/2+1][M] complex in the workspace
+    size_t off_th = 0;
+    void* thomas = nullptr;
     // kernel variants in use: forward, x pass, y/z pass, 1D tridiagonal split (0 = built-in)
     int var[4] = {0, 0, 0, 0};
     int tune_reps = 0;                // > 0: the solves time the variants first (autotune)
@@ -513,6 +521,7 @@ void attach_workspace(pint_plan* P, void* ws) {
     P->norm_tmp = reinterpret_cast<double*>(b + P->off_norm);
     P->Sg = P->off_sg ? static_cast<void*>(b + P->off_sg) : nullptr;
     P->Rb = P->off_r ? reinterpret_cast<double*>(b + P->off_r) : nullptr;
+    P->thomas = P->off_th ? static_cast<void*>(b + P->off_th) : nullptr;
     if (P->off_nl) {
         const size_t nm = align256((size_t)P->N * P->M * sizeof(double));
         P->nlW = reinterpret_cast<double*>(b + P->off_nl);
@@ -1114,6 +1123,28 @@ pint_status pint_solve(pint_plan* P, const double* v, const double* f, const dou
     return pint::solve_loop(P, U, upd, upd_l2T, sweeps);
 }
 
+pint_status pint_solve_windows(pint_plan* P, int nwin, const double* v, const double* f, const double* fder,
+                               double* U, double* upd, int* sweeps) {
+    if (!P || !U || !v || nwin < 1) return fail(PINT_E_ARG, "bad arguments to pint_solve_windows");
+    if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans are not supported here");
+    const size_t N = P->N, M = P->M, kd = P->p.k > 2 ? P->p.k - 2 : 0;
+    pint_status result = PINT_OK;
+    for (int w = 0; w < nwin; ++w) {
+        // window w starts from the last level of window w-1 (U_w[-1] stays untouched
+        // while window w sweeps)
+        const double* vw = w == 0 ? v : U + ((size_t)w * N - 1) * M;
+        const double* fw = f ? f + (size_t)w * N * M : nullptr;
+        const double* dw = (fder && kd > 0) ? fder + (size_t)w * kd * M : nullptr;
+        int done = 0;
+        const pint_status rc = pint_solve(P, vw, fw, dw, U + (size_t)w * N * M,
+                                          upd ? upd + (size_t)w * P->p.max_sweeps : nullptr, nullptr, &done);
+        if (sweeps) sweeps[w] = done;
+        if (rc < 0) return rc;
+        if (rc == PINT_NOT_CONVERGED) result = rc;
+    }
+    return result;
+}
+
 pint_status pint_sequential_solve(pint_plan* P, const double* v, const double* f, const double* fder, double* U) {
     if (!P || !U || !v) return fail(PINT_E_ARG, "plan, v and U must not be NULL");
     if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans are not supported here");
@@ -1247,9 +1278,29 @@ pint_status pint_batch_plan_create(pint_plan** plan, int count, const pint_grid*
         if (!Q) return bail(fail(PINT_E_NOMEM, "host allocation failed"));
         P->inst.push_back(Q);
         pint_status rc = build_plan(Q, &grids[i], &params[i], P->st);
+        if (rc == PINT_OK && Q->dim == 1) {
+            // the persistent 1D launch solves each frequency by Thomas in place,
+            // with the modified super-diagonal kept here
+            Q->off_th = Q->ws_bytes;
+            Q->ws_bytes += align256((size_t)Q->nP * Q->M * (Q->mixed ? 8 : 16));
+        }
         if (rc == PINT_OK) rc = own_workspace(Q);
         if (rc != PINT_OK) return bail(fail(rc, "instance " + std::to_string(i) + ": " + g_err));
+        P->bsmax = std::max(P->bsmax, params[i].max_sweeps);
     }
+    void* q = nullptr;
+    if ((e = hipMalloc(&q, (size_t)count * sizeof(pint::Batch1D))) != hipSuccess)
+        return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
+    P->owned.push_back(q);
+    P->d_batch = static_cast<pint::Batch1D*>(q);
+    if ((e = hipMalloc(&q, (size_t)count * 2 * sizeof(int))) != hipSuccess)
+        return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
+    P->owned.push_back(q);
+    P->d_bres = static_cast<int*>(q);
+    if ((e = hipMalloc(&q, (size_t)count * 2 * P->bsmax * sizeof(double))) != hipSuccess)
+        return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
+    P->owned.push_back(q);
+    P->d_bupd = static_cast<double*>(q);
     *plan = P;
     return PINT_OK;
 }
@@ -1264,8 +1315,65 @@ pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double*
             return fail(PINT_E_ARG, "instance " + std::to_string(i) + ": max_sweeps exceeds the upd stride");
     }
     pint_status result = PINT_OK;
+    // 1D instances: bound and started here, then solved by persistent launches,
+    // one per (precision, time Bluestein length) class, one workgroup each
+    std::vector<int> ones;
+    for (int i = 0; i < count; ++i)
+        if (P->inst[i]->dim == 1) ones.push_back(i);
+    if (!ones.empty()) {
+        std::vector<std::pair<std::pair<int, int>, int>> order;   // ((mixed, logP), instance)
+        for (int i : ones) {
+            pint_plan* Q = P->inst[i];
+            pint_status rc = pint_bind(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr);
+            if (rc == PINT_OK) rc = pint_init_iterate(Q, U[i]);
+            if (rc != PINT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+            order.push_back({{Q->mixed ? 1 : 0, Q->logPt}, i});
+        }
+        std::sort(order.begin(), order.end());
+        std::vector<pint::Batch1D> packed;
+        for (auto& o : order) {
+            const int i = o.second;
+            pint_plan* Q = P->inst[i];
+            pint::Batch1D b{};
+            b.ga = gen_args(Q, U[i]);
+            b.sigma = Q->d_sigma;
+            b.thomas = Q->thomas;
+            b.ih2 = Q->ih2[0];
+            b.tol = Q->p.tol;
+            b.hd = Q->hd;
+            b.norm = Q->p.norm == PINT_NORM_INF ? 0 : 1;
+            b.max_sweeps = Q->p.max_sweeps;
+            b.upd = P->d_bupd + (size_t)i * 2 * P->bsmax;
+            b.upd_l2 = b.upd + P->bsmax;
+            b.result = P->d_bres + 2 * i;
+            packed.push_back(b);
+        }
+        HIP_TRY(hipMemcpyAsync(P->d_batch, packed.data(), packed.size() * sizeof(pint::Batch1D),
+                               hipMemcpyHostToDevice, P->st));
+        for (size_t a = 0; a < order.size();) {
+            size_t e2 = a;
+            while (e2 < order.size() && order[e2].first == order[a].first) ++e2;
+            HIP_TRY(pint::launch_batch1d(P->d_batch + a, (int)(e2 - a), order[a].first.first == 1,
+                                         order[a].first.second, P->st));
+            a = e2;
+        }
+        std::vector<int> res((size_t)count * 2, 0);
+        std::vector<double> bupd((size_t)count * 2 * P->bsmax, 0.0);
+        HIP_TRY(hipMemcpyAsync(res.data(), P->d_bres, res.size() * sizeof(int), hipMemcpyDeviceToHost, P->st));
+        HIP_TRY(hipMemcpyAsync(bupd.data(), P->d_bupd, bupd.size() * sizeof(double), hipMemcpyDeviceToHost, P->st));
+        HIP_TRY(hipStreamSynchronize(P->st));   // also keeps packed alive until its copy is done
+        for (int i : ones) {
+            const int done = res[2 * i], st = res[2 * i + 1];
+            if (sweeps) sweeps[i] = done;
+            if (upd)
+                for (int m = 0; m < done; ++m) upd[(size_t)i * stride + m] = bupd[(size_t)i * 2 * P->bsmax + m];
+            if (st == -5) result = fail(PINT_E_DIVERGED, "instance " + std::to_string(i) + ": diverged");
+            else if (st == 1 && result == PINT_OK) result = PINT_NOT_CONVERGED;
+        }
+    }
     for (int i = 0; i < count; ++i) {
         pint_plan* Q = P->inst[i];
+        if (Q->dim == 1) continue;
         Q->tune_reps = P->tune_reps;
         int done = 0;
         const pint_status rc = pint_solve(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr, U[i],

@@ -92,6 +92,21 @@ struct GenArgs {
     const double* dvar;     // [M] or nullptr
 };
 
+// One 1D problem of a persistent batch launch (one workgroup runs its whole
+// solve: WR sweeps with the general-length time DFTs and a Thomas solve per
+// frequency, and its own stop test).
+struct Batch1D {
+    GenArgs ga;             // the problem's sweep arguments (U, data, tables, workspace)
+    const double2* sigma;   // [N/2+1] tau^{-alpha} d_p
+    void* thomas;           // [N/2+1][m] complex scratch in the spectrum precision
+    double ih2, tol, hd;
+    int norm;               // 0 max over space-time, 1 terminal L2_h
+    int max_sweeps;
+    double* upd;            // [max_sweeps] max-norm update per sweep (device, out)
+    double* upd_l2;         // [max_sweeps] terminal L2_h update per sweep (device, out)
+    int* result;            // [2] sweeps done, status (0 converged, 1 max_sweeps, -5 diverged)
+};
+
 // Spatial shifted solves on the spectrum.
 struct SpaceArgs {
     void* S;                // [nP][ldS] complex, in place
@@ -143,6 +158,9 @@ hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st);
 hipError_t launch_gn_resid(const GenArgs& a, hipStream_t st);
 hipError_t launch_gn_forward(const GenArgs& a, bool mixed, hipStream_t st);
 hipError_t launch_gn_inverse(const GenArgs& a, bool mixed, int* nblocks_out, hipStream_t st);
+// Persistent batch launch over count 1D problems that share the spectrum
+// precision and the time Bluestein length 2^logP (one workgroup per problem).
+hipError_t launch_batch1d(const Batch1D* descs, int count, bool mixed, int logP, hipStream_t st);
 // Sequential-in-time solver: right-hand side of step n into one complex plane
 // (slot order), and U^n back from the solved plane.
 hipError_t launch_seq_rhs(const GenArgs& a, int n, void* plane, hipStream_t st);
