@@ -90,13 +90,13 @@ def three_stage_bytes(w, mixed):
     return 8 * N * M * (3 if w.f is not None else 2) + 2 * spectrum_bytes(N, M, mixed)
 
 
-def measured_traffic(w, precision, slot):
+def measured_traffic(w, precision, slot, variants):
     """HBM bytes per launch of a pass from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE record of this workload, or None when that record is missing or the
-    kernel sources changed since it was taken."""
+    WRITE_SIZE record of this workload, or None when that record is missing, was
+    taken with other kernel variants, or the kernel sources changed since."""
     try:
         rec = json.load(open(profile_stem(w) + "_traffic.json"))
-        if rec["sources_sha256"] != sources_sha():
+        if rec["sources_sha256"] != sources_sha() or list(rec.get("variants", [])) != list(variants):
             return None
         k = rec["kernels"][precision][slot]
         return k["read"] + k["write"]
@@ -144,13 +144,13 @@ def slot_summary(slots):
     return {"launches": [[n, t] for n, t in slots], "per_pass": by}
 
 
-def roofline_of(w, precision, slots):
+def roofline_of(w, precision, slots, variants):
     mixed = precision == "mixed"
     dom = max(slots, key=lambda s: s[1])
     b = slot_bytes(dom[0], w, mixed)
     gbs = b / (dom[1] * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": dom[0], "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(w, precision, dom[0]), "alg_bytes": b,
+            "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(w, precision, dom[0], variants), "alg_bytes": b,
             "ms": dom[1]}
 
 
@@ -226,14 +226,15 @@ def bench_workload(w, args, refs):
         e = {"ms_per_step": ms, "value": w.N * w.M / (ms * 1e-3), "kernels_ms": slot_summary(slots),
              "hbm_frac_as_built": asb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
              "hbm_frac_3stage": three_stage_bytes(w, mixed) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-             "roofline": roofline_of(w, precision, slots), "variants": var}
+             "roofline": roofline_of(w, precision, slots, var), "variants": var}
         if refs is not None and w.name in refs:
             e["time_to_1e-10"] = time_to_tol(plan, U, sample, refs[w.name], 1e-10)
         entry[key] = e
         plan.close()
         del U
         torch.cuda.empty_cache()
-    entry["sequential"] = sequential_time(w)
+    if not args.only:
+        entry["sequential"] = sequential_time(w)
     return entry
 
 
@@ -277,6 +278,65 @@ def bench_heat1d(args, refs):
     plan.close()
     torch.cuda.synchronize()
     return e
+
+
+def bench_batch(count=256):
+    """The many-instance recipe (count instances, seed (4, i)), mixed precision, stop
+    test 1e-10 on the update: all of its 1D instances in one pint_batch_solve (the
+    persistent launches), and the four smallest 2D instances one plan each (the
+    single-plan path that batches take for them, autotuned).  The 2D instances of the
+    full recipe (up to 1023^2 x 1024 unknowns each, 1.3e10 in all) are not run here:
+    their host-side data generation alone would take many minutes."""
+    import torch
+
+    from paper_2007_13125_amd import binding as B
+    from paper_2007_13125_amd import workloads as wl
+    params = [wl.batch_params(i) for i in range(count)]
+    one = [i for i in range(count) if params[i][0] == 1]
+    two = sorted([i for i in range(count) if params[i][0] == 2],
+                 key=lambda i: params[i][2] * params[i][1][0] * params[i][1][1])[:4]
+    ws = [wl.batch_instance(i) for i in one]
+    S = 40
+    grids = [B.make_grid(w.m) for w in ws]
+    prm = [B.make_params(w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-10, max_sweeps=S, precision="mixed") for w in ws]
+    h = B.pint_batch_plan_create(grids, prm)
+    data = [(to_dev(w.v), to_dev(w.f), to_dev(w.fder)) for w in ws]
+    Us = [torch.empty((w.N, w.M), dtype=torch.float64, device="cuda") for w in ws]
+    args = ([d[0] for d in data], [d[1] for d in data], [d[2] for d in data], Us, S)
+    B.pint_batch_solve(h, *args)                 # warm-up (code objects)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, upd, sw = B.pint_batch_solve(h, *args)
+    torch.cuda.synchronize()
+    t1d = time.perf_counter() - t0
+    B.pint_plan_destroy(h)
+    upd1 = sum(w.N * w.M * s for w, s in zip(ws, sw))
+    out = {"recipe": f"{count} instances, seed (4, i), mixed, tol 1e-10", "n_1d": len(one),
+           "unknowns_1d": sum(w.N * w.M for w in ws), "status_1d": st, "sweeps_1d_max": max(sw),
+           "sweeps_1d_mean": float(sum(sw)) / len(sw), "ms_1d": t1d * 1e3,
+           "unknown_updates_per_s_1d": upd1 / t1d}
+    del Us, data
+    torch.cuda.empty_cache()
+    rows = []
+    for i in two:
+        w = wl.batch_instance(i)
+        plan = B.Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-10, max_sweeps=S, precision="mixed")
+        plan.set_autotune(2)
+        d = (to_dev(w.v), to_dev(w.f), to_dev(w.fder))
+        plan.solve(*d)                            # warm-up + tuning
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, info = plan.solve(*d)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rows.append({"instance": i, "grid": list(w.m), "N": w.N, "k": w.k, "alpha": w.alpha, "kappa": w.kappa,
+                     "sweeps": info["sweeps"], "ms": dt * 1e3,
+                     "unknown_updates_per_s": w.N * w.M * info["sweeps"] / dt})
+        plan.close()
+        del U, d
+        torch.cuda.empty_cache()
+    out["smallest_2d"] = rows
+    return out
 
 
 # ---------------------------------------------------------------------------------------
@@ -404,7 +464,8 @@ def summarize(outdir, name):
     one workload from rocprofv3 CSV output of the three runs listed in the summary:
     <outdir>/trace (--kernel-trace --stats), <outdir>/FETCH_SIZE, <outdir>/WRITE_SIZE
     (--pmc), each of `bench.py --only <name> --steps 5 --warmup 1 --no-cpu-baseline
-    --copy-calibration`."""
+    --copy-calibration --no-tune` (the built-in kernel variants, so that each pass
+    launches one kernel)."""
     import csv
     from collections import defaultdict
 
@@ -434,7 +495,7 @@ def summarize(outdir, name):
     wcal = max(max(counters["WRITE_SIZE"][k]) for k in copies)
     rf, wf = COPY_BYTES / (fcal * 1024), COPY_BYTES / (wcal * 1024)
     sha = sources_sha()
-    rec = {"workload": DESCR[name], "sources": KERNEL_SOURCES, "sources_sha256": sha,
+    rec = {"workload": DESCR[name], "sources": KERNEL_SOURCES, "sources_sha256": sha, "variants": [0, 0, 0, 0],
            "calibration": {"copy_bytes": COPY_BYTES, "FETCH_SIZE_KiB": fcal, "WRITE_SIZE_KiB": wcal,
                            "read_factor": rf, "write_factor": wf},
            "kernels": {"fp64": {}, "mixed": {}}}
@@ -444,13 +505,14 @@ def summarize(outdir, name):
              "Commands (run from /tmp with TMPDIR=/tmp; each writes CSV under the -d folder), then "
              f"`python bench.py --summarize <out> --only {name}` writes this file and the traffic record:", "",
              "```"]
-    cmd = f"python3 /root/repo/bench.py --only {name} --steps 5 --warmup 1 --no-cpu-baseline --copy-calibration"
+    cmd = (f"python3 /root/repo/bench.py --only {name} --steps 5 --warmup 1 --no-cpu-baseline --copy-calibration "
+           f"--no-tune")
     lines += [f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o {name} -- {cmd}",
               f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/FETCH_SIZE -o {name} -- {cmd}",
               f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/WRITE_SIZE -o {name} -- {cmd}",
               "```", "",
               "bench.py runs the FP64 plan (kernels `<double,...>`), the mixed plan (`<float,...>`) and the FP64 "
-              "direct-form plan, each for the autotuner's trial launches, warmup and timed sweeps.", "",
+              "direct-form plan with the built-in kernel variants, each for its warmup and timed sweeps.", "",
               "## --kernel-trace --stats", "",
               "| kernel | calls | average us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
     for r in stats:
@@ -460,7 +522,7 @@ def summarize(outdir, name):
               f"Calibration: a plain {COPY_BYTES >> 20} MiB device copy read FETCH_SIZE = {fcal:.0f} KiB and "
               f"WRITE_SIZE = {wcal:.0f} KiB, so HBM read bytes = {rf:.3f} x FETCH_SIZE KiB x 1024 and write "
               f"bytes = {wf:.3f} x WRITE_SIZE KiB x 1024.", "",
-              "Kernels with few dispatches are the autotuner's trial launches of the variants not chosen.", "",
+              "", 
               "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | write MB |",
               "|---|---|---|---|---|---|"]
     calls = {}
@@ -542,10 +604,14 @@ def main():
         res["mixed"] = h["mixed"]
         res["fp64_direct"] = h["fp64_direct"]
         res["fp64"] = h["fp64"]
-        res["sequential"] = h["sequential"]
+        if "sequential" in h:
+            res["sequential"] = h["sequential"]
     if base is not None:
         res["cpu_baseline"] = base
     res["workloads"] = {n: r for n, r in results.items() if n != head}
+    if not args.only:
+        print("[bench] batch", file=sys.stderr, flush=True)
+        res["workloads"]["batch"] = bench_batch()
     res["variant_knobs"] = ["forward kernel", "x pass rows", "y/z pass columns", "1D solver"]
     print(json.dumps(res), flush=True)
     if args.copy_calibration:

@@ -27,6 +27,7 @@ __device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, i
     const size_t M = a.M;
     double* om = gl;            // [N]
     double* tl = gl + N;        // [N][W]
+    double* hs = tl + (size_t)N * W;   // [N][W] history sums (long histories only)
     const int tid = threadIdx.x;
     const int ntiles = (a.M + W - 1) / W;
     const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
@@ -39,6 +40,39 @@ __device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, i
             tl[idx] = d < a.M ? a.U[(size_t)q * M + d] : 0.0;
         }
         __syncthreads();
+        // Long histories (CQ): the time-stencil sums of QB consecutive rows of one
+        // dof are formed together, QB independent accumulators, the weights in a
+        // sliding register window; they go to the LDS row of the dof's sums hs.
+        constexpr int QB = 8;
+        const bool blocked = a.form == 0 && a.jmax >= 16;
+        if (blocked) {
+            const int nb = (N + QB - 1) / QB;
+            for (int it = tid; it < nb * W; it += kGenNT) {
+                const int q0 = (it / W) * QB, wl = it % W;
+                double acc[QB], win[QB];
+#pragma unroll
+                for (int r = 0; r < QB; ++r) {
+                    acc[r] = 0.0;
+                    win[r] = (q0 + r < N && q0 + r <= a.jmax) ? om[q0 + r] : 0.0;   // w_{q0+r-i} at i = 0
+                }
+                const int iend = q0 + QB < N ? q0 + QB : N;
+                for (int i = 0; i < iend; ++i) {
+                    const double ui = tl[i * W + wl];
+#pragma unroll
+                    for (int r = 0; r < QB; ++r)
+                        if (i <= q0 + r) acc[r] += win[r] * ui;
+                    // next i: w_{q0+r-i-1}: shift the window down, the new low entry
+#pragma unroll
+                    for (int r = QB - 1; r > 0; --r) win[r] = win[r - 1];
+                    const int jn = q0 - i - 1;
+                    win[0] = (jn >= 0 && jn <= a.jmax) ? om[jn] : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < QB; ++r)
+                    if (q0 + r < N) hs[(q0 + r) * W + wl] = acc[r];
+            }
+            __syncthreads();
+        }
         for (int idx = tid; idx < N * W; idx += kGenNT) {
             const int q = idx / W, wl = idx % W, d = d0 + wl;
             if (d >= a.M) continue;
@@ -59,8 +93,12 @@ __device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, i
                 if (a.my > 1) nb += a.ihy2 * ((y > 0 ? Uq[d - sy] : 0.0) + (y < a.my - 1 ? Uq[d + sy] : 0.0));
                 if (a.mz > 1) nb += a.ihz2 * ((z > 0 ? Uq[d - sz] : 0.0) + (z < a.mz - 1 ? Uq[d + sz] : 0.0));
                 double h = 0.0;
-                const int top = q < a.jmax ? q : a.jmax;
-                for (int j = 0; j <= top; ++j) h += om[j] * tl[(q - j) * W + wl];
+                if (blocked) {
+                    h = hs[q * W + wl];
+                } else {
+                    const int top = q < a.jmax ? q : a.jmax;
+                    for (int j = 0; j <= top; ++j) h += om[j] * tl[(q - j) * W + wl];
+                }
                 r += nb - diag * tl[q * W + wl] - a.ta * h;
             } else {
                 double c = 0.0;
@@ -78,10 +116,11 @@ __global__ __launch_bounds__(kGenNT) void k_gn_resid(GenArgs a, int W) {
     gn_resid_body(a, W, blockIdx.x, gridDim.x, gl);
 }
 
-// Dofs per tile of the residual: the N x W tile and the N weights within 64 KB of LDS.
+// Dofs per tile of the residual: the N weights and two N x W tiles (levels,
+// history sums) within 64 KB of LDS.
 __host__ __device__ inline int gn_resid_width(int N) {
     int W = 16;
-    while (W > 1 && (size_t)N * (W + 1) * sizeof(double) > 65536) W /= 2;
+    while (W > 1 && (size_t)N * (2 * W + 1) * sizeof(double) > 65536) W /= 2;
     return W;
 }
 
@@ -268,19 +307,47 @@ __device__ __forceinline__ void thomas_rows(const Batch1D& d) {
         Cp[0] = cprev;
         T xprev = cdiv(X[0], den);
         X[0] = xprev;
-        for (int i = 1; i < m; ++i) {
-            den = mk<T>(b.x - off * cprev.x, b.y - off * cprev.y);
-            cprev = cdiv(mk<T>(off, (R)0), den);
-            Cp[i] = cprev;
-            const T xi = X[i];
-            xprev = cdiv(mk<T>(xi.x - off * xprev.x, xi.y - off * xprev.y), den);
-            X[i] = xprev;
+        // chunks of CH equations: the chunk's loads are issued together, then the
+        // recurrence runs on registers (no memory latency per step)
+        constexpr int CH = 16;
+        for (int i0 = 1; i0 < m; i0 += CH) {
+            T xs[CH];
+#pragma unroll
+            for (int r = 0; r < CH; ++r) xs[r] = i0 + r < m ? X[i0 + r] : mk<T>((R)0, (R)0);
+#pragma unroll
+            for (int r = 0; r < CH; ++r) {
+                if (i0 + r < m) {
+                    den = mk<T>(b.x - off * cprev.x, b.y - off * cprev.y);
+                    cprev = cdiv(mk<T>(off, (R)0), den);
+                    Cp[i0 + r] = cprev;
+                    xprev = cdiv(mk<T>(xs[r].x - off * xprev.x, xs[r].y - off * xprev.y), den);
+                    xs[r] = xprev;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < CH; ++r)
+                if (i0 + r < m) X[i0 + r] = xs[r];
         }
-        for (int i = m - 2; i >= 0; --i) {
-            const T ci = Cp[i];
-            const T xi = X[i];
-            xprev = mk<T>(xi.x - (ci.x * xprev.x - ci.y * xprev.y), xi.y - (ci.x * xprev.y + ci.y * xprev.x));
-            X[i] = xprev;
+        // back substitution, chunks from the end (x_{m-1} = xprev already)
+        for (int i1 = m - 2; i1 >= 0; i1 -= CH) {
+            T xs[CH], cs[CH];
+#pragma unroll
+            for (int r = 0; r < CH; ++r) {
+                const int i = i1 - r;
+                xs[r] = i >= 0 ? X[i] : mk<T>((R)0, (R)0);
+                cs[r] = i >= 0 ? Cp[i] : mk<T>((R)0, (R)0);
+            }
+#pragma unroll
+            for (int r = 0; r < CH; ++r) {
+                if (i1 - r >= 0) {
+                    xprev = mk<T>(xs[r].x - (cs[r].x * xprev.x - cs[r].y * xprev.y),
+                                  xs[r].y - (cs[r].x * xprev.y + cs[r].y * xprev.x));
+                    xs[r] = xprev;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < CH; ++r)
+                if (i1 - r >= 0) X[i1 - r] = xs[r];
         }
     }
 }
@@ -428,7 +495,7 @@ hipError_t launch_nl_axpy(double* U, const double* W, double* partial, int N, in
 hipError_t launch_gn_resid(const GenArgs& a, hipStream_t st) {
     // dofs per workgroup: the N x W tile and the N weights within 64 KB of LDS
     const int W = gn_resid_width(a.N);
-    const size_t lds = (size_t)a.N * (W + 1) * sizeof(double);
+    const size_t lds = (size_t)a.N * (2 * W + 1) * sizeof(double);
     const void* fn = reinterpret_cast<const void*>(&k_gn_resid);
     const long long ntiles = ((long long)a.M + W - 1) / W;
     const long long grid = std::max<long long>(1, std::min<long long>(ntiles, persistent_blocks(fn, kGenNT)));

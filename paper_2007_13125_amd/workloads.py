@@ -159,8 +159,8 @@ def heat3d(seed=5, m=(127, 127, 127), N=256, k=6, T=1.0, kappa=1e-6, modes=8, to
     return Workload("heat3d", m, k, 1.0, T, N, kappa, v, f, fder, tol, modes={"v": cv, "f": cf})
 
 
-def batch_instance(i, seed=4, m_range=(63, 1023), N_choices=(32, 64, 128, 256, 512, 1024)):
-    """Instance i of the many-instance batch (parameters and data)."""
+def batch_params(i, seed=4, m_range=(63, 1023), N_choices=(32, 64, 128, 256, 512, 1024)):
+    """(dim, m, N, k, alpha, kappa, data seed) of instance i of the many-instance batch."""
     rng = np.random.default_rng([seed, i])
     dim = int(rng.integers(1, 3))
     m = tuple(int(rng.integers(m_range[0], m_range[1] + 1)) for _ in range(dim))
@@ -169,6 +169,12 @@ def batch_instance(i, seed=4, m_range=(63, 1023), N_choices=(32, 64, 128, 256, 5
     alpha = float(rng.choice([1.0, 0.3, 0.7]))
     kappa = float(10.0 ** rng.uniform(-6, -2))
     dseed = int(rng.integers(0, 2 ** 31))
+    return dim, m, N, k, alpha, kappa, dseed
+
+
+def batch_instance(i, seed=4, m_range=(63, 1023), N_choices=(32, 64, 128, 256, 512, 1024)):
+    """Instance i of the many-instance batch (parameters and data)."""
+    dim, m, N, k, alpha, kappa, dseed = batch_params(i, seed, m_range, N_choices)
     if dim == 1:
         w = heat1d(seed=dseed, m=m[0], N=N, k=k, kappa=kappa)
     else:
