@@ -282,8 +282,9 @@ def bench_heat1d(args, refs):
 
 def bench_batch(count=256):
     """The many-instance recipe (count instances, seed (4, i)), mixed precision, stop
-    test 1e-10 on the update: all of its 1D instances in one pint_batch_solve (the
-    persistent launches), and the four smallest 2D instances one plan each (the
+    test 1e-10 on the update: all of its 1D instances in one pint_batch_solve (batched
+    sweeps), beside the same instances solved one plan after another, and the four
+    smallest 2D instances one plan each (the
     single-plan path that batches take for them, autotuned).  The 2D instances of the
     full recipe (up to 1023^2 x 1024 unknowns each, 1.3e10 in all) are not run here:
     their host-side data generation alone would take many minutes."""
@@ -310,11 +311,23 @@ def bench_batch(count=256):
     torch.cuda.synchronize()
     t1d = time.perf_counter() - t0
     B.pint_plan_destroy(h)
+    # the same instances one plan after another (single-plan path, no tuning)
+    plans = [B.Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-10, max_sweeps=S, precision="mixed") for w in ws]
+    for p, d, U in zip(plans, data, Us):
+        p.solve(*d, U=U)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, d, U in zip(plans, data, Us):
+        p.solve(*d, U=U)
+    torch.cuda.synchronize()
+    tone = time.perf_counter() - t0
+    for p in plans:
+        p.close()
     upd1 = sum(w.N * w.M * s for w, s in zip(ws, sw))
     out = {"recipe": f"{count} instances, seed (4, i), mixed, tol 1e-10", "n_1d": len(one),
            "unknowns_1d": sum(w.N * w.M for w in ws), "status_1d": st, "sweeps_1d_max": max(sw),
            "sweeps_1d_mean": float(sum(sw)) / len(sw), "ms_1d": t1d * 1e3,
-           "unknown_updates_per_s_1d": upd1 / t1d}
+           "unknown_updates_per_s_1d": upd1 / t1d, "ms_1d_one_plan_each": tone * 1e3}
     del Us, data
     torch.cuda.empty_cache()
     rows = []

@@ -245,13 +245,14 @@ pint_status pint_solve_noalloc(pint_plan *plan, const double *v, const double *f
 /* Many independent problems in one plan (each instance with its own grid and
  * params; N, k, alpha, precision may all differ).  Every instance is validated
  * as in pint_plan_create and gets its own tables and workspace, which this
- * call allocates (pint_batch_solve allocates nothing).  pint_batch_solve runs
- * the 1D instances in persistent launches, one per class of (precision, time
- * transform length), one workgroup per instance: each workgroup sweeps its
- * instance (general-length time DFTs, a Thomas solve per frequency) until its
- * own stop test, with no host round trip between sweeps; the instances of
- * dimension 2 and 3 are solved one after another on the plan's stream through
- * the single-plan path.  count >= 1; grids/params are HOST arrays of count
+ * call allocates (pint_batch_solve allocates nothing).  pint_batch_solve
+ * sweeps the 1D instances together: each pass of a sweep (residual, time DFT
+ * of general length, a Thomas solve per retained frequency, inverse DFT and
+ * update, norms) is one launch over all active instances of a class of
+ * (precision, time transform length), and after every sweep one host stop
+ * test per instance (the rules of pint_solve) drops the finished ones; the
+ * instances of dimension 2 and 3 are solved one after another on the plan's
+ * stream through the single-plan path.  count >= 1; grids/params are HOST arrays of count
  * entries.  Errors: as pint_plan_create (the message names the instance). */
 pint_status pint_batch_plan_create(pint_plan **plan, int count, const pint_grid *grids,
                                    const pint_params *params, void *hip_stream);

@@ -20,17 +20,46 @@ constexpr int kGenNT = 256;
 // Rb [N][M] (FP64).  A workgroup owns W consecutive dofs: their N time levels
 // and the weights w_0..w_{N-1} are staged in LDS, so the history sums read LDS
 // only; stencil neighbours come from global memory (L2).
+// The residual of dof d at row q from its level u = U_q[d] and the history sum
+// h = sum_{j<=q} w_j U_{q-j}[d] (residual form), or the direct-form
+// right-hand side with c = sum_{j>q} w_j U_{N+q-j}[d] in h; written to Rb.
+__device__ __forceinline__ void gn_resid_point(const GenArgs& a, int q, int d, double u, double h) {
+    const size_t M = a.M;
+    double r = a.v ? a.ta * a.s[q] * a.v[d] : 0.0;
+    if (a.f) r += a.f[(size_t)(q + 1) * M + d];
+    if (q < a.ncorr) r += a.corr[(size_t)q * M + d];
+    if (a.nl) {
+        const double vd = a.v ? a.v[d] : 0.0;
+        r -= a.c3 * u * u * u + a.c1 * u;
+        if (q < a.ncorr) r -= a.an[q] * (a.c3 * vd * vd * vd + a.c1 * vd);
+    }
+    if (a.dvar) r -= a.dvar[d] * u;
+    if (a.form == 0) {
+        const int x = d % a.mx, rr = d / a.mx, y = rr % a.my, z = rr / a.my;
+        const double* Uq = a.U + (size_t)q * M;
+        const size_t sy = (size_t)a.mx, sz = (size_t)a.mx * a.my;
+        double nb = a.ihx2 * ((x > 0 ? Uq[d - 1] : 0.0) + (x < a.mx - 1 ? Uq[d + 1] : 0.0));
+        if (a.my > 1) nb += a.ihy2 * ((y > 0 ? Uq[d - sy] : 0.0) + (y < a.my - 1 ? Uq[d + sy] : 0.0));
+        if (a.mz > 1) nb += a.ihz2 * ((z > 0 ? Uq[d - sz] : 0.0) + (z < a.mz - 1 ? Uq[d + sz] : 0.0));
+        r += nb - 2.0 * (a.ihx2 + a.ihy2 + a.ihz2) * u - a.ta * h;
+    } else {
+        r += a.kappa * a.ta * h;
+    }
+    a.Rb[(size_t)q * M + d] = a.raw ? r : r * a.scale[q];
+}
+
+// Short histories (BDF-k) and the direct form: a workgroup owns W consecutive
+// dofs; their N time levels and the weights w_0..w_{N-1} are staged in LDS and
+// the sums read LDS only; stencil neighbours come from global memory (L2).
 // Tiles t0, t0 + tstride, ... of the problem (every workgroup of a grid, or one
-// workgroup walking all tiles of its problem); gl: N (W + 1) doubles of LDS.
+// workgroup per tile); gl: N (W + 1) doubles of LDS.
 __device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, int tstride, double* gl) {
     const int N = a.N;
     const size_t M = a.M;
     double* om = gl;            // [N]
     double* tl = gl + N;        // [N][W]
-    double* hs = tl + (size_t)N * W;   // [N][W] history sums (long histories only)
     const int tid = threadIdx.x;
     const int ntiles = (a.M + W - 1) / W;
-    const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
     for (int j = tid; j < N; j += kGenNT) om[j] = j <= a.jmax ? a.w[j] : 0.0;
     for (int tile = t0; tile < ntiles; tile += tstride) {
         const int d0 = tile * W;
@@ -40,73 +69,18 @@ __device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, i
             tl[idx] = d < a.M ? a.U[(size_t)q * M + d] : 0.0;
         }
         __syncthreads();
-        // Long histories (CQ): the time-stencil sums of QB consecutive rows of one
-        // dof are formed together, QB independent accumulators, the weights in a
-        // sliding register window; they go to the LDS row of the dof's sums hs.
-        constexpr int QB = 8;
-        const bool blocked = a.form == 0 && a.jmax >= 16;
-        if (blocked) {
-            const int nb = (N + QB - 1) / QB;
-            for (int it = tid; it < nb * W; it += kGenNT) {
-                const int q0 = (it / W) * QB, wl = it % W;
-                double acc[QB], win[QB];
-#pragma unroll
-                for (int r = 0; r < QB; ++r) {
-                    acc[r] = 0.0;
-                    win[r] = (q0 + r < N && q0 + r <= a.jmax) ? om[q0 + r] : 0.0;   // w_{q0+r-i} at i = 0
-                }
-                const int iend = q0 + QB < N ? q0 + QB : N;
-                for (int i = 0; i < iend; ++i) {
-                    const double ui = tl[i * W + wl];
-#pragma unroll
-                    for (int r = 0; r < QB; ++r)
-                        if (i <= q0 + r) acc[r] += win[r] * ui;
-                    // next i: w_{q0+r-i-1}: shift the window down, the new low entry
-#pragma unroll
-                    for (int r = QB - 1; r > 0; --r) win[r] = win[r - 1];
-                    const int jn = q0 - i - 1;
-                    win[0] = (jn >= 0 && jn <= a.jmax) ? om[jn] : 0.0;
-                }
-#pragma unroll
-                for (int r = 0; r < QB; ++r)
-                    if (q0 + r < N) hs[(q0 + r) * W + wl] = acc[r];
-            }
-            __syncthreads();
-        }
         for (int idx = tid; idx < N * W; idx += kGenNT) {
             const int q = idx / W, wl = idx % W, d = d0 + wl;
             if (d >= a.M) continue;
-            double r = a.v ? a.ta * a.s[q] * a.v[d] : 0.0;
-            if (a.f) r += a.f[(size_t)(q + 1) * M + d];
-            if (q < a.ncorr) r += a.corr[(size_t)q * M + d];
-            if (a.nl) {
-                const double u = tl[q * W + wl], vd = a.v ? a.v[d] : 0.0;
-                r -= a.c3 * u * u * u + a.c1 * u;
-                if (q < a.ncorr) r -= a.an[q] * (a.c3 * vd * vd * vd + a.c1 * vd);
-            }
-            if (a.dvar) r -= a.dvar[d] * tl[q * W + wl];
+            double h = 0.0;
             if (a.form == 0) {
-                const int x = d % a.mx, rr = d / a.mx, y = rr % a.my, z = rr / a.my;
-                const double* Uq = a.U + (size_t)q * M;
-                const size_t sy = (size_t)a.mx, sz = (size_t)a.mx * a.my;
-                double nb = a.ihx2 * ((x > 0 ? Uq[d - 1] : 0.0) + (x < a.mx - 1 ? Uq[d + 1] : 0.0));
-                if (a.my > 1) nb += a.ihy2 * ((y > 0 ? Uq[d - sy] : 0.0) + (y < a.my - 1 ? Uq[d + sy] : 0.0));
-                if (a.mz > 1) nb += a.ihz2 * ((z > 0 ? Uq[d - sz] : 0.0) + (z < a.mz - 1 ? Uq[d + sz] : 0.0));
-                double h = 0.0;
-                if (blocked) {
-                    h = hs[q * W + wl];
-                } else {
-                    const int top = q < a.jmax ? q : a.jmax;
-                    for (int j = 0; j <= top; ++j) h += om[j] * tl[(q - j) * W + wl];
-                }
-                r += nb - diag * tl[q * W + wl] - a.ta * h;
+                const int top = q < a.jmax ? q : a.jmax;
+                for (int j = 0; j <= top; ++j) h += om[j] * tl[(q - j) * W + wl];
             } else {
-                double c = 0.0;
                 const int top = a.jmax < N - 1 ? a.jmax : N - 1;
-                for (int j = q + 1; j <= top; ++j) c += om[j] * tl[(N + q - j) * W + wl];
-                r += a.kappa * a.ta * c;
+                for (int j = q + 1; j <= top; ++j) h += om[j] * tl[(N + q - j) * W + wl];
             }
-            a.Rb[(size_t)q * M + d] = a.raw ? r : r * a.scale[q];
+            gn_resid_point(a, q, d, tl[q * W + wl], h);
         }
     }
 }
@@ -116,12 +90,93 @@ __global__ __launch_bounds__(kGenNT) void k_gn_resid(GenArgs a, int W) {
     gn_resid_body(a, W, blockIdx.x, gridDim.x, gl);
 }
 
-// Dofs per tile of the residual: the N weights and two N x W tiles (levels,
-// history sums) within 64 KB of LDS.
+// Dofs per tile of the direct-sum residual: the N weights and the N x W tile of
+// levels within 64 KB of LDS.
 __host__ __device__ inline int gn_resid_width(int N) {
     int W = 16;
-    while (W > 1 && (size_t)N * (2 * W + 1) * sizeof(double) > 65536) W /= 2;
+    while (W > 1 && (size_t)N * (W + 1) * sizeof(double) > 65536) W /= 2;
     return W;
+}
+
+// Residual form with the full CQ history (a.wh set): the causal sums of a tile
+// of 2B dofs by one linear convolution per pair of dofs (dof d0 + 2j in the real
+// part, d0 + 2j + 1 in the imaginary part; the weights are real), zero-padded
+// to P = 2^LOGP >= 2N - 1 points so that no wrap-around reaches rows q < N:
+// h = IFFT_P(Wh . FFT_P(u)), Wh = FFT_P(omega, 0)/P.  This is the circulant
+// embedding of the lower-triangular Toeplitz history product (Sec. 3, cost of
+// Step 1), O(N log N) per dof instead of O(N^2).  sm: P B complex of LDS.
+template <int LOGP, int B>
+__device__ __forceinline__ void gn_resid_fft_body(const GenArgs& a, int t0, int tstride, double2* sm) {
+    constexpr int P = 1 << LOGP;
+    constexpr int W = 2 * B;
+    const int N = a.N;
+    const size_t M = a.M;
+    const int tid = threadIdx.x;
+    const int ntiles = (a.M + W - 1) / W;
+    for (int tile = t0; tile < ntiles; tile += tstride) {
+        const int d0 = tile * W;
+        for (int idx = tid; idx < P * B; idx += kGenNT) {
+            const int t = idx / B, d = d0 + 2 * (idx % B);
+            double2 z = mk<double2>(0.0, 0.0);
+            if (t < N) {
+                const double* Ut = a.U + (size_t)t * M;
+                if (d < a.M) z.x = Ut[d];
+                if (d + 1 < a.M) z.y = Ut[d + 1];
+            }
+            sm[idx] = z;
+        }
+        __syncthreads();
+        lds_fft<double, LOGP, B, kGenNT, false, true, 0>(sm, a.twh);
+        for (int idx = tid; idx < P * B; idx += kGenNT) sm[idx] = cmul(sm[idx], a.wh[idx / B]);
+        __syncthreads();
+        lds_fft<double, LOGP, B, kGenNT, true, true, 0>(sm, a.twh);
+        for (int idx = tid; idx < N * W; idx += kGenNT) {
+            const int q = idx / W, wl = idx % W, d = d0 + wl;
+            if (d >= a.M) continue;
+            const double2 hz = sm[q * B + (wl >> 1)];
+            gn_resid_point(a, q, d, a.U[(size_t)q * M + d], (wl & 1) ? hz.y : hz.x);
+        }
+        __syncthreads();   // the next tile overwrites sm
+    }
+}
+
+// Dof pairs per tile of the convolution residual: the [P][B] tile within 64 KB.
+template <int LOGP> constexpr int gn_hist_pairs() {
+    const int b = 65536 / ((1 << LOGP) * (int)sizeof(double2));
+    return b > 16 ? 16 : (b < 1 ? 1 : b);
+}
+
+template <int LOGP>
+__global__ __launch_bounds__(kGenNT) void k_gn_resid_fft(GenArgs a) {
+    __shared__ double2 sm[(1 << LOGP) * gn_hist_pairs<LOGP>()];
+    gn_resid_fft_body<LOGP, gn_hist_pairs<LOGP>()>(a, blockIdx.x, gridDim.x, sm);
+}
+
+template <int LOGP>
+hipError_t gn_resid_fft_one(const GenArgs& a, hipStream_t st) {
+    constexpr int W = 2 * gn_hist_pairs<LOGP>();
+    const void* fn = reinterpret_cast<const void*>(&k_gn_resid_fft<LOGP>);
+    const long long ntiles = ((long long)a.M + W - 1) / W;
+    const long long grid = std::max<long long>(1, std::min<long long>(ntiles, persistent_blocks(fn, kGenNT)));
+    PINT_LAUNCH(k_gn_resid_fft<LOGP>, dim3((unsigned)grid), dim3(kGenNT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t gn_resid_fft_dispatch(const GenArgs& a, hipStream_t st) {
+    switch (a.logP) {
+        case 2: return gn_resid_fft_one<2>(a, st);
+        case 3: return gn_resid_fft_one<3>(a, st);
+        case 4: return gn_resid_fft_one<4>(a, st);
+        case 5: return gn_resid_fft_one<5>(a, st);
+        case 6: return gn_resid_fft_one<6>(a, st);
+        case 7: return gn_resid_fft_one<7>(a, st);
+        case 8: return gn_resid_fft_one<8>(a, st);
+        case 9: return gn_resid_fft_one<9>(a, st);
+        case 10: return gn_resid_fft_one<10>(a, st);
+        case 11: return gn_resid_fft_one<11>(a, st);
+        case 12: return gn_resid_fft_one<12>(a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -280,144 +335,225 @@ hipError_t gn_dft_dispatch(const GenArgs& a, int* nb, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent batch of 1D problems: workgroup i runs the whole solve of problem
-// i, sweep after sweep (residual, forward time DFT, one Thomas solve per
-// retained frequency, inverse time DFT + update + norms), and stops on its own
-// update norm with the rules of the single-problem solve (tolerance, non-finite
-// update, growth in two consecutive sweeps beyond the first).  Problems of one
-// launch share the spectrum precision R and the time Bluestein length 2^LOGP.
-// The Thomas solve of (sigma_p + A_h) Q_p = H_p (diagonal sigma_p + 2/h^2,
-// off-diagonals -1/h^2) runs one frequency per lane, without pivoting (stable
-// on these diagonally dominant shifted systems), on the spectrum row in place
-// with the modified super-diagonal in the scratch.
-template <typename R>
-__device__ __forceinline__ void thomas_rows(const Batch1D& d) {
-    using T = cx<R>;
-    const int m = d.ga.mx, nP = d.ga.N / 2 + 1;
-    T* S = reinterpret_cast<T*>(d.ga.S);
-    T* C = reinterpret_cast<T*>(d.thomas);
-    const R off = (R)(-d.ih2);
-    for (int p = threadIdx.x; p < nP; p += kGenNT) {
-        const double2 sg = d.sigma[p];
-        const T b = mk<T>((R)(sg.x + 2.0 * d.ih2), (R)sg.y);
-        T* X = S + (size_t)p * d.ga.ldS;
-        T* Cp = C + (size_t)p * m;
-        T den = b;
-        T cprev = cdiv(mk<T>(off, (R)0), den);
-        Cp[0] = cprev;
-        T xprev = cdiv(X[0], den);
-        X[0] = xprev;
-        // chunks of CH equations: the chunk's loads are issued together, then the
-        // recurrence runs on registers (no memory latency per step)
-        constexpr int CH = 16;
-        for (int i0 = 1; i0 < m; i0 += CH) {
-            T xs[CH];
-#pragma unroll
-            for (int r = 0; r < CH; ++r) xs[r] = i0 + r < m ? X[i0 + r] : mk<T>((R)0, (R)0);
-#pragma unroll
-            for (int r = 0; r < CH; ++r) {
-                if (i0 + r < m) {
-                    den = mk<T>(b.x - off * cprev.x, b.y - off * cprev.y);
-                    cprev = cdiv(mk<T>(off, (R)0), den);
-                    Cp[i0 + r] = cprev;
-                    xprev = cdiv(mk<T>(xs[r].x - off * xprev.x, xs[r].y - off * xprev.y), den);
-                    xs[r] = xprev;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < CH; ++r)
-                if (i0 + r < m) X[i0 + r] = xs[r];
-        }
-        // back substitution, chunks from the end (x_{m-1} = xprev already)
-        for (int i1 = m - 2; i1 >= 0; i1 -= CH) {
-            T xs[CH], cs[CH];
-#pragma unroll
-            for (int r = 0; r < CH; ++r) {
-                const int i = i1 - r;
-                xs[r] = i >= 0 ? X[i] : mk<T>((R)0, (R)0);
-                cs[r] = i >= 0 ? Cp[i] : mk<T>((R)0, (R)0);
-            }
-#pragma unroll
-            for (int r = 0; r < CH; ++r) {
-                if (i1 - r >= 0) {
-                    xprev = mk<T>(xs[r].x - (cs[r].x * xprev.x - cs[r].y * xprev.y),
-                                  xs[r].y - (cs[r].x * xprev.y + cs[r].y * xprev.x));
-                    xs[r] = xprev;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < CH; ++r)
-                if (i1 - r >= 0) X[i1 - r] = xs[r];
-        }
+// Batched sweeps over many 1D problems that share the spectrum precision R and
+// the time Bluestein length 2^LOGP: every pass of a sweep is one launch over
+// all active problems (their tiles or frequency rows laid end to end), so each
+// pass fills the device however small the problems are.  tstart[i] .. tstart[i+1]
+// are problem i's blocks (residual and DFT tiles) or lanes (Thomas rows).
+__device__ __forceinline__ int batch_owner(const int* __restrict__ start, int n, int x) {
+    int lo = 0, hi = n;   // start[lo] <= x < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int LOGP>
+__global__ __launch_bounds__(kGenNT) void k_batch_resid(const Batch1D* __restrict__ descs,
+                                                       const int* __restrict__ tstart, int n, int W) {
+    extern __shared__ double gl[];
+    const int i = batch_owner(tstart, n, blockIdx.x);
+    const GenArgs& a = descs[i].ga;
+    if (a.wh) {
+        gn_resid_fft_body<LOGP, gn_hist_pairs<LOGP>()>(a, blockIdx.x - tstart[i], 1 << 30,
+                                                       reinterpret_cast<double2*>(gl));
+    } else {
+        gn_resid_body(a, W, blockIdx.x - tstart[i], 1 << 30, gl);
     }
 }
 
-template <typename R, int LOGP>
-__global__ __launch_bounds__(kGenNT) void k_batch1d(const Batch1D* __restrict__ descs, int count) {
-    constexpr int B = gn_slots<R, LOGP>();
-    __shared__ __align__(16) double lds[8192];        // 64 KB: residual tile, then DFT tile
+template <typename R, int LOGP, int B, bool INV>
+__global__ __launch_bounds__(kGenNT) void k_batch_dft(const Batch1D* __restrict__ descs,
+                                                     const int* __restrict__ tstart, int n,
+                                                     double* __restrict__ part) {
+    __shared__ cx<R> sm[(1 << LOGP) * B];
     __shared__ double red[2][kGenNT / 64];
-    const int i = blockIdx.x;
-    if (i >= count) return;
+    const int i = batch_owner(tstart, n, blockIdx.x);
+    double mx = 0.0, s2 = 0.0;
+    gn_dft_body<R, LOGP, B, INV>(descs[i].ga, blockIdx.x - tstart[i], 1 << 30, sm, red, mx, s2);
+    if (INV && threadIdx.x == 0) {
+        part[2 * blockIdx.x] = mx;
+        part[2 * blockIdx.x + 1] = s2;
+    }
+}
+
+// The Thomas solves of (sigma_p + A_h) Q_p = H_p (diagonal sigma_p + 2/h^2,
+// off-diagonals -1/h^2) for the retained frequencies of one problem, without
+// pivoting (stable on these diagonally dominant shifted systems), on the
+// spectrum rows in place with the modified super-diagonals in the scratch.
+// One wave per 64 frequencies, one frequency per lane: chunks of TC equations
+// of the 64 rows pass through LDS by coalesced loads and stores (consecutive
+// lanes take consecutive equations of a row), each lane runs its row's
+// recurrence on registers, and the next chunk's loads are in flight meanwhile
+// (issued unconditionally, from a clamped address, so that they overlap).
+// Problems of any time length share a launch; bstart[i] .. bstart[i+1] are
+// problem i's waves.
+template <typename R>
+__global__ __launch_bounds__(64) void k_batch_thomas(const Batch1D* __restrict__ descs,
+                                                    const int* __restrict__ bstart, int n) {
+    using T = cx<R>;
+    constexpr int TC = 16;        // equations per chunk
+    constexpr int RS = 64 / TC;   // rows per load instruction
+    constexpr int LDW = TC + 1;   // row pitch: the lanes' row reads fall on distinct banks
+    __shared__ T xs[64 * LDW];
+    __shared__ T cs[64 * LDW];
+    const int i = batch_owner(bstart, n, blockIdx.x);
     const Batch1D& d = descs[i];
-    const int W = gn_resid_width(d.ga.N);
-    double first = 0.0, prev1 = 0.0, prev2 = 0.0, mx = 0.0, s2 = 0.0;
-    int status = 1, m = 0;
-    while (m < d.max_sweeps) {
-        gn_resid_body(d.ga, W, 0, 1, lds);
+    const int m = d.ga.mx, nP = d.ga.N / 2 + 1;
+    const int p0 = (blockIdx.x - bstart[i]) * 64;
+    const int lane = threadIdx.x;
+    const int rows = nP - p0 < 64 ? nP - p0 : 64;
+    const bool live = lane < rows;
+    T* S = reinterpret_cast<T*>(d.ga.S) + (size_t)p0 * d.ga.ldS;
+    T* C = reinterpret_cast<T*>(d.thomas) + (size_t)p0 * m;
+    const size_t ld = d.ga.ldS;
+    const R off = (R)(-d.ih2);
+    const T zero = mk<T>((R)0, (R)0);
+    const double2 sg = d.sigma[live ? p0 + lane : p0];
+    const T b = mk<T>((R)(sg.x + 2.0 * d.ih2), (R)sg.y);
+    // the lane's share of a chunk: element k is (row lane/TC + k RS, equation
+    // i0 + lane%TC)
+    const int e = lane % TC, r0 = lane / TC;
+    // (the chunk buffers are kept as real and imaginary arrays, which the
+    // compiler keeps in registers)
+    auto gload = [&](const T* base, size_t pitch, int i0, int len, R (&re)[TC], R (&im)[TC]) {
+        const T* lp = base + (size_t)r0 * pitch + e + i0;
+#pragma unroll
+        for (int k = 0; k < TC; ++k) {
+            const bool ok = r0 + k * RS < rows && e < len;
+            const T t = *(ok ? lp + (size_t)k * RS * pitch : base);
+            re[k] = t.x;
+            im[k] = t.y;
+        }
+    };
+    auto to_lds = [&](T* dst, int len, const R (&re)[TC], const R (&im)[TC]) {
+#pragma unroll
+        for (int k = 0; k < TC; ++k)
+            if (r0 + k * RS < rows && e < len) dst[(r0 + k * RS) * LDW + e] = mk<T>(re[k], im[k]);
+    };
+    auto from_lds = [&](T* base, size_t pitch, int i0, int len, const T* src) {
+        T* lp = base + (size_t)r0 * pitch + e + i0;
+#pragma unroll
+        for (int k = 0; k < TC; ++k)
+            if (r0 + k * RS < rows && e < len) lp[(size_t)k * RS * pitch] = src[(r0 + k * RS) * LDW + e];
+    };
+    // forward elimination: c_i = off / den_i, x_i = (r_i - off x_{i-1}) / den_i,
+    // den_i = b - off c_{i-1} (c_{-1} = x_{-1} = 0)
+    T cprev = zero, xprev = zero;
+    R bxr[TC], bxi[TC], bcr[TC], bci[TC];
+    gload(S, ld, 0, m < TC ? m : TC, bxr, bxi);
+    for (int i0 = 0; i0 < m; i0 += TC) {
+        const int len = m - i0 < TC ? m - i0 : TC;
+        to_lds(xs, len, bxr, bxi);
+        if (i0 + TC < m) gload(S, ld, i0 + TC, m - i0 - TC < TC ? m - i0 - TC : TC, bxr, bxi);
         __syncthreads();
-        gn_dft_body<R, LOGP, B, false>(d.ga, 0, 1, reinterpret_cast<cx<R>*>(lds), red, mx, s2);
+        if (live) {
+            T v[TC];
+#pragma unroll
+            for (int j = 0; j < TC; ++j) v[j] = xs[lane * LDW + j];
+#pragma unroll
+            for (int j = 0; j < TC; ++j) {
+                if (j < len) {
+                    const T den = mk<T>(b.x - off * cprev.x, b.y - off * cprev.y);
+                    cprev = cdiv(mk<T>(off, (R)0), den);
+                    xprev = cdiv(mk<T>(v[j].x - off * xprev.x, v[j].y - off * xprev.y), den);
+                    cs[lane * LDW + j] = cprev;
+                    xs[lane * LDW + j] = xprev;
+                }
+            }
+        }
         __syncthreads();
-        thomas_rows<R>(d);
+        from_lds(S, ld, i0, len, xs);
+        from_lds(C, (size_t)m, i0, len, cs);
         __syncthreads();
-        gn_dft_body<R, LOGP, B, true>(d.ga, 0, 1, reinterpret_cast<cx<R>*>(lds), red, mx, s2);
-        const double l2 = sqrt(d.hd * s2);
-        if (threadIdx.x == 0) {
-            d.upd[m] = mx;
-            d.upd_l2[m] = l2;
+    }
+    // back substitution x_i -= c_i x_{i+1}, chunks from the last one down
+    // (x_{m-1} is final: it is the carry xprev)
+    int i0 = ((m - 1) / TC) * TC;
+    gload(S, ld, i0, m - i0, bxr, bxi);
+    gload(C, (size_t)m, i0, m - i0, bcr, bci);
+    for (; i0 >= 0; i0 -= TC) {
+        const int len = m - i0 < TC ? m - i0 : TC;
+        to_lds(xs, len, bxr, bxi);
+        to_lds(cs, len, bcr, bci);
+        if (i0 >= TC) {
+            gload(S, ld, i0 - TC, TC, bxr, bxi);
+            gload(C, (size_t)m, i0 - TC, TC, bcr, bci);
         }
-        ++m;
-        const double crit = d.norm == 0 ? mx : l2;
-        if (!(mx <= 1.0e300) || !(l2 <= 1.0e300)) {
-            status = -5;
-            break;
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int j = TC - 1; j >= 0; --j) {
+                if (j < len && i0 + j < m - 1) {
+                    const T x = xs[lane * LDW + j], c = cs[lane * LDW + j];
+                    xprev = mk<T>(x.x - (c.x * xprev.x - c.y * xprev.y), x.y - (c.x * xprev.y + c.y * xprev.x));
+                    xs[lane * LDW + j] = xprev;
+                }
+            }
         }
-        if (m == 1) first = crit;
-        if (crit <= d.tol) {
-            status = 0;
-            break;
-        }
-        if (m >= 3 && crit > prev1 && prev1 > prev2 && crit > first) {
-            status = -5;
-            break;
-        }
-        prev2 = prev1;
-        prev1 = crit;
+        __syncthreads();
+        from_lds(S, ld, i0, len, xs);
+        __syncthreads();
+    }
+}
+
+// Norms of each problem's update from its inverse-DFT blocks' partials, in a
+// fixed order: norms[i] = (max |U_m - U_{m-1}|, (h sum_x (U_m^N - U_{m-1}^N)^2)^{1/2}).
+__global__ __launch_bounds__(64) void k_batch_norms(const Batch1D* __restrict__ descs, const int* __restrict__ tstart,
+                                                    const double* __restrict__ part, double* __restrict__ norms) {
+    const int i = blockIdx.x;
+    double mx = 0.0, s2 = 0.0;
+    for (int b = tstart[i] + (int)threadIdx.x; b < tstart[i + 1]; b += 64) {
+        mx = nanmax(mx, part[2 * b]);
+        s2 += part[2 * b + 1];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = nanmax(mx, __shfl_xor(mx, off, 64));
+        s2 += __shfl_xor(s2, off, 64);
     }
     if (threadIdx.x == 0) {
-        d.result[0] = m;
-        d.result[1] = status;
+        norms[2 * i] = mx;
+        norms[2 * i + 1] = sqrt(descs[i].hd * s2);
     }
 }
 
-template <typename R>
-hipError_t batch1d_dispatch(const Batch1D* descs, int count, int logP, hipStream_t st) {
-    const dim3 g((unsigned)count), b(kGenNT);
-    switch (logP) {
-        case 2: PINT_LAUNCH((k_batch1d<R, 2>), g, b, 0, st, descs, count); break;
-        case 3: PINT_LAUNCH((k_batch1d<R, 3>), g, b, 0, st, descs, count); break;
-        case 4: PINT_LAUNCH((k_batch1d<R, 4>), g, b, 0, st, descs, count); break;
-        case 5: PINT_LAUNCH((k_batch1d<R, 5>), g, b, 0, st, descs, count); break;
-        case 6: PINT_LAUNCH((k_batch1d<R, 6>), g, b, 0, st, descs, count); break;
-        case 7: PINT_LAUNCH((k_batch1d<R, 7>), g, b, 0, st, descs, count); break;
-        case 8: PINT_LAUNCH((k_batch1d<R, 8>), g, b, 0, st, descs, count); break;
-        case 9: PINT_LAUNCH((k_batch1d<R, 9>), g, b, 0, st, descs, count); break;
-        case 10: PINT_LAUNCH((k_batch1d<R, 10>), g, b, 0, st, descs, count); break;
-        case 11: PINT_LAUNCH((k_batch1d<R, 11>), g, b, 0, st, descs, count); break;
-        case 12: PINT_LAUNCH((k_batch1d<R, 12>), g, b, 0, st, descs, count); break;
-        default: return hipErrorInvalidValue;
+template <typename R, int LOGP, bool INV>
+hipError_t batch_pass_one(const BatchLaunch& L, hipStream_t st) {
+    constexpr int B = gn_slots<R, LOGP>();
+    if (!INV) {
+        const int W = gn_resid_width(L.N);
+        const size_t lds = std::max((size_t)L.N * (W + 1) * sizeof(double),
+                                    (size_t)(1 << LOGP) * gn_hist_pairs<LOGP>() * sizeof(double2));
+        PINT_LAUNCH(k_batch_resid<LOGP>, dim3(L.nres), dim3(kGenNT), lds, st, L.descs, L.res_start, L.n, W);
+        PINT_LAUNCH((k_batch_dft<R, LOGP, B, false>), dim3(L.ndft), dim3(kGenNT), 0, st, L.descs, L.dft_start, L.n,
+                    L.part);
+    } else {
+        PINT_LAUNCH((k_batch_dft<R, LOGP, B, true>), dim3(L.ndft), dim3(kGenNT), 0, st, L.descs, L.dft_start, L.n,
+                    L.part);
+        PINT_LAUNCH(k_batch_norms, dim3(L.n), dim3(64), 0, st, L.descs, L.dft_start, L.part, L.norms);
     }
     return hipGetLastError();
+}
+
+template <typename R, bool INV>
+hipError_t batch_pass_dispatch(const BatchLaunch& L, hipStream_t st) {
+    switch (L.logP) {
+        case 2: return batch_pass_one<R, 2, INV>(L, st);
+        case 3: return batch_pass_one<R, 3, INV>(L, st);
+        case 4: return batch_pass_one<R, 4, INV>(L, st);
+        case 5: return batch_pass_one<R, 5, INV>(L, st);
+        case 6: return batch_pass_one<R, 6, INV>(L, st);
+        case 7: return batch_pass_one<R, 7, INV>(L, st);
+        case 8: return batch_pass_one<R, 8, INV>(L, st);
+        case 9: return batch_pass_one<R, 9, INV>(L, st);
+        case 10: return batch_pass_one<R, 10, INV>(L, st);
+        case 11: return batch_pass_one<R, 11, INV>(L, st);
+        case 12: return batch_pass_one<R, 12, INV>(L, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // g'(Ubar) with Ubar[x] the mean of U over the N time levels (fixed order).
@@ -472,9 +608,37 @@ __global__ __launch_bounds__(kGenNT) void k_nl_axpy(double* __restrict__ U, cons
 
 }  // namespace
 
-hipError_t launch_batch1d(const Batch1D* descs, int count, bool mixed, int logP, hipStream_t st) {
-    if (count < 1) return hipSuccess;
-    return mixed ? batch1d_dispatch<float>(descs, count, logP, st) : batch1d_dispatch<double>(descs, count, logP, st);
+int batch_dft_slots(bool mixed, int logP) {
+    const int cb = mixed ? 8 : 16;
+    const int b = 65536 / ((1 << logP) * cb);
+    return b > 16 ? 16 : (b < 1 ? 1 : b);
+}
+
+int batch_resid_width(int N) { return gn_resid_width(N); }
+
+int batch_hist_width(int logP) {
+    const int b = 65536 / ((1 << logP) * (int)sizeof(double2));
+    return 2 * (b > 16 ? 16 : (b < 1 ? 1 : b));
+}
+
+hipError_t launch_batch_forward(const BatchLaunch& L, hipStream_t st) {
+    if (L.n < 1) return hipSuccess;
+    return L.mixed ? batch_pass_dispatch<float, false>(L, st) : batch_pass_dispatch<double, false>(L, st);
+}
+
+hipError_t launch_batch_inverse(const BatchLaunch& L, hipStream_t st) {
+    if (L.n < 1) return hipSuccess;
+    return L.mixed ? batch_pass_dispatch<float, true>(L, st) : batch_pass_dispatch<double, true>(L, st);
+}
+
+hipError_t launch_batch_thomas(const Batch1D* descs, const int* bstart, int n, int nwaves, bool mixed,
+                               hipStream_t st) {
+    if (n < 1) return hipSuccess;
+    if (mixed)
+        PINT_LAUNCH((k_batch_thomas<float>), dim3(nwaves), dim3(64), 0, st, descs, bstart, n);
+    else
+        PINT_LAUNCH((k_batch_thomas<double>), dim3(nwaves), dim3(64), 0, st, descs, bstart, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_nl_mean_dg(const double* U, double* dg, int N, int M, double c3, double c1, hipStream_t st) {
@@ -493,9 +657,10 @@ hipError_t launch_nl_axpy(double* U, const double* W, double* partial, int N, in
 }
 
 hipError_t launch_gn_resid(const GenArgs& a, hipStream_t st) {
+    if (a.wh && a.form == 0) return gn_resid_fft_dispatch(a, st);
     // dofs per workgroup: the N x W tile and the N weights within 64 KB of LDS
     const int W = gn_resid_width(a.N);
-    const size_t lds = (size_t)a.N * (2 * W + 1) * sizeof(double);
+    const size_t lds = (size_t)a.N * (W + 1) * sizeof(double);
     const void* fn = reinterpret_cast<const void*>(&k_gn_resid);
     const long long ntiles = ((long long)a.M + W - 1) / W;
     const long long grid = std::max<long long>(1, std::min<long long>(ntiles, persistent_blocks(fn, kGenNT)));

@@ -143,6 +143,7 @@ struct pint_plan {
     bool gn = false;
     int logPt = 0;
     void *d_chirpT = nullptr, *d_bhT = nullptr, *d_twPT = nullptr;
+    double2 *d_whT = nullptr, *d_twhT = nullptr;   // CQ history convolution on the Bluestein length
     double* Rb = nullptr;
     size_t off_r = 0;
     // 1D plans: buffers of the semilinear solve (Newton correction W, Newton
@@ -167,11 +168,12 @@ struct pint_plan {
     double* h_norms = nullptr;  // pinned host, 2 doubles
     // batch: sub-plans sharing the stream
     std::vector<pint_plan*> inst;
-    // batch of 1D instances in persistent launches: descriptors, results, norms (device)
-    pint::Batch1D* d_batch = nullptr;
-    int* d_bres = nullptr;
-    double* d_bupd = nullptr;
-    int bsmax = 0;
+    // batch of 1D instances in batched sweeps: descriptors, prefix tables and
+    // norms (device block and its pinned host stage, same layout), DFT partials
+    void* d_bblk = nullptr;
+    void* h_bblk = nullptr;
+    size_t b_int_off = 0, b_norm_off = 0, b_bytes = 0;
+    double* d_bpart = nullptr;
     // batch 1D instance: Thomas scratch [N/2+1][M] complex in the workspace
     size_t off_th = 0;
     void* thomas = nullptr;
@@ -184,6 +186,7 @@ struct pint_plan {
         for (void* q : owned) (void)hipFree(q);
         if (ws_owned && ws) (void)hipFree(ws);
         if (h_norms) (void)hipHostFree(h_norms);
+        if (h_bblk) (void)hipHostFree(h_bblk);
         for (pint_plan* q : inst) delete q;
     }
 };
@@ -438,6 +441,27 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     if (P->gn || g->dim == 1) {
         if ((rc = upload_bluestein_tables(P, N, 2, &P->d_chirpT, &P->d_bhT, &P->d_twPT, &P->logPt)) != PINT_OK)
             return rc;
+        if (P->cq) {
+            // the residual's causal history sums as a linear convolution on the
+            // same P >= 2N - 1 points: FFT_P(omega, 0)/P and FP64 twiddles
+            const long long Pn = 1LL << P->logPt;
+            std::vector<cld> wz(Pn, cld(0, 0));
+            for (int j = 0; j < N; ++j) wz[j] = (long double)w[j];
+            host_fft(wz);
+            std::vector<double2> wh(Pn);
+            for (long long t = 0; t < Pn; ++t) {
+                wh[t].x = (double)(wz[t].real() / (long double)Pn);
+                wh[t].y = (double)(wz[t].imag() / (long double)Pn);
+            }
+            if ((rc = upload(P, &P->d_whT, wh.data(), (size_t)Pn)) != PINT_OK) return rc;
+            if (P->mixed) {
+                void* t2 = nullptr;
+                if ((rc = upload_tw(P, &t2, Pn, false)) != PINT_OK) return rc;
+                P->d_twhT = static_cast<double2*>(t2);
+            } else {
+                P->d_twhT = static_cast<double2*>(P->d_twPT);
+            }
+        }
     }
     if (!P->gn && P->cq) {
         // spectrum of (omega, 0) on 2N points, divided by 2N (inverse normalisation)
@@ -676,6 +700,10 @@ GenArgs gen_args(const pint_plan* P, double* U) {
     ga.form = P->p.form == PINT_DIRECT ? 1 : 0;
     ga.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
     ga.an = P->d_an;
+    if (ga.form == 0) {
+        ga.wh = P->d_whT;
+        ga.twh = P->d_twhT;
+    }
     return ga;
 }
 
@@ -1279,28 +1307,39 @@ pint_status pint_batch_plan_create(pint_plan** plan, int count, const pint_grid*
         P->inst.push_back(Q);
         pint_status rc = build_plan(Q, &grids[i], &params[i], P->st);
         if (rc == PINT_OK && Q->dim == 1) {
-            // the persistent 1D launch solves each frequency by Thomas in place,
+            // the batched 1D sweep solves each frequency by Thomas in place,
             // with the modified super-diagonal kept here
             Q->off_th = Q->ws_bytes;
             Q->ws_bytes += align256((size_t)Q->nP * Q->M * (Q->mixed ? 8 : 16));
         }
         if (rc == PINT_OK) rc = own_workspace(Q);
         if (rc != PINT_OK) return bail(fail(rc, "instance " + std::to_string(i) + ": " + g_err));
-        P->bsmax = std::max(P->bsmax, params[i].max_sweeps);
     }
+    // batched 1D sweeps: descriptors [count], prefix tables (two of n+1
+    // entries per class, one of n+1 per precision: at most 5 count + 2 in
+    // all), norms [count][2]; DFT partials, one pair per DFT tile of every 1D
+    // instance
+    size_t ntile = 0;
+    for (pint_plan* Q : P->inst)
+        if (Q->dim == 1) {
+            const int B = pint::batch_dft_slots(Q->mixed, Q->logPt);
+            ntile += ((size_t)Q->Mp + B - 1) / B;
+        }
+    P->b_int_off = align256((size_t)count * sizeof(pint::Batch1D));
+    P->b_norm_off = P->b_int_off + align256((size_t)6 * (count + 1) * sizeof(int));
+    P->b_bytes = P->b_norm_off + align256((size_t)count * 2 * sizeof(double));
     void* q = nullptr;
-    if ((e = hipMalloc(&q, (size_t)count * sizeof(pint::Batch1D))) != hipSuccess)
+    if ((e = hipMalloc(&q, P->b_bytes)) != hipSuccess) return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
+    P->owned.push_back(q);
+    P->d_bblk = q;
+    if ((e = hipMalloc(&q, std::max<size_t>(ntile, 1) * 2 * sizeof(double))) != hipSuccess)
         return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
     P->owned.push_back(q);
-    P->d_batch = static_cast<pint::Batch1D*>(q);
-    if ((e = hipMalloc(&q, (size_t)count * 2 * sizeof(int))) != hipSuccess)
+    P->d_bpart = static_cast<double*>(q);
+    if ((e = hipHostMalloc(&P->h_bblk, P->b_bytes, hipHostMallocDefault)) != hipSuccess) {
+        P->h_bblk = nullptr;
         return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
-    P->owned.push_back(q);
-    P->d_bres = static_cast<int*>(q);
-    if ((e = hipMalloc(&q, (size_t)count * 2 * P->bsmax * sizeof(double))) != hipSuccess)
-        return bail(fail(PINT_E_NOMEM, hipGetErrorString(e)));
-    P->owned.push_back(q);
-    P->d_bupd = static_cast<double*>(q);
+    }
     *plan = P;
     return PINT_OK;
 }
@@ -1315,60 +1354,143 @@ pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double*
             return fail(PINT_E_ARG, "instance " + std::to_string(i) + ": max_sweeps exceeds the upd stride");
     }
     pint_status result = PINT_OK;
-    // 1D instances: bound and started here, then solved by persistent launches,
-    // one per (precision, time Bluestein length) class, one workgroup each
-    std::vector<int> ones;
-    for (int i = 0; i < count; ++i)
-        if (P->inst[i]->dim == 1) ones.push_back(i);
-    if (!ones.empty()) {
-        std::vector<std::pair<std::pair<int, int>, int>> order;   // ((mixed, logP), instance)
-        for (int i : ones) {
-            pint_plan* Q = P->inst[i];
-            pint_status rc = pint_bind(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr);
-            if (rc == PINT_OK) rc = pint_init_iterate(Q, U[i]);
-            if (rc != PINT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
-            order.push_back({{Q->mixed ? 1 : 0, Q->logPt}, i});
-        }
-        std::sort(order.begin(), order.end());
-        std::vector<pint::Batch1D> packed;
-        for (auto& o : order) {
-            const int i = o.second;
-            pint_plan* Q = P->inst[i];
-            pint::Batch1D b{};
-            b.ga = gen_args(Q, U[i]);
-            b.sigma = Q->d_sigma;
-            b.thomas = Q->thomas;
-            b.ih2 = Q->ih2[0];
-            b.tol = Q->p.tol;
-            b.hd = Q->hd;
-            b.norm = Q->p.norm == PINT_NORM_INF ? 0 : 1;
-            b.max_sweeps = Q->p.max_sweeps;
-            b.upd = P->d_bupd + (size_t)i * 2 * P->bsmax;
-            b.upd_l2 = b.upd + P->bsmax;
-            b.result = P->d_bres + 2 * i;
-            packed.push_back(b);
-        }
-        HIP_TRY(hipMemcpyAsync(P->d_batch, packed.data(), packed.size() * sizeof(pint::Batch1D),
-                               hipMemcpyHostToDevice, P->st));
-        for (size_t a = 0; a < order.size();) {
+    // 1D instances: bound and started here, then swept together: each sweep is
+    // one launch per pass over all active instances of a (precision, time
+    // Bluestein length) class, followed by the host stop test of every instance
+    // (the rules of the single-problem solve); finished instances drop out
+    struct Track {
+        int i;
+        int key;           // 64 mixed + logP: the class (the precisions apart)
+        double first, prev1, prev2;
+        bool active;
+    };
+    std::vector<Track> tr;
+    for (int i = 0; i < count; ++i) {
+        pint_plan* Q = P->inst[i];
+        if (Q->dim != 1) continue;
+        pint_status rc = pint_bind(Q, v[i], f ? f[i] : nullptr, fder ? fder[i] : nullptr);
+        if (rc == PINT_OK) rc = pint_init_iterate(Q, U[i]);
+        if (rc != PINT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+        if (sweeps) sweeps[i] = 0;
+        tr.push_back({i, (Q->mixed ? 64 : 0) + Q->logPt, 0.0, 0.0, 0.0, true});
+    }
+    std::stable_sort(tr.begin(), tr.end(), [](const Track& x, const Track& y) { return x.key < y.key; });
+    char* hb = static_cast<char*>(P->h_bblk);
+    char* db = static_cast<char*>(P->d_bblk);
+    pint::Batch1D* hdesc = reinterpret_cast<pint::Batch1D*>(hb);
+    int* hint = reinterpret_cast<int*>(hb + P->b_int_off);
+    const double* hnorm = reinterpret_cast<const double*>(hb + P->b_norm_off);
+    std::vector<pint::BatchLaunch> launches;
+    std::vector<int> who;   // packed position -> index into tr
+    struct ThomasLaunch {
+        int d0, n, nwaves, i0;   // descriptors d0 .. d0+n-1, prefix table at int offset i0
+        bool mixed;
+    };
+    std::vector<ThomasLaunch> thomas;
+    for (int m = 0;; ++m) {
+        // pack the active instances, class by class (all FP64 classes first)
+        launches.clear();
+        who.clear();
+        thomas.clear();
+        int nd = 0, ni = 0, npart = 0;
+        for (size_t a = 0; a < tr.size();) {
             size_t e2 = a;
-            while (e2 < order.size() && order[e2].first == order[a].first) ++e2;
-            HIP_TRY(pint::launch_batch1d(P->d_batch + a, (int)(e2 - a), order[a].first.first == 1,
-                                         order[a].first.second, P->st));
+            while (e2 < tr.size() && tr[e2].key == tr[a].key) ++e2;
+            pint::BatchLaunch L{};
+            L.logP = tr[a].key & 63;
+            L.mixed = tr[a].key >= 64;
+            const int B = pint::batch_dft_slots(L.mixed, L.logP);
+            for (size_t t = a; t < e2; ++t)
+                if (tr[t].active && P->inst[tr[t].i]->p.max_sweeps > m) L.N = std::max(L.N, P->inst[tr[t].i]->N);
+            const int W = L.N > 0 ? pint::batch_resid_width(L.N) : 1;
+            int* rs = hint + ni;
+            int n = 0;
+            rs[0] = 0;
+            std::vector<int> ds{0};
+            for (size_t t = a; t < e2; ++t) {
+                pint_plan* Q = P->inst[tr[t].i];
+                if (!tr[t].active || Q->p.max_sweeps <= m) continue;
+                pint::Batch1D& b = hdesc[nd + n];
+                b = pint::Batch1D{};
+                b.ga = gen_args(Q, U[tr[t].i]);
+                b.sigma = Q->d_sigma;
+                b.thomas = Q->thomas;
+                b.ih2 = Q->ih2[0];
+                b.hd = Q->hd;
+                const int Wq = b.ga.wh ? pint::batch_hist_width(L.logP) : W;
+                rs[n + 1] = rs[n] + (Q->M + Wq - 1) / Wq;
+                ds.push_back(ds.back() + (Q->Mp + B - 1) / B);
+                who.push_back((int)t);
+                ++n;
+            }
+            if (n > 0) {
+                std::copy(ds.begin(), ds.end(), rs + n + 1);
+                L.descs = reinterpret_cast<const pint::Batch1D*>(db) + nd;
+                L.res_start = reinterpret_cast<const int*>(db + P->b_int_off) + ni;
+                L.dft_start = L.res_start + n + 1;
+                L.part = P->d_bpart + 2 * (size_t)npart;
+                L.norms = reinterpret_cast<double*>(db + P->b_norm_off) + 2 * nd;
+                L.n = n;
+                L.nres = rs[n];
+                L.ndft = ds.back();
+                launches.push_back(L);
+                if (thomas.empty() || thomas.back().mixed != L.mixed) thomas.push_back({nd, 0, 0, 0, L.mixed});
+                thomas.back().n += n;
+                nd += n;
+                ni += 2 * (n + 1);
+                npart += ds.back();
+            }
             a = e2;
         }
-        std::vector<int> res((size_t)count * 2, 0);
-        std::vector<double> bupd((size_t)count * 2 * P->bsmax, 0.0);
-        HIP_TRY(hipMemcpyAsync(res.data(), P->d_bres, res.size() * sizeof(int), hipMemcpyDeviceToHost, P->st));
-        HIP_TRY(hipMemcpyAsync(bupd.data(), P->d_bupd, bupd.size() * sizeof(double), hipMemcpyDeviceToHost, P->st));
-        HIP_TRY(hipStreamSynchronize(P->st));   // also keeps packed alive until its copy is done
-        for (int i : ones) {
-            const int done = res[2 * i], st = res[2 * i + 1];
-            if (sweeps) sweeps[i] = done;
-            if (upd)
-                for (int m = 0; m < done; ++m) upd[(size_t)i * stride + m] = bupd[(size_t)i * 2 * P->bsmax + m];
-            if (st == -5) result = fail(PINT_E_DIVERGED, "instance " + std::to_string(i) + ": diverged");
-            else if (st == 1 && result == PINT_OK) result = PINT_NOT_CONVERGED;
+        if (nd == 0) break;
+        // the Thomas pass: one launch per precision over its instances of every class
+        for (ThomasLaunch& T : thomas) {
+            T.i0 = ni;
+            int* ts = hint + ni;
+            ts[0] = 0;
+            for (int k = 0; k < T.n; ++k) ts[k + 1] = ts[k] + (hdesc[T.d0 + k].ga.N / 2 + 1 + 63) / 64;
+            T.nwaves = ts[T.n];
+            ni += T.n + 1;
+        }
+        HIP_TRY(hipMemcpyAsync(db, hb, (size_t)nd * sizeof(pint::Batch1D), hipMemcpyHostToDevice, P->st));
+        HIP_TRY(hipMemcpyAsync(db + P->b_int_off, hint, (size_t)ni * sizeof(int), hipMemcpyHostToDevice, P->st));
+        for (const pint::BatchLaunch& L : launches) HIP_TRY(pint::launch_batch_forward(L, P->st));
+        for (const ThomasLaunch& T : thomas)
+            HIP_TRY(pint::launch_batch_thomas(reinterpret_cast<const pint::Batch1D*>(db) + T.d0,
+                                              reinterpret_cast<const int*>(db + P->b_int_off) + T.i0, T.n,
+                                              T.nwaves, T.mixed, P->st));
+        for (const pint::BatchLaunch& L : launches) HIP_TRY(pint::launch_batch_inverse(L, P->st));
+        HIP_TRY(hipMemcpyAsync(hb + P->b_norm_off, db + P->b_norm_off, (size_t)nd * 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, P->st));
+        HIP_TRY(hipStreamSynchronize(P->st));   // also frees the stage for the next sweep
+        for (int k = 0; k < nd; ++k) {
+            Track& T = tr[who[k]];
+            pint_plan* Q = P->inst[T.i];
+            const double ninf = hnorm[2 * k], nl2 = hnorm[2 * k + 1];
+            if (upd) upd[(size_t)T.i * stride + m] = ninf;
+            if (sweeps) sweeps[T.i] = m + 1;
+            const double crit = Q->p.norm == PINT_NORM_INF ? ninf : nl2;
+            if (!std::isfinite(ninf) || !std::isfinite(nl2)) {
+                result = fail(PINT_E_DIVERGED, "instance " + std::to_string(T.i) + ": non-finite update");
+                T.active = false;
+                continue;
+            }
+            if (m == 0) T.first = crit;
+            if (crit <= Q->p.tol) {
+                T.active = false;
+                continue;
+            }
+            if (m >= 2 && crit > T.prev1 && T.prev1 > T.prev2 && crit > T.first) {
+                result = fail(PINT_E_DIVERGED, "instance " + std::to_string(T.i) + ": update grew");
+                T.active = false;
+                continue;
+            }
+            T.prev2 = T.prev1;
+            T.prev1 = crit;
+            if (m + 1 >= Q->p.max_sweeps) {
+                T.active = false;
+                if (result == PINT_OK) result = PINT_NOT_CONVERGED;
+            }
         }
     }
     for (int i = 0; i < count; ++i) {

@@ -90,21 +90,33 @@ struct GenArgs {
     double c3, c1;
     const double* an;       // [5] a_n of Table 1
     const double* dvar;     // [M] or nullptr
+    // residual form with the full CQ history: the causal sums by a zero-padded
+    // length-P convolution (nullptr: direct sums)
+    const double2* wh;      // [P] FFT_P(omega_0..omega_{N-1}, 0, ..., 0) / P
+    const double2* twh;     // [P] e^{-2 pi i j/P} in FP64
 };
 
-// One 1D problem of a persistent batch launch (one workgroup runs its whole
-// solve: WR sweeps with the general-length time DFTs and a Thomas solve per
-// frequency, and its own stop test).
+// One 1D problem of a batched sweep (every pass one launch over all active
+// problems of a class): its sweep arguments and the Thomas solve's tables.
 struct Batch1D {
     GenArgs ga;             // the problem's sweep arguments (U, data, tables, workspace)
     const double2* sigma;   // [N/2+1] tau^{-alpha} d_p
     void* thomas;           // [N/2+1][m] complex scratch in the spectrum precision
-    double ih2, tol, hd;
-    int norm;               // 0 max over space-time, 1 terminal L2_h
-    int max_sweeps;
-    double* upd;            // [max_sweeps] max-norm update per sweep (device, out)
-    double* upd_l2;         // [max_sweeps] terminal L2_h update per sweep (device, out)
-    int* result;            // [2] sweeps done, status (0 converged, 1 max_sweeps, -5 diverged)
+    double ih2, hd;
+};
+
+// One batched sweep over the n active problems of a class (same spectrum
+// precision and time Bluestein length 2^logP; N the largest time length of
+// the class).  Device arrays: descs [n]; res_start / dft_start [n+1] prefix
+// sums of each problem's residual tiles / DFT tiles; part [dft_start[n]][2]
+// scratch; norms [n][2] out.
+struct BatchLaunch {
+    const Batch1D* descs;
+    const int *res_start, *dft_start;
+    double* part;
+    double* norms;
+    int n, N, logP, nres, ndft;
+    bool mixed;
 };
 
 // Spatial shifted solves on the spectrum.
@@ -158,9 +170,21 @@ hipError_t launch_space(const SpaceArgs& a, bool mixed, hipStream_t st);
 hipError_t launch_gn_resid(const GenArgs& a, hipStream_t st);
 hipError_t launch_gn_forward(const GenArgs& a, bool mixed, hipStream_t st);
 hipError_t launch_gn_inverse(const GenArgs& a, bool mixed, int* nblocks_out, hipStream_t st);
-// Persistent batch launch over count 1D problems that share the spectrum
-// precision and the time Bluestein length 2^logP (one workgroup per problem).
-hipError_t launch_batch1d(const Batch1D* descs, int count, bool mixed, int logP, hipStream_t st);
+// Batched sweep in three steps: launch_batch_forward (residual, forward time
+// DFT) per class, launch_batch_thomas (a Thomas solve per retained frequency)
+// over all problems of one precision, whatever their class (bstart [n+1]
+// prefix sums of each problem's waves ceil((N_i/2+1)/64), one workgroup of 64
+// lanes each), launch_batch_inverse (inverse DFT + update, norms) per class.
+// Tiles per problem: residual tiles of batch_hist_width(logP) dofs when its
+// history is convolved (ga.wh set), else of batch_resid_width(N) dofs; DFT
+// tiles of batch_dft_slots(mixed, logP) slots.
+hipError_t launch_batch_forward(const BatchLaunch& L, hipStream_t st);
+hipError_t launch_batch_thomas(const Batch1D* descs, const int* bstart, int n, int nwaves, bool mixed,
+                               hipStream_t st);
+hipError_t launch_batch_inverse(const BatchLaunch& L, hipStream_t st);
+int batch_dft_slots(bool mixed, int logP);
+int batch_resid_width(int N);
+int batch_hist_width(int logP);
 // Sequential-in-time solver: right-hand side of step n into one complex plane
 // (slot order), and U^n back from the solved plane.
 hipError_t launch_seq_rhs(const GenArgs& a, int n, void* plane, hipStream_t st);
