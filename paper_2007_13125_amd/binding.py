@@ -239,7 +239,8 @@ def pint_batch_solve(plan, v, f, fder, U, max_sweeps):
     st = lib().pint_batch_solve(plan, arr(v), arr(f), arr(fder), arr(U), upd, int(max_sweeps), sw)
     _check(st, "pint_batch_solve", allow=(PINT_OK, PINT_NOT_CONVERGED, PINT_E_DIVERGED))
     sw = list(sw)
-    return st, [list(upd)[i * max_sweeps:i * max_sweeps + sw[i]] for i in range(n)], sw
+    u = list(upd)
+    return st, [u[i * max_sweeps:i * max_sweeps + sw[i]] for i in range(n)], sw
 
 
 def pint_plan_set_autotune(plan, reps):

@@ -196,9 +196,11 @@ hipError_t gn_resid_fft_dispatch(const GenArgs& a, hipStream_t st) {
 // Tiles g0, g0 + gstride, ... of B slots; sm: P B values of LDS, red: 2 x 4
 // doubles of LDS.  INV: on return every lane holds the workgroup's (max |U_m -
 // U_{m-1}|, sum over q = N-1 of the update squared) in mx_out, s2_out.
-template <typename R, int LOGP, int B, bool INV>
+// BLUE = false (N = 2^LOGP itself, twx its twiddles): the same transforms by
+// one power-of-two FFT of length N, no chirp.
+template <typename R, int LOGP, int B, bool INV, bool BLUE = true>
 __device__ __forceinline__ void gn_dft_body(const GenArgs& a, int g0, int gstride, cx<R>* sm, double (*red)[kGenNT / 64],
-                                            double& mx_out, double& s2_out) {
+                                            double& mx_out, double& s2_out, const cx<R>* twx = nullptr) {
     using T = cx<R>;
     constexpr int P = 1 << LOGP;
     const int tid = threadIdx.x;
@@ -228,26 +230,30 @@ __device__ __forceinline__ void gn_dft_body(const GenArgs& a, int g0, int gstrid
                     if (t > N / 2) qv.y = -qv.y;     // Q_t = conj(Q_{N-t})
                     val = mk<T>(qv.x, -qv.y);        // DFT input conj(Q_t)
                 }
-                val = cmul(val, cw[t]);
+                if (BLUE) val = cmul(val, cw[t]);
             }
             sm[idx] = val;
         }
         __syncthreads();
-        lds_fft<R, LOGP, B, kGenNT, false, true, 0>(sm, tw);
-        for (int idx = tid; idx < P * B; idx += kGenNT) sm[idx] = cmul(sm[idx], bh[idx / B]);
-        __syncthreads();
-        lds_fft<R, LOGP, B, kGenNT, true, true, 0>(sm, tw);
+        if constexpr (BLUE) {
+            lds_fft<R, LOGP, B, kGenNT, false, true, 0>(sm, tw);
+            for (int idx = tid; idx < P * B; idx += kGenNT) sm[idx] = cmul(sm[idx], bh[idx / B]);
+            __syncthreads();
+            lds_fft<R, LOGP, B, kGenNT, true, true, 0>(sm, tw);
+        } else {
+            lds_fft<R, LOGP, B, kGenNT, false, true, 0>(sm, twx);
+        }
         if constexpr (!INV) {
             for (int idx = tid; idx < (N / 2 + 1) * B; idx += kGenNT) {
                 const int p = idx / B, slot = s0 + idx % B;
-                if (slot < a.Mp) S[(size_t)p * a.ldS + slot] = cmul(sm[idx], cw[p]);
+                if (slot < a.Mp) S[(size_t)p * a.ldS + slot] = BLUE ? cmul(sm[idx], cw[p]) : sm[idx];
             }
         } else {
             for (int idx = tid; idx < N * B; idx += kGenNT) {
                 const int q = idx / B, slot = s0 + idx % B;
                 const int d = slot < a.Mp ? slot_dof(slot, a.mx, a.mxp, a.Mp) : -1;
                 if (d < 0) continue;
-                const T xq = cmul(sm[idx], cw[q]);
+                const T xq = BLUE ? cmul(sm[idx], cw[q]) : sm[idx];
                 const double delta = (double)xq.x * a.unscale[q];
                 double* up = a.Uw + (size_t)q * M + d;
                 const double u = *up;
@@ -364,15 +370,18 @@ __global__ __launch_bounds__(kGenNT) void k_batch_resid(const Batch1D* __restric
     }
 }
 
-template <typename R, int LOGP, int B, bool INV>
+// Time DFTs of a class: Bluestein on 2^LOGX points (BLUE), or, for a class of
+// power-of-two time lengths N = 2^LOGX, one FFT of length N.
+template <typename R, int LOGX, int B, bool INV, bool BLUE>
 __global__ __launch_bounds__(kGenNT) void k_batch_dft(const Batch1D* __restrict__ descs,
                                                      const int* __restrict__ tstart, int n,
                                                      double* __restrict__ part) {
-    __shared__ cx<R> sm[(1 << LOGP) * B];
+    __shared__ cx<R> sm[(1 << LOGX) * B];
     __shared__ double red[2][kGenNT / 64];
     const int i = batch_owner(tstart, n, blockIdx.x);
     double mx = 0.0, s2 = 0.0;
-    gn_dft_body<R, LOGP, B, INV>(descs[i].ga, blockIdx.x - tstart[i], 1 << 30, sm, red, mx, s2);
+    gn_dft_body<R, LOGX, B, INV, BLUE>(descs[i].ga, blockIdx.x - tstart[i], 1 << 30, sm, red, mx, s2,
+                                       reinterpret_cast<const cx<R>*>(descs[i].twN));
     if (INV && threadIdx.x == 0) {
         part[2 * blockIdx.x] = mx;
         part[2 * blockIdx.x + 1] = s2;
@@ -414,40 +423,44 @@ __global__ __launch_bounds__(64) void k_batch_thomas(const Batch1D* __restrict__
     const double2 sg = d.sigma[live ? p0 + lane : p0];
     const T b = mk<T>((R)(sg.x + 2.0 * d.ih2), (R)sg.y);
     // the lane's share of a chunk: element k is (row lane/TC + k RS, equation
-    // i0 + lane%TC)
+    // i0 + lane%TC).  Raw buffer accesses over the wave's rows (32-bit lane
+    // offsets; a lane without an element gets the offset kNoLane, whose load
+    // returns 0 and whose store is dropped), so the loads of a chunk issue
+    // back to back and only the vector-memory counter tracks them.  The chunk
+    // buffers are real and imaginary arrays, which the compiler keeps in
+    // registers.
     const int e = lane % TC, r0 = lane / TC;
-    // (the chunk buffers are kept as real and imaginary arrays, which the
-    // compiler keeps in registers)
-    auto gload = [&](const T* base, size_t pitch, int i0, int len, R (&re)[TC], R (&im)[TC]) {
-        const T* lp = base + (size_t)r0 * pitch + e + i0;
+    const __amdgpu_buffer_rsrc_t rs_S = buf_rsrc(S, (unsigned long long)rows * ld * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rs_C = buf_rsrc(C, (unsigned long long)rows * m * sizeof(T));
+    auto offs = [&](size_t pitch, int i0, int len, int k) -> unsigned {
+        const int r = r0 + k * RS;
+        return (r < rows && e < len) ? (unsigned)(((size_t)r * pitch + i0 + e) * sizeof(T)) : kNoLane;
+    };
+    auto gload = [&](__amdgpu_buffer_rsrc_t rsrc, size_t pitch, int i0, int len, R (&re)[TC], R (&im)[TC]) {
 #pragma unroll
         for (int k = 0; k < TC; ++k) {
-            const bool ok = r0 + k * RS < rows && e < len;
-            const T t = *(ok ? lp + (size_t)k * RS * pitch : base);
+            const T t = buf_ld(rsrc, offs(pitch, i0, len, k), T{});
             re[k] = t.x;
             im[k] = t.y;
         }
     };
-    auto to_lds = [&](T* dst, int len, const R (&re)[TC], const R (&im)[TC]) {
+    auto to_lds = [&](T* dst, const R (&re)[TC], const R (&im)[TC]) {
 #pragma unroll
-        for (int k = 0; k < TC; ++k)
-            if (r0 + k * RS < rows && e < len) dst[(r0 + k * RS) * LDW + e] = mk<T>(re[k], im[k]);
+        for (int k = 0; k < TC; ++k) dst[(r0 + k * RS) * LDW + e] = mk<T>(re[k], im[k]);
     };
-    auto from_lds = [&](T* base, size_t pitch, int i0, int len, const T* src) {
-        T* lp = base + (size_t)r0 * pitch + e + i0;
+    auto from_lds = [&](__amdgpu_buffer_rsrc_t rsrc, size_t pitch, int i0, int len, const T* src) {
 #pragma unroll
-        for (int k = 0; k < TC; ++k)
-            if (r0 + k * RS < rows && e < len) lp[(size_t)k * RS * pitch] = src[(r0 + k * RS) * LDW + e];
+        for (int k = 0; k < TC; ++k) buf_st(rsrc, offs(pitch, i0, len, k), src[(r0 + k * RS) * LDW + e]);
     };
     // forward elimination: c_i = off / den_i, x_i = (r_i - off x_{i-1}) / den_i,
     // den_i = b - off c_{i-1} (c_{-1} = x_{-1} = 0)
     T cprev = zero, xprev = zero;
     R bxr[TC], bxi[TC], bcr[TC], bci[TC];
-    gload(S, ld, 0, m < TC ? m : TC, bxr, bxi);
+    gload(rs_S, ld, 0, m < TC ? m : TC, bxr, bxi);
     for (int i0 = 0; i0 < m; i0 += TC) {
         const int len = m - i0 < TC ? m - i0 : TC;
-        to_lds(xs, len, bxr, bxi);
-        if (i0 + TC < m) gload(S, ld, i0 + TC, m - i0 - TC < TC ? m - i0 - TC : TC, bxr, bxi);
+        to_lds(xs, bxr, bxi);
+        if (i0 + TC < m) gload(rs_S, ld, i0 + TC, m - i0 - TC < TC ? m - i0 - TC : TC, bxr, bxi);
         __syncthreads();
         if (live) {
             T v[TC];
@@ -465,22 +478,22 @@ __global__ __launch_bounds__(64) void k_batch_thomas(const Batch1D* __restrict__
             }
         }
         __syncthreads();
-        from_lds(S, ld, i0, len, xs);
-        from_lds(C, (size_t)m, i0, len, cs);
+        from_lds(rs_S, ld, i0, len, xs);
+        from_lds(rs_C, (size_t)m, i0, len, cs);
         __syncthreads();
     }
     // back substitution x_i -= c_i x_{i+1}, chunks from the last one down
     // (x_{m-1} is final: it is the carry xprev)
     int i0 = ((m - 1) / TC) * TC;
-    gload(S, ld, i0, m - i0, bxr, bxi);
-    gload(C, (size_t)m, i0, m - i0, bcr, bci);
+    gload(rs_S, ld, i0, m - i0, bxr, bxi);
+    gload(rs_C, (size_t)m, i0, m - i0, bcr, bci);
     for (; i0 >= 0; i0 -= TC) {
         const int len = m - i0 < TC ? m - i0 : TC;
-        to_lds(xs, len, bxr, bxi);
-        to_lds(cs, len, bcr, bci);
+        to_lds(xs, bxr, bxi);
+        to_lds(cs, bcr, bci);
         if (i0 >= TC) {
-            gload(S, ld, i0 - TC, TC, bxr, bxi);
-            gload(C, (size_t)m, i0 - TC, TC, bcr, bci);
+            gload(rs_S, ld, i0 - TC, TC, bxr, bxi);
+            gload(rs_C, (size_t)m, i0 - TC, TC, bcr, bci);
         }
         __syncthreads();
         if (live) {
@@ -494,7 +507,7 @@ __global__ __launch_bounds__(64) void k_batch_thomas(const Batch1D* __restrict__
             }
         }
         __syncthreads();
-        from_lds(S, ld, i0, len, xs);
+        from_lds(rs_S, ld, i0, len, xs);
         __syncthreads();
     }
 }
@@ -520,19 +533,20 @@ __global__ __launch_bounds__(64) void k_batch_norms(const Batch1D* __restrict__ 
     }
 }
 
-template <typename R, int LOGP, bool INV>
+template <typename R, int LOGP, bool INV, bool POW2>
 hipError_t batch_pass_one(const BatchLaunch& L, hipStream_t st) {
-    constexpr int B = gn_slots<R, LOGP>();
+    constexpr int LOGX = POW2 ? LOGP - 1 : LOGP;   // power-of-two N: P = 2N
+    constexpr int B = gn_slots<R, LOGX>();
     if (!INV) {
         const int W = gn_resid_width(L.N);
         const size_t lds = std::max((size_t)L.N * (W + 1) * sizeof(double),
                                     (size_t)(1 << LOGP) * gn_hist_pairs<LOGP>() * sizeof(double2));
         PINT_LAUNCH(k_batch_resid<LOGP>, dim3(L.nres), dim3(kGenNT), lds, st, L.descs, L.res_start, L.n, W);
-        PINT_LAUNCH((k_batch_dft<R, LOGP, B, false>), dim3(L.ndft), dim3(kGenNT), 0, st, L.descs, L.dft_start, L.n,
-                    L.part);
+        PINT_LAUNCH((k_batch_dft<R, LOGX, B, false, !POW2>), dim3(L.ndft), dim3(kGenNT), 0, st, L.descs,
+                    L.dft_start, L.n, L.part);
     } else {
-        PINT_LAUNCH((k_batch_dft<R, LOGP, B, true>), dim3(L.ndft), dim3(kGenNT), 0, st, L.descs, L.dft_start, L.n,
-                    L.part);
+        PINT_LAUNCH((k_batch_dft<R, LOGX, B, true, !POW2>), dim3(L.ndft), dim3(kGenNT), 0, st, L.descs,
+                    L.dft_start, L.n, L.part);
         PINT_LAUNCH(k_batch_norms, dim3(L.n), dim3(64), 0, st, L.descs, L.dft_start, L.part, L.norms);
     }
     return hipGetLastError();
@@ -540,18 +554,31 @@ hipError_t batch_pass_one(const BatchLaunch& L, hipStream_t st) {
 
 template <typename R, bool INV>
 hipError_t batch_pass_dispatch(const BatchLaunch& L, hipStream_t st) {
+    if (L.pow2) {
+        switch (L.logP) {
+            case 5: return batch_pass_one<R, 5, INV, true>(L, st);
+            case 6: return batch_pass_one<R, 6, INV, true>(L, st);
+            case 7: return batch_pass_one<R, 7, INV, true>(L, st);
+            case 8: return batch_pass_one<R, 8, INV, true>(L, st);
+            case 9: return batch_pass_one<R, 9, INV, true>(L, st);
+            case 10: return batch_pass_one<R, 10, INV, true>(L, st);
+            case 11: return batch_pass_one<R, 11, INV, true>(L, st);
+            case 12: return batch_pass_one<R, 12, INV, true>(L, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (L.logP) {
-        case 2: return batch_pass_one<R, 2, INV>(L, st);
-        case 3: return batch_pass_one<R, 3, INV>(L, st);
-        case 4: return batch_pass_one<R, 4, INV>(L, st);
-        case 5: return batch_pass_one<R, 5, INV>(L, st);
-        case 6: return batch_pass_one<R, 6, INV>(L, st);
-        case 7: return batch_pass_one<R, 7, INV>(L, st);
-        case 8: return batch_pass_one<R, 8, INV>(L, st);
-        case 9: return batch_pass_one<R, 9, INV>(L, st);
-        case 10: return batch_pass_one<R, 10, INV>(L, st);
-        case 11: return batch_pass_one<R, 11, INV>(L, st);
-        case 12: return batch_pass_one<R, 12, INV>(L, st);
+        case 2: return batch_pass_one<R, 2, INV, false>(L, st);
+        case 3: return batch_pass_one<R, 3, INV, false>(L, st);
+        case 4: return batch_pass_one<R, 4, INV, false>(L, st);
+        case 5: return batch_pass_one<R, 5, INV, false>(L, st);
+        case 6: return batch_pass_one<R, 6, INV, false>(L, st);
+        case 7: return batch_pass_one<R, 7, INV, false>(L, st);
+        case 8: return batch_pass_one<R, 8, INV, false>(L, st);
+        case 9: return batch_pass_one<R, 9, INV, false>(L, st);
+        case 10: return batch_pass_one<R, 10, INV, false>(L, st);
+        case 11: return batch_pass_one<R, 11, INV, false>(L, st);
+        case 12: return batch_pass_one<R, 12, INV, false>(L, st);
         default: return hipErrorInvalidValue;
     }
 }

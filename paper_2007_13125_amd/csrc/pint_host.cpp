@@ -663,6 +663,10 @@ SpaceArgs space_args(const pint_plan* P) {
     return sa;
 }
 
+// A 1D batch instance whose time DFTs take plain FFTs of length N (power of
+// two, at least 16; the Bluestein length is then 2N).
+bool batch_pow2(const pint_plan* Q) { return is_pow2(Q->N) && Q->N >= 16 && (1 << Q->logPt) == 2 * Q->N; }
+
 GenArgs gen_args(const pint_plan* P, double* U) {
     GenArgs ga{};
     ga.U = U;
@@ -1322,7 +1326,7 @@ pint_status pint_batch_plan_create(pint_plan** plan, int count, const pint_grid*
     size_t ntile = 0;
     for (pint_plan* Q : P->inst)
         if (Q->dim == 1) {
-            const int B = pint::batch_dft_slots(Q->mixed, Q->logPt);
+            const int B = pint::batch_dft_slots(Q->mixed, batch_pow2(Q) ? Q->logPt - 1 : Q->logPt);
             ntile += ((size_t)Q->Mp + B - 1) / B;
         }
     P->b_int_off = align256((size_t)count * sizeof(pint::Batch1D));
@@ -1360,7 +1364,7 @@ pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double*
     // (the rules of the single-problem solve); finished instances drop out
     struct Track {
         int i;
-        int key;           // 64 mixed + logP: the class (the precisions apart)
+        int key;           // 128 mixed + 64 pow2 + logP: the class (the precisions apart)
         double first, prev1, prev2;
         bool active;
     };
@@ -1372,7 +1376,7 @@ pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double*
         if (rc == PINT_OK) rc = pint_init_iterate(Q, U[i]);
         if (rc != PINT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
         if (sweeps) sweeps[i] = 0;
-        tr.push_back({i, (Q->mixed ? 64 : 0) + Q->logPt, 0.0, 0.0, 0.0, true});
+        tr.push_back({i, (Q->mixed ? 128 : 0) + (batch_pow2(Q) ? 64 : 0) + Q->logPt, 0.0, 0.0, 0.0, true});
     }
     std::stable_sort(tr.begin(), tr.end(), [](const Track& x, const Track& y) { return x.key < y.key; });
     char* hb = static_cast<char*>(P->h_bblk);
@@ -1398,8 +1402,9 @@ pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double*
             while (e2 < tr.size() && tr[e2].key == tr[a].key) ++e2;
             pint::BatchLaunch L{};
             L.logP = tr[a].key & 63;
-            L.mixed = tr[a].key >= 64;
-            const int B = pint::batch_dft_slots(L.mixed, L.logP);
+            L.pow2 = (tr[a].key & 64) != 0;
+            L.mixed = tr[a].key >= 128;
+            const int B = pint::batch_dft_slots(L.mixed, L.pow2 ? L.logP - 1 : L.logP);
             for (size_t t = a; t < e2; ++t)
                 if (tr[t].active && P->inst[tr[t].i]->p.max_sweeps > m) L.N = std::max(L.N, P->inst[tr[t].i]->N);
             const int W = L.N > 0 ? pint::batch_resid_width(L.N) : 1;
@@ -1415,6 +1420,7 @@ pint_status pint_batch_solve(pint_plan* P, const double* const* v, const double*
                 b.ga = gen_args(Q, U[tr[t].i]);
                 b.sigma = Q->d_sigma;
                 b.thomas = Q->thomas;
+                b.twN = Q->d_twN;
                 b.ih2 = Q->ih2[0];
                 b.hd = Q->hd;
                 const int Wq = b.ga.wh ? pint::batch_hist_width(L.logP) : W;

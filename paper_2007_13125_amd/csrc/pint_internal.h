@@ -102,12 +102,14 @@ struct Batch1D {
     GenArgs ga;             // the problem's sweep arguments (U, data, tables, workspace)
     const double2* sigma;   // [N/2+1] tau^{-alpha} d_p
     void* thomas;           // [N/2+1][m] complex scratch in the spectrum precision
+    const void* twN;        // [N] e^{-2 pi i j/N}, spectrum precision (power-of-two N)
     double ih2, hd;
 };
 
 // One batched sweep over the n active problems of a class (same spectrum
-// precision and time Bluestein length 2^logP; N the largest time length of
-// the class).  Device arrays: descs [n]; res_start / dft_start [n+1] prefix
+// precision and time Bluestein length 2^logP, and either all of power-of-two
+// time length N = 2^(logP-1) >= 16 (pow2: plain FFTs of length N) or none;
+// N the largest time length of the class).  Device arrays: descs [n]; res_start / dft_start [n+1] prefix
 // sums of each problem's residual tiles / DFT tiles; part [dft_start[n]][2]
 // scratch; norms [n][2] out.
 struct BatchLaunch {
@@ -116,7 +118,7 @@ struct BatchLaunch {
     double* part;
     double* norms;
     int n, N, logP, nres, ndft;
-    bool mixed;
+    bool mixed, pow2;
 };
 
 // Spatial shifted solves on the spectrum.
@@ -177,7 +179,7 @@ hipError_t launch_gn_inverse(const GenArgs& a, bool mixed, int* nblocks_out, hip
 // lanes each), launch_batch_inverse (inverse DFT + update, norms) per class.
 // Tiles per problem: residual tiles of batch_hist_width(logP) dofs when its
 // history is convolved (ga.wh set), else of batch_resid_width(N) dofs; DFT
-// tiles of batch_dft_slots(mixed, logP) slots.
+// tiles of batch_dft_slots(mixed, pow2 ? logP - 1 : logP) slots.
 hipError_t launch_batch_forward(const BatchLaunch& L, hipStream_t st);
 hipError_t launch_batch_thomas(const Batch1D* descs, const int* bstart, int n, int nwaves, bool mixed,
                                hipStream_t st);
