@@ -1,13 +1,16 @@
-"""The persistent batch launch for 1D problems (one workgroup per problem runs
-all of its WR sweeps and its own stop test): a batch of problems with different
-m, N (powers of two and others), k, alpha, kappa and precision, each against the
-sequential oracle, through pint_batch_plan_create / pint_batch_solve."""
+"""Batched sweeps of 1D problems (every pass of a sweep one launch over all
+active problems of a class, a host stop test per problem after each sweep): a
+batch of problems with different m, N (powers of two and others), k, alpha,
+kappa and precision, each against the sequential oracle, through
+pint_batch_plan_create / pint_batch_solve; and a batch that mixes 1D, 2D and
+3D problems (the 2D and 3D ones take the single-plan path and must equal their
+own single-plan solves bit for bit)."""
 import numpy as np
 import pytest
 
 from paper_2007_13125_amd import binding as B
 from paper_2007_13125_amd import workloads as wl
-from tests.gpu_util import errors, oracle_solution, to_dev
+from tests.gpu_util import errors, gpu_solve, oracle_solution, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -17,7 +20,7 @@ def _batch(ws, precs, tol=1e-13, max_sweeps=40):
     grids = [B.make_grid(w.m) for w in ws]
     params = [B.make_params(w.k, w.alpha, w.T, w.N, w.kappa, tol=tol, max_sweeps=max_sweeps, precision=p)
               for w, p in zip(ws, precs)]
-    print("[gpu] persistent 1D batch:", [(w.m, w.N, w.k, w.alpha, p) for w, p in zip(ws, precs)], flush=True)
+    print("[gpu] batch:", [(w.m, w.N, w.k, w.alpha, p) for w, p in zip(ws, precs)], flush=True)
     h = B.pint_batch_plan_create(grids, params)
     data = [(to_dev(w.v), to_dev(w.f), to_dev(w.fder)) for w in ws]
     Us = [torch.empty((w.N, w.M), dtype=torch.float64, device="cuda") for w in ws]
@@ -61,3 +64,23 @@ def test_persistent_batch_of_recipe_1d_instances():
         print(f"recipe 1D {i}: m={w.m} N={w.N} k={w.k} alpha={w.alpha} kappa={w.kappa:.2g}: sweeps={sw[i]} "
               f"(rel_l2, max_rel)={err}", flush=True)
         assert max(err) <= 1e-10, (i, err)
+
+
+def test_batch_of_mixed_dimensions():
+    ws = [wl.heat1d(seed=51, m=63, N=64, k=2, kappa=1e-3), wl.heat2d(seed=52, m=(31, 15), N=128, k=4, kappa=1e-4),
+          wl.heat1d(seed=53, m=127, N=48, k=3, kappa=1e-3), wl.heat3d(seed=54, m=(7, 15, 7), N=32, k=6, kappa=1e-4),
+          wl.heat2d(seed=55, m=(20, 33), N=30, k=3, kappa=1e-3), wl.heat1d(seed=56, m=40, N=256, k=4, kappa=1e-4)]
+    ws[2].alpha = 0.6
+    ws[4].alpha = 0.5
+    precs = ["fp64", "fp64", "mixed", "mixed", "fp64", "fp64"]
+    st, got, upd, sw = _batch(ws, precs)
+    assert st == B.PINT_OK, (st, sw)
+    for i, (w, p) in enumerate(zip(ws, precs)):
+        err = errors(got[i], oracle_solution(w))
+        print(f"mixed-dim {i}: m={w.m} N={w.N} k={w.k} alpha={w.alpha} {p}: sweeps={sw[i]} (rel_l2, max_rel)={err}",
+              flush=True)
+        assert max(err) <= (1e-11 if p == "fp64" else 1e-10), (i, err)
+        if len(w.m) > 1:
+            single, info = gpu_solve(w, precision=p, tol=1e-13, max_sweeps=40)
+            assert info["sweeps"] == sw[i] and np.array_equal(got[i], single), i
+            assert upd[i] == list(info["upd"][:sw[i]]), i
