@@ -29,6 +29,10 @@ contraction  spectral radius of the WR error-propagation matrix for one
              spatial mode (Sec. 2.4 Lemma conv-heat, Sec. 3.3 Lemma conv-frac).
 exact        exact semi-discrete single-mode solutions used to pin the order
              of the corrected schemes (Lemmas 2.2 and 3.2).
+fem          P1 finite elements in 1D (Sec. 4's discretisation): the scaled
+             mass matrix, O1 and O2 with the mass on the time derivative.
+nonlinear    the semilinear scheme stepped in time and Algorithm 3.
+windows      consecutive time windows, each solved by O1.
 
 Parity pins for every function live in ``tests/test_oracle_*.py``; the only
 result without an external pin is listed as "parity unpinned" in the module

@@ -32,16 +32,18 @@ def lower_toeplitz(k, alpha, N):
     return L
 
 
-def all_at_once(A, k, alpha, T, N, kappa):
-    """Dense P (NM x NM), time index slowest."""
+def all_at_once(A, k, alpha, T, N, kappa, mass=None):
+    """Dense P (NM x NM), time index slowest.  With a mass matrix (P1 finite
+    elements) the time part is B (x) mass instead of B (x) I."""
     A = np.asarray(A.toarray() if hasattr(A, "toarray") else A, dtype=np.float64)
     M = A.shape[0]
     tau = T / N
-    return tau ** (-alpha) * np.kron(kappa_circulant(k, alpha, N, kappa), np.eye(M)) + np.kron(np.eye(N), A)
+    E = np.eye(M) if mass is None else np.asarray(mass.toarray() if hasattr(mass, "toarray") else mass)
+    return tau ** (-alpha) * np.kron(kappa_circulant(k, alpha, N, kappa), E) + np.kron(np.eye(N), A)
 
 
-def sweep_dense(A, k, alpha, T, N, kappa, F):
+def sweep_dense(A, k, alpha, T, N, kappa, F, mass=None):
     """U_m = P^{-1} F_{m-1} by one dense LU solve; F is [N, M]."""
-    P = all_at_once(A, k, alpha, T, N, kappa)
+    P = all_at_once(A, k, alpha, T, N, kappa, mass)
     F = np.asarray(F, dtype=np.float64)
     return np.linalg.solve(P, F.reshape(-1)).reshape(F.shape)

@@ -359,7 +359,10 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
     if (lin >= ncol * nchunk) return;
     const int col = lin % ncol, chk = lin / ncol;
     const int nxt = a.mxp / W;
-    const int xt = IS3 ? col / a.my : col % nxt, yl = IS3 ? col % a.my : col / nxt;   // 3D: y lines fastest
+    // x tiles fastest: an XCD's resident workgroups hold whole grid rows of a few
+    // consecutive lines, so the x halos and most y-neighbour lines are loaded by
+    // workgroups of the same XCD at the same time (its L2 serves them)
+    const int xt = col % nxt, yl = col / nxt;
     const int nm = IS3 ? a.mz : a.my;
     const int c0 = chk * chunk, c1 = min(nm, c0 + chunk);
     const int tid = threadIdx.x;

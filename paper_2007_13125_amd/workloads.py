@@ -59,6 +59,9 @@ class Workload:
     # {"v": c_v, "f": c_f} with c[i, j, ...] the coefficient of
     # sin((i+1) pi x) sin((j+1) pi y) ...; f(x, t) = cos(2 pi t) * series(c_f)
     modes: Optional[dict] = None
+    # spatial discretisation: "fd" (finite differences; f holds the source) or
+    # "fem" (1D P1 elements; f holds the scaled loads (f(t), phi_i)/h)
+    space: str = "fd"
 
     @property
     def dim(self):
@@ -216,6 +219,66 @@ def example4(k, alpha, M=999, N=100, eps=1.0):
     fder = np.zeros((k - 2, M)) if k > 2 else None
     w = Workload("example4", (M,), k, alpha, T, N, 0.1, np.zeros(M), f, fder, 1e-12)
     return w, 1.0 / eps ** 2, -1.0 / eps ** 2
+
+
+def _hat_integral(x, h, a, b):
+    """Integral over (a, b) of the hat function of node x (support x - h .. x + h)."""
+    def prim(s):   # antiderivative of the hat from x - h, s clipped to the support
+        s = min(max(s, x - h), x + h)
+        if s <= x:
+            return (s - x + h) ** 2 / (2 * h)
+        return h / 2 + (s - x) - (s - x) ** 2 / (2 * h)
+    return prim(b) - prim(a) if b > a else 0.0
+
+
+def _l2_projection(load_over_h):
+    """Nodal values of the P1 L2 projection from the scaled load (v, phi_i)/h:
+    the solve of tridiag(1, 4, 1)/6 y = load/h (Dirichlet nodes excluded)."""
+    from scipy.linalg import solve_banded
+    m = load_over_h.shape[0]
+    ab = np.zeros((3, m))
+    ab[0, 1:] = 1.0 / 6.0
+    ab[1, :] = 4.0 / 6.0
+    ab[2, :-1] = 1.0 / 6.0
+    return solve_banded((1, 1), ab, load_over_h)
+
+
+def example1_fem(k, M=999, N=100):
+    """Sec. 4, Example 1 (Table 2) with the paper's P1 elements: v_h the L2
+    projection of the indicator of (0, 1/2); Ft(t)_i = (e^t cos x, phi_i)/h
+    = e^t cos(x_i) 2 (1 - cos h)/h^2 exactly; its time derivatives likewise."""
+    h = 1.0 / (M + 1)
+    x = _nodes(M)
+    T = 0.5
+    load_v = np.array([_hat_integral(xi, h, 0.0, 0.5) for xi in x]) / h
+    v = _l2_projection(load_v)
+    t = T * np.arange(N + 1) / N
+    g = np.cos(x) * 2.0 * (1.0 - np.cos(h)) / h ** 2
+    f = np.exp(t)[:, None] * g[None, :]
+    fder = np.tile(g, (k - 2, 1)) if k > 2 else None
+    w = Workload("example1_fem", (M,), k, 1.0, T, N, 0.5, v, f, fder, 1e-12)
+    w.space = "fem"
+    return w
+
+
+def example2_fem(k, M=999, N=100):
+    """Sec. 4, Example 2 (Table 3) with P1 elements: v_h the L2 projection of
+    delta_{1/2}, whose load (delta, phi_i) = phi_i(1/2); f = 0."""
+    h = 1.0 / (M + 1)
+    x = _nodes(M)
+    load_v = np.maximum(0.0, 1.0 - np.abs(x - 0.5) / h) / h
+    v = _l2_projection(load_v)
+    w = Workload("example2_fem", (M,), k, 0.5, 0.1, N, 0.1, v, None, None, 1e-12)
+    w.space = "fem"
+    return w
+
+
+def fem1d(seed=61, m=63, N=64, k=2, alpha=1.0, T=1.0, kappa=1e-3, tol=1e-12):
+    """A 1D P1 problem with smooth random data: v_h nodal values of 8 sine modes
+    with N(0,1)/j^2 amplitudes, scaled loads Ft = 4 sine modes x cos(2 pi j t)."""
+    w = heat1d(seed=seed, m=m, N=N, k=k, T=T, kappa=kappa, tol=tol)
+    w.name, w.alpha, w.space = "fem1d", alpha, "fem"
+    return w
 
 
 CONFIGS = {
