@@ -64,6 +64,21 @@ enum { PINT_NORM_INF = 0,     /* stop on max over space-time of |U_m - U_{m-1}| 
 enum { PINT_INIT_V = 0,       /* U_0^n = v for all n (Thm 2.6 / Thm 3.5)             */
        PINT_INIT_ZERO = 1,    /* U_0 = 0 (the start of Tables 2 and 3)               */
        PINT_INIT_USER = 2 };  /* U_0 is the content of U on entry                    */
+enum { PINT_SPACE_FD = 0,     /* finite-difference Dirichlet Laplacian A_h (default)  */
+       PINT_SPACE_FEM_P1 = 1 }; /* 1D only: Galerkin P1 elements on the uniform mesh,
+                                 the discretisation of Sec. 4's experiments: mass
+                                 M_h = h/6 tridiag(1,4,1), stiffness K_h = (1/h)
+                                 tridiag(-1,2,-1).  The library solves the system
+                                 divided by h, Mt d_t^alpha u + A_h u = Ft with
+                                 Mt = M_h/h, A_h = K_h/h (the FD matrix), so:
+                                 v holds the nodal values of v_h, and f, fder hold
+                                 the scaled loads Ft(t_n)_i = (f(t_n), phi_i)/h and
+                                 their time derivatives at 0.  The time schemes,
+                                 Table 1 corrections and Algorithms 1/2 are those of
+                                 the FD case with Mt on the time-derivative terms;
+                                 Step 2 solves (tau^{-alpha} d_p Mt + A_h) Q_p = H_p
+                                 (exact per sine mode: Mt has eigenvalues
+                                 (2 + cos(j pi h))/3).  Stop-test norms as for FD. */
 
 /* Box (0,len_0) x ... with m[i] interior nodes per direction, h_i = len_i/(m_i+1).
  * dim in 1..3; entries beyond dim are ignored. */
@@ -77,7 +92,7 @@ typedef struct {
     int k;            /* BDF order 1..6                                              */
     double alpha;     /* 0 < alpha <= 1; alpha == 1 selects the heat equation         */
     double T;         /* final time > 0                                               */
-    int N;            /* number of time steps; a power of two, 8 <= N <= 2048, N > k  */
+    int N;            /* number of time steps; even, k < N <= 2048                    */
     double kappa;     /* WR relaxation parameter, 0 < kappa < 1                       */
     double tol;       /* stop when the chosen update norm is <= tol (> 0)             */
     int max_sweeps;   /* >= 1                                                         */
@@ -85,6 +100,7 @@ typedef struct {
     int form;         /* PINT_RESIDUAL | PINT_DIRECT                                  */
     int norm;         /* PINT_NORM_INF | PINT_NORM_L2_TERMINAL                        */
     int init;         /* PINT_INIT_V | PINT_INIT_ZERO | PINT_INIT_USER                */
+    int space;        /* PINT_SPACE_FD | PINT_SPACE_FEM_P1 (0 = FD)                    */
 } pint_params;
 
 typedef struct pint_plan pint_plan;

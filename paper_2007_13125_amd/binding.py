@@ -24,6 +24,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 FORM = {"residual": 0, "direct": 1}
 NORM = {"inf": 0, "l2T": 1}
 INIT = {"v": 0, "zero": 1, "user": 2}
+SPACE = {"fd": 0, "fem": 1}
 
 
 class pint_grid(ctypes.Structure):
@@ -33,7 +34,7 @@ class pint_grid(ctypes.Structure):
 class pint_params(ctypes.Structure):
     _fields_ = [("k", c_int), ("alpha", c_double), ("T", c_double), ("N", c_int),
                 ("kappa", c_double), ("tol", c_double), ("max_sweeps", c_int),
-                ("precision", c_int), ("form", c_int), ("norm", c_int), ("init", c_int)]
+                ("precision", c_int), ("form", c_int), ("norm", c_int), ("init", c_int), ("space", c_int)]
 
 
 EXPORTS = {
@@ -110,11 +111,12 @@ def make_grid(m, length=None):
 
 
 def make_params(k, alpha, T, N, kappa, tol=1e-12, max_sweeps=50, precision="fp64", form="residual",
-                norm="inf", init="v"):
+                norm="inf", init="v", space="fd"):
     p = pint_params()
     p.k, p.alpha, p.T, p.N, p.kappa = int(k), float(alpha), float(T), int(N), float(kappa)
     p.tol, p.max_sweeps = float(tol), int(max_sweeps)
     p.precision, p.form, p.norm, p.init = PRECISION[precision], FORM[form], NORM[norm], INIT[init]
+    p.space = SPACE[space]
     return p
 
 
@@ -277,14 +279,14 @@ class Plan:
     """One problem on one device: owns the plan handle and a torch-allocated workspace."""
 
     def __init__(self, m, k, alpha, T, N, kappa, tol=1e-12, max_sweeps=50, precision="fp64",
-                 form="residual", norm="inf", init="v", length=None, stream=None):
+                 form="residual", norm="inf", init="v", length=None, stream=None, space="fd"):
         import torch
         self.m, self.N, self.max_sweeps = tuple(m), int(N), int(max_sweeps)
         self.M = 1
         for x in m:
             self.M *= int(x)
         self.grid = make_grid(m, length)
-        self.params = make_params(k, alpha, T, N, kappa, tol, max_sweeps, precision, form, norm, init)
+        self.params = make_params(k, alpha, T, N, kappa, tol, max_sweeps, precision, form, norm, init, space)
         self.h = pint_plan_create(self.grid, self.params, stream)
         nbytes = pint_plan_workspace_bytes(self.h)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")

@@ -23,9 +23,20 @@ constexpr int kGenNT = 256;
 // The residual of dof d at row q from its level u = U_q[d] and the history sum
 // h = sum_{j<=q} w_j U_{q-j}[d] (residual form), or the direct-form
 // right-hand side with c = sum_{j>q} w_j U_{N+q-j}[d] in h; written to Rb.
+// 1D P1 elements: (Mt x)_d with Mt = tridiag(1, 4, 1)/6 and zero Dirichlet values.
+__device__ __forceinline__ double mass_row(const double* x, int d, int m) {
+    return (4.0 * x[d] + (d > 0 ? x[d - 1] : 0.0) + (d + 1 < m ? x[d + 1] : 0.0)) * (1.0 / 6.0);
+}
+
+// A value at (row q, dof d) of the history sums' input: U, or Mt U for P1 elements.
+__device__ __forceinline__ double hist_input(const GenArgs& a, int q, int d) {
+    const double* Uq = a.U + (size_t)q * a.M;
+    return a.fem ? mass_row(Uq, d, a.mx) : Uq[d];
+}
+
 __device__ __forceinline__ void gn_resid_point(const GenArgs& a, int q, int d, double u, double h) {
     const size_t M = a.M;
-    double r = a.v ? a.ta * a.s[q] * a.v[d] : 0.0;
+    double r = a.v ? a.ta * a.s[q] * (a.fem ? mass_row(a.v, d, a.mx) : a.v[d]) : 0.0;
     if (a.f) r += a.f[(size_t)(q + 1) * M + d];
     if (q < a.ncorr) r += a.corr[(size_t)q * M + d];
     if (a.nl) {
@@ -51,6 +62,7 @@ __device__ __forceinline__ void gn_resid_point(const GenArgs& a, int q, int d, d
 // Short histories (BDF-k) and the direct form: a workgroup owns W consecutive
 // dofs; their N time levels and the weights w_0..w_{N-1} are staged in LDS and
 // the sums read LDS only; stencil neighbours come from global memory (L2).
+// For P1 elements the staged levels are Mt U (the history carries the mass).
 // Tiles t0, t0 + tstride, ... of the problem (every workgroup of a grid, or one
 // workgroup per tile); gl: N (W + 1) doubles of LDS.
 __device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, int tstride, double* gl) {
@@ -66,7 +78,7 @@ __device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, i
         __syncthreads();   // the previous tile's sums are done with tl
         for (int idx = tid; idx < N * W; idx += kGenNT) {
             const int q = idx / W, d = d0 + idx % W;
-            tl[idx] = d < a.M ? a.U[(size_t)q * M + d] : 0.0;
+            tl[idx] = d < a.M ? hist_input(a, q, d) : 0.0;
         }
         __syncthreads();
         for (int idx = tid; idx < N * W; idx += kGenNT) {
@@ -80,7 +92,7 @@ __device__ __forceinline__ void gn_resid_body(const GenArgs& a, int W, int t0, i
                 const int top = a.jmax < N - 1 ? a.jmax : N - 1;
                 for (int j = q + 1; j <= top; ++j) h += om[j] * tl[(N + q - j) * W + wl];
             }
-            gn_resid_point(a, q, d, tl[q * W + wl], h);
+            gn_resid_point(a, q, d, a.fem ? a.U[(size_t)q * M + d] : tl[q * W + wl], h);
         }
     }
 }
@@ -104,7 +116,8 @@ __host__ __device__ inline int gn_resid_width(int N) {
 // to P = 2^LOGP >= 2N - 1 points so that no wrap-around reaches rows q < N:
 // h = IFFT_P(Wh . FFT_P(u)), Wh = FFT_P(omega, 0)/P.  This is the circulant
 // embedding of the lower-triangular Toeplitz history product (Sec. 3, cost of
-// Step 1), O(N log N) per dof instead of O(N^2).  sm: P B complex of LDS.
+// Step 1), O(N log N) per dof instead of O(N^2).  For P1 elements the
+// convolved levels are Mt U.  sm: P B complex of LDS.
 template <int LOGP, int B>
 __device__ __forceinline__ void gn_resid_fft_body(const GenArgs& a, int t0, int tstride, double2* sm) {
     constexpr int P = 1 << LOGP;
@@ -119,9 +132,8 @@ __device__ __forceinline__ void gn_resid_fft_body(const GenArgs& a, int t0, int 
             const int t = idx / B, d = d0 + 2 * (idx % B);
             double2 z = mk<double2>(0.0, 0.0);
             if (t < N) {
-                const double* Ut = a.U + (size_t)t * M;
-                if (d < a.M) z.x = Ut[d];
-                if (d + 1 < a.M) z.y = Ut[d + 1];
+                if (d < a.M) z.x = hist_input(a, t, d);
+                if (d + 1 < a.M) z.y = hist_input(a, t, d + 1);
             }
             sm[idx] = z;
         }

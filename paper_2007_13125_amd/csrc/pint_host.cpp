@@ -144,6 +144,8 @@ struct pint_plan {
     int logPt = 0;
     void *d_chirpT = nullptr, *d_bhT = nullptr, *d_twPT = nullptr;
     double2 *d_whT = nullptr, *d_twhT = nullptr;   // CQ history convolution on the Bluestein length
+    bool fem = false;                 // P1 elements (1D): mass matrix on the time derivative
+    double* d_mass = nullptr;         // [m] eigenvalues of the scaled mass matrix (P1 only)
     double* Rb = nullptr;
     size_t off_r = 0;
     // 1D plans: buffers of the semilinear solve (Newton correction W, Newton
@@ -318,6 +320,9 @@ pint_status validate(const pint_grid* g, const pint_params* p) {
     if (p->form != PINT_RESIDUAL && p->form != PINT_DIRECT) return fail(PINT_E_ARG, "bad form");
     if (p->norm != PINT_NORM_INF && p->norm != PINT_NORM_L2_TERMINAL) return fail(PINT_E_ARG, "bad norm");
     if (p->init < PINT_INIT_V || p->init > PINT_INIT_USER) return fail(PINT_E_ARG, "bad init");
+    if (p->space != PINT_SPACE_FD && p->space != PINT_SPACE_FEM_P1) return fail(PINT_E_ARG, "bad space");
+    if (p->space == PINT_SPACE_FEM_P1 && g->dim != 1)
+        return fail(PINT_E_UNSUPPORTED, "P1 elements are implemented for 1D grids");
     if (p->N <= p->k) return fail(PINT_E_ARG, "N must exceed k");
     if (p->N % 2 != 0) return fail(PINT_E_ARG, "N must be even");
     // The direct form's right-hand side would be assembled from FP32 spectra, so
@@ -360,7 +365,9 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
     P->ldS = (int)((P->Mp + 63) / 64 * 64);
     P->mixed = p->precision == PINT_MIXED;
     P->cq = p->alpha < 1.0;
-    P->gn = !(is_pow2(p->N) && p->N >= (1 << pint::kMinLogN));
+    P->fem = p->space == PINT_SPACE_FEM_P1;
+    // P1 elements take the general-length kernels, whose residual applies the mass matrix
+    P->gn = P->fem || !(is_pow2(p->N) && p->N >= (1 << pint::kMinLogN));
     const int N = P->N, k = p->k;
     const long double tau = (long double)p->T / N;
     P->tau = (double)tau;
@@ -498,8 +505,15 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
             mu[j] = (double)(4.0L / ((long double)h * h) * sn * sn);
         }
         if ((rc = upload(P, &P->d_mu[i], mu.data(), m)) != PINT_OK) return rc;
+        if (P->fem) {
+            // eigenvalues (2 + cos(j pi h))/3 of the scaled P1 mass matrix tridiag(1, 4, 1)/6
+            std::vector<double> mt(m);
+            for (int j = 0; j < m; ++j) mt[j] = (double)((2.0L + cosl((j + 1) * kPi / (m + 1))) / 3.0L);
+            if ((rc = upload(P, &P->d_mass, mt.data(), m)) != PINT_OK) return rc;
+        }
         const long long L = 2LL * (m + 1);
-        if (is_pow2(L) && L <= (1LL << pint::kMaxLogL) && (g->dim == 1 || L >= 8)) {
+        // (P1 elements: the sine solve with the mass divide is the Bluestein pass)
+        if (is_pow2(L) && L <= (1LL << pint::kMaxLogL) && (g->dim == 1 || L >= 8) && !P->fem) {
             if ((rc = upload_tw(P, &P->d_twL[i], L, P->mixed)) != PINT_OK) return rc;
         } else {
             if ((rc = upload_bluestein(P, i, m)) != PINT_OK) return rc;
@@ -660,6 +674,7 @@ SpaceArgs space_args(const pint_plan* P) {
     sa.var_rows = P->var[1];
     sa.var_cols = P->var[2];
     sa.var_tri = P->var[3];
+    sa.mass = P->d_mass;
     return sa;
 }
 
@@ -704,6 +719,7 @@ GenArgs gen_args(const pint_plan* P, double* U) {
     ga.form = P->p.form == PINT_DIRECT ? 1 : 0;
     ga.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
     ga.an = P->d_an;
+    ga.fem = P->fem ? 1 : 0;
     if (ga.form == 0) {
         ga.wh = P->d_whT;
         ga.twh = P->d_twhT;
@@ -1181,6 +1197,7 @@ pint_status pint_sequential_solve(pint_plan* P, const double* v, const double* f
     if (!P || !U || !v) return fail(PINT_E_ARG, "plan, v and U must not be NULL");
     if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans are not supported here");
     if (P->mixed) return fail(PINT_E_UNSUPPORTED, "the sequential solver runs in FP64");
+    if (P->fem) return fail(PINT_E_UNSUPPORTED, "the sequential solver is implemented for finite differences");
     pint_status rc = pint_bind(P, v, f, fder);
     if (rc != PINT_OK) return rc;
     GenArgs ga = gen_args(P, U);
@@ -1203,6 +1220,7 @@ pint_status pint_nonlinear_solve(pint_plan* P, double c3, double c1, const doubl
     if (!P || !U || !v) return fail(PINT_E_ARG, "plan, v and U must not be NULL");
     if (!P->inst.empty()) return fail(PINT_E_ARG, "batch plans are not supported here");
     if (P->dim != 1 || !P->nlW) return fail(PINT_E_UNSUPPORTED, "the semilinear solve is implemented for 1D grids");
+    if (P->fem) return fail(PINT_E_UNSUPPORTED, "the semilinear solve is implemented for finite differences");
     if (newton_steps < 1 || !(newton_tol >= 0.0) || !std::isfinite(c3) || !std::isfinite(c1))
         return fail(PINT_E_ARG, "bad arguments to pint_nonlinear_solve");
     if (P->p.form != PINT_RESIDUAL || P->p.precision != PINT_FP64)
@@ -1251,6 +1269,8 @@ pint_status pint_plan_set_variants(pint_plan* P, int instance, const int* choice
     const int hi[4] = {pint::kFwdVariants - 1, 1, 1, 2};
     for (int k = 0; k < 4; ++k)
         if (choices[k] < 0 || choices[k] > hi[k]) return fail(PINT_E_ARG, "variant out of range");
+    if (Q->fem && choices[3] != 0)
+        return fail(PINT_E_UNSUPPORTED, "P1 elements take the sine solve (knob 3 must be 0)");
     for (int k = 0; k < 4; ++k) Q->var[k] = choices[k];
     Q->tuned = true;   // pinned choices are not re-tuned
     return PINT_OK;
@@ -1295,6 +1315,8 @@ pint_status pint_batch_plan_create(pint_plan** plan, int count, const pint_grid*
     for (int i = 0; i < count; ++i) {
         pint_status rc = validate(&grids[i], &params[i]);
         if (rc != PINT_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+        if (params[i].space != PINT_SPACE_FD)
+            return fail(PINT_E_UNSUPPORTED, "instance " + std::to_string(i) + ": batches take finite differences");
     }
     pint_plan* P = new (std::nothrow) pint_plan();
     if (!P) return fail(PINT_E_NOMEM, "host allocation failed");

@@ -94,6 +94,9 @@ struct GenArgs {
     // length-P convolution (nullptr: direct sums)
     const double2* wh;      // [P] FFT_P(omega_0..omega_{N-1}, 0, ..., 0) / P
     const double2* twh;     // [P] e^{-2 pi i j/P} in FP64
+    // 1D P1 elements: the scaled mass matrix tridiag(1, 4, 1)/6 multiplies the
+    // time-derivative terms (history sums and the s_n v term)
+    int fem;
 };
 
 // One 1D problem of a batched sweep (every pass one launch over all active
@@ -143,6 +146,8 @@ struct SpaceArgs {
                             // 1 = PCR/Thomas (built-in split), 2 = PCR/Thomas with more PCR lanes
     const double* dvar;     // 1D only: [m] extra diagonal of the shifted operator (sigma_p + A_h +
                             // diag(dvar)), solved by PCR/Thomas whatever var_tri; or nullptr
+    const double* mass;     // 1D P1 elements only: [m] sine eigenvalues of the scaled mass
+                            // matrix; the divide is by sigma_p mass_j + mu_j (Bluestein pass); or nullptr
 };
 
 // Kernel variants the autotuner chooses between (index 0 is the built-in choice).

@@ -835,11 +835,14 @@ __global__ __launch_bounds__(NT) void k_dst_blue(SpaceArgs a, int axis, long lon
                     const long long l = g * B + b;
                     const Line ln = line(l < nlines ? l : 0);
                     const double2 sg = a.sigma[ln.p];
-                    double dre = sg.x + (axis == 0 ? a.mu[0] : (axis == 1 ? a.mu[1] : a.mu[2]))[k - 1];
+                    // P1 elements (1D): sigma_p mass_k + mu_k
+                    const double mm = a.mass ? a.mass[k - 1] : 1.0;
+                    double dre = sg.x * mm + (axis == 0 ? a.mu[0] : (axis == 1 ? a.mu[1] : a.mu[2]))[k - 1];
                     if (axis >= 1) dre += a.mu[0][ln.i1];
                     if (axis == 2) dre += a.mu[1][ln.i2];
-                    const double inv = a.inv_factor / (dre * dre + sg.y * sg.y);
-                    const T c = mk<T>((R)(dre * inv), (R)(-sg.y * inv));
+                    const double dim = sg.y * mm;
+                    const double inv = a.inv_factor / (dre * dre + dim * dim);
+                    const T c = mk<T>((R)(dre * inv), (R)(-dim * inv));
                     val[i] = cmul(cmul(sm[k * B + b], cw[k]), c);
                 }
             }
@@ -1037,12 +1040,16 @@ hipError_t cols_dispatch(const SpaceArgs& a, int axis, hipStream_t st) {
 //   3D: DST-x, DST-y, DST-z + divide + inverse, DST-y, DST-x.
 int pass_count(const SpaceArgs& a) { return a.dim == 1 ? 1 : (a.dim == 2 ? 3 : 5); }
 
+// 1D: the power-of-two sine solve (P1 elements, whose divide carries the mass
+// eigenvalues, take the Bluestein pass whatever the length).
 bool dst1d(const SpaceArgs& a) {
     const unsigned L = 2u * (unsigned)(a.mx + 1);
-    return (L & (L - 1)) == 0 && L <= (1u << kMaxLogL);
+    return (L & (L - 1)) == 0 && L <= (1u << kMaxLogL) && !a.mass;
 }
 
-bool tri1d(const SpaceArgs& a) { return a.dim == 1 && (a.dvar || (!dst1d(a) && a.var_tri >= 1)); }
+bool tri1d(const SpaceArgs& a) {
+    return a.dim == 1 && !a.mass && (a.dvar || (!dst1d(a) && a.var_tri >= 1));
+}
 
 const char* pass_name(const SpaceArgs& a, int i) {
     if (a.dim == 1) return tri1d(a) ? "tridiag_pcr_thomas" : "dst_x_solve";

@@ -2,9 +2,14 @@
 binding and the CPU oracle on the same seeded workload."""
 import numpy as np
 
+from oracle.fem import FemProblem, fem_sequential
 from oracle.grid import Grid, laplacian
 from oracle.sequential import sequential
 from oracle.sweep import Problem, iterate
+
+
+def space_of(w):
+    return getattr(w, "space", "fd")
 
 
 def to_dev(a):
@@ -17,9 +22,9 @@ def gpu_solve(w, precision="fp64", form="residual", init="v", tol=None, max_swee
 
     from paper_2007_13125_amd.binding import Plan
     print(f"[gpu] solve {w.name} m={w.m} N={w.N} k={w.k} alpha={w.alpha} kappa={w.kappa} "
-          f"{precision}/{form}/{init} variants={variants}", flush=True)
+          f"{precision}/{form}/{init}/{space_of(w)} variants={variants}", flush=True)
     plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=tol or w.tol, max_sweeps=max_sweeps,
-                precision=precision, form=form, init=init, norm=norm)
+                precision=precision, form=form, init=init, norm=norm, space=space_of(w))
     if variants is not None:
         plan.set_variants(variants)
     U, info = plan.solve(to_dev(w.v), to_dev(w.f), to_dev(w.fder))
@@ -34,8 +39,10 @@ def gpu_iterates(w, sweeps, precision="fp64", form="residual", init="v"):
     import torch
 
     from paper_2007_13125_amd.binding import Plan
-    print(f"[gpu] iterates {w.name} m={w.m} N={w.N} k={w.k} alpha={w.alpha} {precision}/{form}", flush=True)
-    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, precision=precision, form=form, init=init)
+    print(f"[gpu] iterates {w.name} m={w.m} N={w.N} k={w.k} alpha={w.alpha} {precision}/{form}/{space_of(w)}",
+          flush=True)
+    plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, precision=precision, form=form, init=init,
+                space=space_of(w))
     U = torch.empty((w.N, int(np.prod(w.m))), dtype=torch.float64, device="cuda")
     v, f, fd = to_dev(w.v), to_dev(w.f), to_dev(w.fder)
     plan.bind(v, f, fd)
@@ -52,16 +59,20 @@ def gpu_iterates(w, sweeps, precision="fp64", form="residual", init="v"):
 
 
 def oracle_solution(w, N=None, T=None):
-    A = laplacian(Grid(w.m))
     N = N or w.N
     T = T or w.T
     f = None if w.f is None else w.f[:N + 1]
+    if space_of(w) == "fem":
+        return fem_sequential(w.m[0], w.k, w.alpha, T, N, w.v, f, w.fder)
+    A = laplacian(Grid(w.m))
     return sequential(A, w.k, w.alpha, T, N, w.v, f, w.fder)
 
 
 def oracle_iterates(w, sweeps, form="residual", init="v"):
-    A = laplacian(Grid(w.m))
-    prob = Problem(A, w.k, w.alpha, w.T, w.N, w.kappa, w.v, w.f, w.fder)
+    if space_of(w) == "fem":
+        prob = FemProblem(w.m[0], w.k, w.alpha, w.T, w.N, w.kappa, w.v, w.f, w.fder)
+    else:
+        prob = Problem(laplacian(Grid(w.m)), w.k, w.alpha, w.T, w.N, w.kappa, w.v, w.f, w.fder)
     return iterate(prob, sweeps, init=init, form=form)
 
 

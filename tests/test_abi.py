@@ -96,3 +96,20 @@ def test_autotune_entry_points_reject_bad_arguments():
     assert L.pint_plan_tune(None, None, 3) == B.PINT_E_ARG
     assert L.pint_plan_get_variants(None, 0, c) == B.PINT_E_ARG
     assert L.pint_plan_set_variants(None, 0, c) == B.PINT_E_ARG
+
+
+def test_fem_validation():
+    # P1 elements are implemented for 1D grids; a bad space value is an argument error;
+    # batches take finite differences
+    p = B.make_params(2, 1.0, 1.0, 64, 1e-3, space="fem")
+    st, h = _create(B.make_grid((15, 15)), p)
+    assert st == B.PINT_E_UNSUPPORTED and not h.value
+    assert b"1D" in B.lib().pint_last_error()
+    p = B.make_params(2, 1.0, 1.0, 64, 1e-3)
+    p.space = 5
+    st, _ = _create(B.make_grid((63,)), p)
+    assert st == B.PINT_E_ARG
+    G = (B.pint_grid * 1)(B.make_grid((63,)))
+    Pm = (B.pint_params * 1)(B.make_params(2, 1.0, 1.0, 64, 1e-3, space="fem"))
+    h = ctypes.c_void_p()
+    assert B.lib().pint_batch_plan_create(ctypes.byref(h), 1, G, Pm, None) == B.PINT_E_UNSUPPORTED
