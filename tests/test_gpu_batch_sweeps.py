@@ -31,7 +31,7 @@ def _batch(ws, precs, tol=1e-13, max_sweeps=40):
     return st, [U.cpu().numpy() for U in Us], upd, sw
 
 
-def test_persistent_1d_batch_matches_oracle():
+def test_1d_batch_matches_oracle():
     ws = [wl.heat1d(seed=41, m=63, N=64, k=2, kappa=1e-3), wl.heat1d(seed=42, m=100, N=32, k=5, kappa=1e-2),
           wl.heat1d(seed=43, m=255, N=128, k=3, kappa=1e-3), wl.heat1d(seed=44, m=31, N=100, k=4, kappa=1e-2),
           wl.heat1d(seed=45, m=500, N=16, k=6, kappa=1e-4), wl.heat1d(seed=46, m=7, N=6, k=1, kappa=0.1)]
@@ -48,7 +48,7 @@ def test_persistent_1d_batch_matches_oracle():
         assert upd[i][-1] <= 1e-13 and 1 <= sw[i] < 40
 
 
-def test_persistent_batch_of_recipe_1d_instances():
+def test_batch_of_recipe_1d_instances():
     # 1D instances of the many-instance recipe (m 63..1023, N 32..1024, k 1..6,
     # alpha in {1, 0.3, 0.7}, kappa 1e-6..1e-2), mixed precision, stop test 1e-10
     ws, i = [], 0
