@@ -29,7 +29,7 @@ import scipy.sparse.linalg as spla
 
 from .cq import time_weights
 from .grid import Grid, laplacian
-from .sequential import source_terms
+from .sequential import refined_solver, source_terms
 from .sweep import Problem
 
 
@@ -55,7 +55,8 @@ def fem_sequential(m, k, alpha, T, N, v, F=None, Fder=None, length=1.0):
     """O1 with the mass matrix: U^1..U^N of
         Mt tau^{-alpha} sum_{j=0..n} omega_j (U^{n-j} - v) + A U^n = Ftbar_n,
     each step solving (omega_0 Mt + tau^alpha A) U^n
-        = Mt (sum_{j=1..n} omega_j (v - U^{n-j}) + omega_0 v) + tau^alpha Ftbar_n."""
+        = Mt (sum_{j=1..n} omega_j (v - U^{n-j}) + omega_0 v) + tau^alpha Ftbar_n
+    (LU plus long-double iterative refinement, as in ``oracle.sequential``)."""
     Mt = mass_scaled(m)
     A = stiffness_scaled(m, length)
     tau = T / N
@@ -63,11 +64,12 @@ def fem_sequential(m, k, alpha, T, N, v, F=None, Fder=None, length=1.0):
     w = time_weights(k, alpha, N + 1)
     fbar = source_terms(A, k, alpha, T, N, v, F, Fder)
     lu = spla.splu(sp.csc_matrix(w[0] * Mt + tau ** alpha * A))
+    solve = refined_solver(lu, w[0], tau ** alpha, A, mass=Mt)
     D = np.zeros((N + 1, m))          # D[n] = U^n - v
     U = np.zeros((N, m))
     for n in range(1, N + 1):
         hist = -(w[1:n + 1][::-1] @ D[:n])
-        U[n - 1] = lu.solve(Mt @ (hist + w[0] * v) + tau ** alpha * fbar[n - 1])
+        U[n - 1] = solve(Mt @ (hist + w[0] * v) + tau ** alpha * fbar[n - 1])
         D[n] = U[n - 1] - v
     return U
 

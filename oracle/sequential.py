@@ -14,6 +14,11 @@ Caputo-to-Riemann-Liouville rewrite of Sec. 3.1.  Step n solves, as in the
 cost paragraph of Sec. 3.2,
     (omega_0 I + tau^alpha A) U^n
         = sum_{j=1..n} omega_j (v - U^{n-j}) + omega_0 v + tau^alpha fbar_n.
+Each step's linear system is solved by sparse LU followed by two steps of
+iterative refinement whose residual is formed in long double, so every U^n is
+the exact solution of its step rounded to FP64 (without refinement the LU's
+error of order eps times the step matrix's condition number, ~5e3 on a
+2047-point line with N = 2048, accumulates over the steps to ~4e-11).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -53,13 +58,34 @@ def sequential(A, k, alpha, T, N, v, f=None, fder=None):
     v = np.asarray(v, dtype=np.float64).reshape(M)
     w = time_weights(k, alpha, N + 1)
     fbar = source_terms(A, k, alpha, T, N, v, f, fder)
-    lu = spla.splu(sp.csc_matrix(w[0] * sp.identity(M) + tau ** alpha * A))
+    S = sp.csc_matrix(w[0] * sp.identity(M) + tau ** alpha * A)
+    lu = spla.splu(S)
+    solve = refined_solver(lu, w[0], tau ** alpha, A)
     D = np.zeros((N + 1, M))          # D[n] = U^n - v, D[0] = 0
     U = np.zeros((N, M))
     for n in range(1, N + 1):
         # sum_{j=1..n} omega_j (v - U^{n-j}) = -sum_j omega_j D[n-j]
         hist = -(w[1:n + 1][::-1] @ D[:n]) if n > 0 else 0.0
         rhs = hist + w[0] * v + tau ** alpha * fbar[n - 1]
-        U[n - 1] = lu.solve(rhs)
+        U[n - 1] = solve(rhs)
         D[n] = U[n - 1] - v
     return U
+
+
+def refined_solver(lu, c0, c1, A, mass=None, steps=2):
+    """x = (c0 E + c1 A)^{-1} b with E = I (or the mass matrix): the LU solve
+    plus `steps` refinement steps with the residual in long double."""
+    A_ld = sp.csr_matrix(A, dtype=np.longdouble)
+    E_ld = None if mass is None else sp.csr_matrix(mass, dtype=np.longdouble)
+    c0_ld, c1_ld = np.longdouble(c0), np.longdouble(c1)
+
+    def solve(b):
+        x = lu.solve(b)
+        b_ld = np.asarray(b, dtype=np.longdouble)
+        for _ in range(steps):
+            x_ld = x.astype(np.longdouble)
+            ex = x_ld if E_ld is None else E_ld @ x_ld
+            r = b_ld - (c0_ld * ex + c1_ld * (A_ld @ x_ld))
+            x = x + lu.solve(r.astype(np.float64))
+        return x
+    return solve

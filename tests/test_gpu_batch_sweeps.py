@@ -69,10 +69,13 @@ def test_batch_of_recipe_1d_instances():
 def test_batch_of_mixed_dimensions():
     ws = [wl.heat1d(seed=51, m=63, N=64, k=2, kappa=1e-3), wl.heat2d(seed=52, m=(31, 15), N=128, k=4, kappa=1e-4),
           wl.heat1d(seed=53, m=127, N=48, k=3, kappa=1e-3), wl.heat3d(seed=54, m=(7, 15, 7), N=32, k=6, kappa=1e-4),
-          wl.heat2d(seed=55, m=(20, 33), N=30, k=3, kappa=1e-3), wl.heat1d(seed=56, m=40, N=256, k=4, kappa=1e-4)]
+          wl.heat2d(seed=55, m=(20, 33), N=30, k=3, kappa=1e-3), wl.heat1d(seed=56, m=40, N=256, k=4, kappa=1e-4),
+          wl.heat1d(seed=57, m=50, N=2048, k=2, kappa=1e-3), wl.heat1d(seed=58, m=33, N=1500, k=3, kappa=1e-3)]
     ws[2].alpha = 0.6
     ws[4].alpha = 0.5
-    precs = ["fp64", "fp64", "mixed", "mixed", "fp64", "fp64"]
+    ws[6].alpha = 0.5   # the 4096-point history convolution, power-of-two time DFTs
+    ws[7].alpha = 0.4   # the same convolution, Bluestein time DFTs
+    precs = ["fp64", "fp64", "mixed", "mixed", "fp64", "fp64", "fp64", "mixed"]
     st, got, upd, sw = _batch(ws, precs)
     assert st == B.PINT_OK, (st, sw)
     for i, (w, p) in enumerate(zip(ws, precs)):

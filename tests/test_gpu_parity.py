@@ -19,6 +19,16 @@ pytestmark = pytest.mark.gpu
 EPS = np.finfo(float).eps
 
 
+_REF = {}
+
+
+def _reference(w, key):
+    """O1 of a case, computed once per case (the largest ones take seconds)."""
+    if key not in _REF:
+        _REF[key] = oracle_solution(w)
+    return _REF[key]
+
+
 def _case(dim, m, N, k, alpha, kappa, seed=0):
     if dim == 1:
         w = wl.heat1d(seed=seed, m=m[0], N=N, k=k, kappa=kappa)
@@ -84,6 +94,10 @@ SMALL = [
     (1, (15,), 2, 1, 1.0, 0.1),
     (1, (7,), 2046, 2, 1.0, 1e-2),
     (1, (40,), 1000, 3, 0.5, 1e-3),
+    # CQ history of a time axis in 1025..2048 (the 4096-point convolution), and the
+    # largest 1D problem (m = 2047, N = 2048)
+    (1, (30,), 2000, 2, 0.5, 1e-3),
+    (1, (2047,), 2048, 2, 1.0, 1e-3),
     (2, (15, 7), 24, 4, 1.0, 1e-4),
     (2, (31, 31), 60, 3, 0.5, 1e-3),
     (2, (20, 13), 98, 6, 1.0, 1e-3),
@@ -97,7 +111,7 @@ SMALL = [
 def test_converged_matches_sequential_oracle(dim, m, N, k, alpha, kappa, precision):
     w = _case(dim, m, N, k, alpha, kappa)
     U, info = gpu_solve(w, precision=precision, tol=1e-14, max_sweeps=40)
-    ref = oracle_solution(w)
+    ref = _reference(w, (dim, m, N, k, alpha, kappa))
     err = errors(U, ref)
     bar = 1e-11 if precision == "fp64" else 1e-10
     assert max(err) <= bar, (err, info)
@@ -107,7 +121,7 @@ def test_converged_matches_sequential_oracle(dim, m, N, k, alpha, kappa, precisi
 def test_direct_form_matches_sequential_oracle(dim, m, N, k, alpha, kappa):
     w = _case(dim, m, N, k, alpha, kappa)
     U, info = gpu_solve(w, form="direct", tol=1e-12, max_sweeps=25)
-    ref = oracle_solution(w)
+    ref = _reference(w, (dim, m, N, k, alpha, kappa))
     err = errors(U, ref)
     assert max(err) <= 1e-11, (err, info)
 

@@ -340,3 +340,27 @@ def test_unpivoted_tridiagonal_is_stable_for_all_shifts(k, N, kappa, m):
             got = _thomas(a, b, a, r)
             worst = max(worst, np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
     assert worst < 1e-12
+
+
+def test_sequential_exact_per_mode_on_long_lines():
+    # O1 solves each step to FP64 rounding (long-double iterative refinement): on data
+    # that are finite sine series, the trajectory equals the sum of the scalar schemes of
+    # the modes (each sine is an eigenvector of A_h), here on the longest 1D line.  A plain
+    # LU solve per step misses this by ~1e-11 at N = 2048.
+    m, N, k = 2047, 512, 2
+    w = wl.heat1d(seed=3, m=m, N=N, k=k, kappa=1e-3)
+    g = Grid(w.m)
+    U = sequential(laplacian(g), k, 1.0, w.T, N, w.v, w.f, w.fder)
+    mu = sine_eigenvalues(m, g.h[0])
+    idx = np.arange(1, m + 1)
+    S = np.sin(np.pi * np.outer(idx, idx) / (m + 1))
+    cv = S @ w.v * 2 / (m + 1)
+    cf = (w.f @ S) * 2 / (m + 1)
+    modes = np.nonzero(np.abs(cv) + np.abs(cf).max(axis=0) > 1e-12)[0]
+    ref = np.zeros((N, m))
+    for j in modes:
+        y = sequential(mu[j], k, 1.0, w.T, N, np.array([cv[j]]), cf[:, j:j + 1])[:, 0]
+        ref += np.outer(y, S[j])
+    assert len(modes) == 8
+    assert np.linalg.norm(U - ref) / np.linalg.norm(ref) <= 1e-12
+    assert np.max(np.abs(U - ref)) <= 1e-12 * np.max(np.abs(ref))
