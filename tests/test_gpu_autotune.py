@@ -18,7 +18,7 @@ CASES = [
     (3, (15, 3, 5), 512, 2, 1.0, 1e-3),  # 3D at N = 512 (the wide tile is not used there)
     (2, (61, 9), 256, 3, 0.5, 1e-3),     # CQ: y-march radix 8 / radix 16 / persistent one tile
     (1, (200,), 16, 2, 1.0, 1e-2),       # 1D: Bluestein sine solve / PCR-Thomas, two splits
-    (1, (600,), 64, 4, 0.5, 1e-3),       # the same on a longer line (CQ)
+    (1, (1500,), 64, 4, 0.5, 1e-3),      # the same on a longer line (CQ)
     (1, (255,), 64, 2, 1.0, 1e-3),       # 1D sine-transform solve: rows per workgroup
 ]
 KNOB_VALUES = [(0, 1), (0, 2), (0, 3), (0, 4), (1, 1), (2, 1), (3, 1), (3, 2)]
@@ -41,7 +41,7 @@ def _solve(w, precision, variants=None, autotune=0):
     from paper_2007_13125_amd.binding import Plan
     print(f"[gpu] autotune case {w.name} m={w.m} N={w.N} alpha={w.alpha} {precision} "
           f"variants={variants} autotune={autotune}", flush=True)
-    # the update norm levels off near eps cond(A_h) |U|: ~2e-13 on the 600-point line
+    # the update norm levels off near eps cond(A_h) |U|: ~2e-13 on a 600-point line
     tol = 1e-14 if max(w.m) < 300 else 1e-12
     plan = Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=tol, max_sweeps=40, precision=precision)
     if variants is not None:
