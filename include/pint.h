@@ -289,10 +289,10 @@ pint_status pint_batch_solve(pint_plan *plan, const double *const *v, const doub
 /* Autotuning of the kernels' tile and split choices (the batching row of the
  * method's GPU mapping: FFT radix and tile shapes, PCR/Thomas split).  Four
  * knobs, each 0 = the built-in choice:
- *   [0] forward kernel: BDF-k residual 2D/3D sweeps 0 wide-tile march along
- *       the outer axis, 1 march with the time-FFT tile, 2 one workgroup per
- *       tile, 3 half-width wide-tile march with two workgroups per CU, 4 split
- *       (a residual kernel marching along time, then a time-FFT kernel); CQ
+ *   [0] forward kernel: BDF-k residual 2D/3D sweeps 0 split (a residual
+ *       kernel marching along time, then a time-FFT kernel), 1 march with the
+ *       time-FFT tile, 2 one workgroup per tile, 3 half-width wide-tile march
+ *       with two workgroups per CU, 4 wide-tile march along the outer axis; CQ
  *       sweeps 0 y-march with radix <= 8 transforms, 1 y-march with radix <= 16,
  *       2 (3, 4) persistent one-tile-at-a-time kernel (a choice that does not
  *       apply to the problem falls back to the next one that does; sweeps whose

@@ -950,98 +950,157 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 
 // ---------------------------------------------------------------------------
 // Forward pass in two kernels (BDF-k residual form, 2D/3D).
-// k_resid: each workgroup owns PT x 256 consecutive spectrum slots and marches
-// along time, q = 0..N-1: it reads U at its slots once per row (the time
-// stencil's earlier rows stay in registers; the space neighbours are read
-// where they lie, mostly from cache) and writes the kappa^{q/N}-scaled residual
-// r~_q = kappa^{q/N} (f(t_{q+1}) + corrections + tau^{-1} s_q v
-//                     - tau^{-1} sum_{j<=min(q,k)} w_j U_{q-j} - A_h U_q)
-// to Rb[q][slot] in the spectrum's real type (zero in padding slots).
+// k_resid: each workgroup owns a block of 64 x slots by 4 x 4 grid lines (3D;
+// 16 lines in 2D) and marches along time, q = 0..N-1, writing the kappa^{q/N}-scaled
+// residual
+//   r~_q = kappa^{q/N} (f(t_{q+1}) + corrections + tau^{-1} s_q v
+//                       - tau^{-1} sum_{j<=min(q,k)} w_j U_{q-j} - A_h U_q)
+// to Rb[q][slot] in the spectrum's real type (zero in padding slots).  The
+// time stencil's earlier rows stay in registers.  Row q of the block is staged
+// in LDS with its halo faces, so every space stencil neighbour is an LDS read:
+// the loads per element are U, f (and the correction rows while q < k - 1) plus
+// about one halo value in 3D (0.3 in 2D), instead of one per neighbour (the
+// kernel is bound by the rate at which the texture addresser takes load
+// instructions, and neighbour lines of other workgroups mostly come from HBM).
+// The loads of row q+1 are in flight while row q is combined.  Two LDS buffers
+// alternate by row, so one barrier per row separates each row's writes from its
+// reads.
 // k_tfft: the time FFT of Rb, a tile of W slots x N rows in LDS, stored as the
 // half spectrum.
 constexpr int kResidNT = 256;
-template <typename RT, int PT>
-__global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc) {
-    constexpr int NT = kResidNT;
-    constexpr int TS = NT * PT;
-    const int ntiles = (a.Mp + TS - 1) / TS;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= ntiles) return;
-    // rows [q0, q1) of this workgroup (blockIdx.y-th chunk of qc rows); the
-    // time stencil's earlier rows q0-6..q0-1 are read once more to start it
+constexpr int kBlkX = 64;   // x slots of a block (one wave's lanes)
+// Block of a workgroup: 64 x slots by BY grid lines by BZ planes (BY BZ / 4
+// lines per lane), and the halo values it stages per row: the y and z faces (64
+// values each line) and the x neighbours of its lines.
+// 64 x 4 x 4 in 3D, 64 x 8 in 2D (measured against 64 x 4 x 2, 64 x 8 x 1 and
+// 64 x 16: the 3D shapes tie, the 2D block of 8 lines is 7% faster than 16).
+template <bool IS3> struct ResidBlock {
+    static constexpr int BY = IS3 ? 4 : 8, BZ = IS3 ? 4 : 1;
+    static constexpr int NH = 2 * BZ * kBlkX + (IS3 ? 2 * BY * kBlkX : 0) + 2 * BY * BZ;
+    static constexpr int HPL = (NH + kResidNT - 1) / kResidNT;   // halo values per lane
+    static constexpr int LZ = IS3 ? BZ + 2 : 1;                  // LDS planes (z halo in 3D)
+    static constexpr int LY = BY + 2, LX = kBlkX + 2;
+};
+template <typename RT, bool IS3>
+__global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc, int nxb, int nyb, int nzb) {
+    using BL = ResidBlock<IS3>;
+    constexpr int BY = BL::BY, BZ = BL::BZ, LZ = BL::LZ, LY = BL::LY, LX = BL::LX, PT = BY * BZ / 4;
+    __shared__ double su[2][LZ * LY * LX];   // [buffer][(z + zo) LY + y + 1][x + 1], zo = 1 in 3D
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    if (b >= nxb * nyb * nzb) return;
+    const int xb = b % nxb, rb = b / nxb, yb = rb % nyb, zb = rb / nyb;
     const int q0 = blockIdx.y * qc, q1 = min(a.N, q0 + qc);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int x0 = xb * kBlkX, y0 = yb * BY, z0 = zb * BZ;
+    const int x = x0 + lane;
     const size_t M = a.M;
-    const size_t sy = (size_t)a.mx, sz = (size_t)a.mx * a.my;
     const double diag = 2.0 * (a.ihx2 + a.ihy2 + a.ihz2);
     const auto rU = buf_rsrc(a.U, (size_t)a.N * M * 8);
     const auto rF = buf_rsrc(a.f ? a.f + M : a.U, (size_t)a.N * M * 8);
     const auto rC = buf_rsrc(a.ncorr > 0 ? a.corr : a.U, (size_t)(a.ncorr > 0 ? a.ncorr : 1) * M * 8);
-    const double cf = a.f ? 1.0 : 0.0;
-    unsigned lu[PT], lxm[PT], lxp[PT], lym[PT], lyp[PT], lzm[PT], lzp[PT];
+    constexpr int zo = IS3 ? 1 : 0;
+    auto lidx = [&](int zl, int yl, int xl) { return ((zl + zo) * LY + yl + 1) * LX + xl + 1; };
+    auto gofs = [&](int zz, int yy, int xx) -> unsigned {   // byte offset within a row of U, or kNoLane
+        const bool in = xx >= 0 && xx < a.mx && yy >= 0 && yy < a.my && zz >= 0 && zz < a.mz;
+        return in ? (((unsigned)zz * (unsigned)a.my + (unsigned)yy) * (unsigned)a.mx + (unsigned)xx) * 8u : kNoLane;
+    };
+    // the lane's lines (line l = wv + 4 e of the block: y = l % BY, z = l / BY)
+    unsigned lu[PT];
+    int li[PT];
     double vt[PT], hist[7][PT];
-    bool valid[PT];
-    int slot[PT];
+    bool valid[PT], store[PT];
+    long long slot[PT];
 #pragma unroll
     for (int e = 0; e < PT; ++e) {
-        slot[e] = tile * TS + e * NT + tid;
-        const int d = slot_dof(slot[e], a.mx, a.mxp, a.Mp);
-        valid[e] = d >= 0;
-        const int dd = valid[e] ? d : 0;
-        const int x = dd % a.mx, rr = dd / a.mx, y = rr % a.my, z = rr / a.my;
-        lu[e] = valid[e] ? (unsigned)dd * 8u : kNoLane;
-        lxm[e] = (valid[e] && x > 0) ? lu[e] - 8u : kNoLane;
-        lxp[e] = (valid[e] && x < a.mx - 1) ? lu[e] + 8u : kNoLane;
-        lym[e] = (valid[e] && y > 0) ? lu[e] - 8u * (unsigned)sy : kNoLane;
-        lyp[e] = (valid[e] && y < a.my - 1) ? lu[e] + 8u * (unsigned)sy : kNoLane;
-        lzm[e] = (valid[e] && z > 0) ? lu[e] - 8u * (unsigned)sz : kNoLane;
-        lzp[e] = (valid[e] && z < a.mz - 1) ? lu[e] + 8u * (unsigned)sz : kNoLane;
-        vt[e] = valid[e] ? a.ta * a.v[dd] : 0.0;
+        const int l = wv + 4 * e, yl = l % BY, zl = l / BY;
+        const int y = y0 + yl, z = z0 + zl;
+        lu[e] = gofs(z, y, x);
+        valid[e] = lu[e] != kNoLane;
+        store[e] = x < a.mxp && y < a.my && z < a.mz;
+        li[e] = lidx(zl, yl, lane);
+        slot[e] = ((long long)z * a.my + y) * a.mxp + x;
+        vt[e] = valid[e] ? a.ta * a.v[lu[e] / 8u] : 0.0;
 #pragma unroll
         for (int j = 0; j < 7; ++j) hist[j][e] = 0.0;
+    }
+    // halo values h = tid + 256 i: the y faces (y0 - 1, y0 + BY) of each plane, in 3D
+    // the z faces (z0 - 1, z0 + BZ) of each line, then the x neighbours (x0 - 1,
+    // x0 + 64) of the block's lines
+    unsigned ho[BL::HPL];
+    int hl[BL::HPL];
+#pragma unroll
+    for (int i = 0; i < BL::HPL; ++i) {
+        int h = tid + kResidNT * i;
+        ho[i] = kNoLane;
+        hl[i] = -1;
+        if (h < 2 * BZ * kBlkX) {
+            const int xl = h % kBlkX, r = h / kBlkX, zl = r % BZ, side = r / BZ;
+            const int yl = side ? BY : -1;
+            ho[i] = gofs(z0 + zl, y0 + yl, x0 + xl);
+            hl[i] = lidx(zl, yl, xl);
+            continue;
+        }
+        h -= 2 * BZ * kBlkX;
+        if (IS3 && h < 2 * BY * kBlkX) {
+            const int xl = h % kBlkX, r = h / kBlkX, yl = r % BY, side = r / BY;
+            const int zl = side ? BZ : -1;
+            ho[i] = gofs(z0 + zl, y0 + yl, x0 + xl);
+            hl[i] = lidx(zl, yl, xl);
+            continue;
+        }
+        if (IS3) h -= 2 * BY * kBlkX;
+        if (h < 2 * BY * BZ) {
+            const int l = h % (BY * BZ), side = h / (BY * BZ), yl = l % BY, zl = l / BY;
+            const int xl = side ? kBlkX : -1;
+            ho[i] = gofs(z0 + zl, y0 + yl, x0 + xl);
+            hl[i] = lidx(zl, yl, xl);
+        }
     }
     double wk[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) wk[j] = a.wk[j];
     RT* __restrict__ out = reinterpret_cast<RT*>(a.Rb);
-    // The loads of row q+1 are issued before row q is combined and stored, so
-    // each lane has a whole row's loads in flight while it works.
-    double u[PT], fq[PT], cq[PT], nv[6][PT];
-    auto load_row = [&](int q, double (&uu)[PT], double (&ff)[PT], double (&cc)[PT], double (&nn)[6][PT]) {
+    struct Row {
+        double u[PT], f[PT], c[PT], h[BL::HPL];
+    };
+    auto load_row = [&](int q, Row& r) {
         const unsigned rq = (unsigned)q * (unsigned)M * 8u;   // row offset (the plan bounds N M 8 < 2^32)
         auto off = [&](unsigned l) { return l == kNoLane ? kNoLane : rq + l; };
 #pragma unroll
         for (int e = 0; e < PT; ++e) {
-            uu[e] = buf_ld(rU, off(lu[e]), 0.0);
-            ff[e] = buf_ld(rF, off(lu[e]), 0.0);
-            cc[e] = buf_ld(rC, q < a.ncorr ? off(lu[e]) : kNoLane, 0.0);
-            nn[0][e] = buf_ld(rU, off(lxm[e]), 0.0);
-            nn[1][e] = buf_ld(rU, off(lxp[e]), 0.0);
-            nn[2][e] = buf_ld(rU, off(lym[e]), 0.0);
-            nn[3][e] = buf_ld(rU, off(lyp[e]), 0.0);
-            nn[4][e] = buf_ld(rU, off(lzm[e]), 0.0);
-            nn[5][e] = buf_ld(rU, off(lzp[e]), 0.0);
+            r.u[e] = buf_ld(rU, off(lu[e]), 0.0);
+            r.f[e] = a.f ? buf_ld(rF, off(lu[e]), 0.0) : 0.0;
+            r.c[e] = q < a.ncorr ? buf_ld(rC, off(lu[e]), 0.0) : 0.0;
         }
+#pragma unroll
+        for (int i = 0; i < BL::HPL; ++i) r.h[i] = hl[i] >= 0 ? buf_ld(rU, off(ho[i]), 0.0) : 0.0;
     };
-    auto emit = [&](int q) {
+    constexpr int SY = LX, SZ = LY * LX;   // LDS strides of the y and z neighbours
+    auto emit = [&](int q, const Row& r) {
+        double* S = su[q & 1];
+#pragma unroll
+        for (int e = 0; e < PT; ++e) S[li[e]] = r.u[e];
+#pragma unroll
+        for (int i = 0; i < BL::HPL; ++i)
+            if (hl[i] >= 0) S[hl[i]] = r.h[i];
+        __syncthreads();
         const double sq = a.s[q], sc = a.scale[q];
 #pragma unroll
         for (int e = 0; e < PT; ++e) {
+            const int c = li[e];
 #pragma unroll
             for (int j = 6; j > 0; --j) hist[j][e] = hist[j - 1][e];
-            hist[0][e] = u[e];
+            hist[0][e] = r.u[e];
             double ts = 0.0;
 #pragma unroll
             for (int j = 0; j < 7; ++j) ts += wk[j] * hist[j][e];
-            const double nb = a.ihx2 * (nv[0][e] + nv[1][e]) + a.ihy2 * (nv[2][e] + nv[3][e]) +
-                              a.ihz2 * (nv[4][e] + nv[5][e]);
-            const double r = vt[e] * sq + cf * fq[e] + cq[e] - a.ta * ts - (diag * u[e] - nb);
-            // slots past the last one (the final tile's tail) belong to no row
-            if (slot[e] < a.Mp) out[(size_t)q * a.Mp + slot[e]] = valid[e] ? (RT)(r * sc) : (RT)0;
+            double nb = a.ihx2 * (S[c - 1] + S[c + 1]) + a.ihy2 * (S[c - SY] + S[c + SY]);
+            if (IS3) nb += a.ihz2 * (S[c - SZ] + S[c + SZ]);
+            const double res = vt[e] * sq + r.f[e] + r.c[e] - a.ta * ts - (diag * r.u[e] - nb);
+            if (store[e]) out[(size_t)q * a.Mp + slot[e]] = valid[e] ? (RT)(res * sc) : (RT)0;
         }
     };
-    // history rows q0-6..q0-1 (absent rows stay zero); hist[j] holds U_{q0-1-j+1}
-    // after the loop, i.e. the row before q0 in hist[0]
+    // history rows q0-6..q0-1 (absent rows stay zero); hist[0] holds the row before q0
 #pragma unroll
     for (int j = 6; j >= 1; --j) {
         const int qh = q0 - j;
@@ -1055,21 +1114,14 @@ __global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc) {
             }
         }
     }
-    load_row(q0, u, fq, cq, nv);
+    Row cur, nxt;
+    load_row(q0, cur);
     for (int q = q0; q + 1 < q1; ++q) {
-        double u2[PT], f2[PT], c2[PT], n2[6][PT];
-        load_row(q + 1, u2, f2, c2, n2);
-        emit(q);
-#pragma unroll
-        for (int e = 0; e < PT; ++e) {
-            u[e] = u2[e];
-            fq[e] = f2[e];
-            cq[e] = c2[e];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) nv[j][e] = n2[j][e];
-        }
+        load_row(q + 1, nxt);
+        emit(q, cur);
+        cur = nxt;
     }
-    emit(q1 - 1);
+    emit(q1 - 1, cur);
 }
 
 template <typename R, int LOGN, int W, int NT>
@@ -1104,12 +1156,17 @@ __global__ __launch_bounds__(NT) void k_tfft(FwdArgs a) {
 
 template <typename R, int LOGN>
 hipError_t fwd_split(const FwdArgs& a, int* nb, hipStream_t st) {
-    constexpr int PT = 2;
-    constexpr int TS = kResidNT * PT;
-    const int nres = ((a.Mp + TS - 1) / TS + 7) / 8 * 8;
+    const bool is3 = a.mz > 1;
+    const int by = is3 ? ResidBlock<true>::BY : ResidBlock<false>::BY;
+    const int bz = is3 ? ResidBlock<true>::BZ : ResidBlock<false>::BZ;
+    const int nxb = (a.mxp + kBlkX - 1) / kBlkX, nyb = (a.my + by - 1) / by, nzb = (a.mz + bz - 1) / bz;
+    const int nres = (nxb * nyb * nzb + 7) / 8 * 8;
     constexpr int QC = 32;   // time rows per workgroup (6 history rows re-read per chunk)
     const int nq = (a.N + QC - 1) / QC;
-    PINT_LAUNCH((k_resid<R, PT>), dim3(nres, nq), dim3(kResidNT), 0, st, a, QC);
+    if (is3)
+        PINT_LAUNCH((k_resid<R, true>), dim3(nres, nq), dim3(kResidNT), 0, st, a, QC, nxb, nyb, nzb);
+    else
+        PINT_LAUNCH((k_resid<R, false>), dim3(nres, nq), dim3(kResidNT), 0, st, a, QC, nxb, nyb, nzb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // 128-byte row segments where the N x W tile fits 64 KB of LDS
@@ -1161,9 +1218,9 @@ hipError_t fwd_march(const FwdArgs& a, int* nb, hipStream_t st) {
 }
 
 // Which forward kernel a variant launches for this problem:
-//   BDF-k: 0 wide-tile march (kind 0 in 2D, 3 in 3D), 1 march with the
-//   time-FFT tile, 2 one workgroup per tile, 3 half-width wide-tile march with
-//   two workgroups per CU (kind 4);
+//   BDF-k: 0 split residual + time FFT (kind 5), 4 wide-tile march (kind 0 in
+//   2D, 3 in 3D), 1 march with the time-FFT tile, 2 one workgroup per tile,
+//   3 half-width wide-tile march with two workgroups per CU (kind 4);
 //   CQ: 0 y-march (radix <= 8), 1 y-march (radix <= 16), 2 persistent one-tile kernel.
 // A variant whose kernel does not apply falls back to the next one that does.
 template <typename R, int LOGN>
@@ -1181,7 +1238,7 @@ int fwd_kind(const FwdArgs& a, bool cq) {
     }
     if (a.form != 0 || a.my == 1 || var == 2) return 2;
     // split residual + time FFT (needs the slot-layout buffer and 32-bit row offsets)
-    if (var == 4 && a.Rb && (long long)a.N * a.M * 8 < (long long)kNoLane) return 5;
+    if (var == 0 && a.Rb && (long long)a.N * a.M * 8 < (long long)kNoLane) return 5;
     constexpr int W = fwd_tile(LOGN);
     constexpr int NT = (N_OF(LOGN) * W >= kNT) ? kNT : 64;
     constexpr int NTM = (N_OF(LOGN) * W >= PINT_MARCH_NT) ? PINT_MARCH_NT : NT;
@@ -1193,7 +1250,7 @@ int fwd_kind(const FwdArgs& a, bool cq) {
     // for the y-neighbour loads without spilling)
     const bool wide_ok = WIDE_OK && (a.mz == 1 || LOGN <= 8) && WW <= a.mxp &&
                          (long long)(NTW / WW + 2) * a.M * 8 < (1LL << 32);
-    if (var == 0 && wide_ok) return a.mz == 1 ? 0 : 3;
+    if ((var == 0 || var == 4) && wide_ok) return a.mz == 1 ? 0 : 3;
     // half-width wide tiles, two workgroups per CU
     if (var == 3 && WIDE_OK && (a.mz == 1 || LOGN <= 8) && N_OF(LOGN) * 8 >= 2 * 256 && 8 <= a.mxp &&
         (256 / 8 + 2) * (long long)a.M * 8 < (1LL << 32))

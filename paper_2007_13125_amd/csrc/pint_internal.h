@@ -151,11 +151,12 @@ struct SpaceArgs {
 };
 
 // Kernel variants the autotuner chooses between (index 0 is the built-in choice).
-//   forward, BDF-k residual 2D/3D: 0 wide-tile march along the outer axis when
-//     eligible (else 1), 1 march with the time-FFT tile, 2 one workgroup per tile,
-//     3 half-width wide-tile march, two workgroups per CU (N in 64..512);
-//     4 split: a residual kernel that marches along time (one pass over U, the
-//     time stencil in registers) into a slot-layout buffer, then a time-FFT kernel;
+//   forward, BDF-k residual 2D/3D: 0 split: a residual kernel that marches along
+//     time (one pass over U, the time stencil in registers) into a slot-layout
+//     buffer, then a time-FFT kernel (else as 4); 1 march with the time-FFT tile,
+//     2 one workgroup per tile, 3 half-width wide-tile march, two workgroups per
+//     CU (N in 64..512), 4 wide-tile march along the outer axis when eligible
+//     (else 1);
 //   forward, CQ: 0 y-march with radix <= 8 transforms when eligible (else 2),
 //     1 y-march with radix <= 16, 2 persistent one-tile-at-a-time kernel.
 constexpr int kFwdVariants = 5;
