@@ -951,7 +951,7 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 // ---------------------------------------------------------------------------
 // Forward pass in two kernels (BDF-k residual form, 2D/3D).
 // k_resid: each workgroup owns a block of 64 x slots by 4 x 4 grid lines (3D;
-// 16 lines in 2D) and marches along time, q = 0..N-1, writing the kappa^{q/N}-scaled
+// 64 x 8 lines in 2D) and marches along time, q = 0..N-1, writing the kappa^{q/N}-scaled
 // residual
 //   r~_q = kappa^{q/N} (f(t_{q+1}) + corrections + tau^{-1} s_q v
 //                       - tau^{-1} sum_{j<=min(q,k)} w_j U_{q-j} - A_h U_q)
@@ -981,14 +981,33 @@ template <bool IS3> struct ResidBlock {
     static constexpr int LZ = IS3 ? BZ + 2 : 1;                  // LDS planes (z halo in 3D)
     static constexpr int LY = BY + 2, LX = kBlkX + 2;
 };
+// 3D block order: regions of nxb x kRegY x kRegZ blocks (whole x rows, 8 y by 4 z
+// blocks: about the workgroups an XCD holds at once) one after another, so the
+// y and z halo faces of most blocks are rows that co-resident workgroups of the
+// same XCD load, and come from its L2.
+constexpr int kRegY = 8, kRegZ = 4;
 template <typename RT, bool IS3>
 __global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc, int nxb, int nyb, int nzb) {
     using BL = ResidBlock<IS3>;
     constexpr int BY = BL::BY, BZ = BL::BZ, LZ = BL::LZ, LY = BL::LY, LX = BL::LX, PT = BY * BZ / 4;
     __shared__ double su[2][LZ * LY * LX];   // [buffer][(z + zo) LY + y + 1][x + 1], zo = 1 in 3D
     const int b = xcd_tile(blockIdx.x, gridDim.x);
-    if (b >= nxb * nyb * nzb) return;
-    const int xb = b % nxb, rb = b / nxb, yb = rb % nyb, zb = rb / nyb;
+    int xb, yb, zb;
+    if (IS3) {
+        // b runs over whole regions (the host rounds nyb, nzb up to them)
+        const int per = nxb * kRegY * kRegZ, nry = (nyb + kRegY - 1) / kRegY;
+        const int r = b / per, w = b % per;
+        xb = w % nxb;
+        yb = (r % nry) * kRegY + (w / nxb) % kRegY;
+        zb = (r / nry) * kRegZ + w / (nxb * kRegY);
+        if (yb >= nyb || zb >= nzb) return;
+    } else {
+        if (b >= nxb * nyb * nzb) return;
+        xb = b % nxb;
+        const int rb = b / nxb;
+        yb = rb % nyb;
+        zb = rb / nyb;
+    }
     const int q0 = blockIdx.y * qc, q1 = min(a.N, q0 + qc);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int x0 = xb * kBlkX, y0 = yb * BY, z0 = zb * BZ;
@@ -1160,13 +1179,18 @@ hipError_t fwd_split(const FwdArgs& a, int* nb, hipStream_t st) {
     const int by = is3 ? ResidBlock<true>::BY : ResidBlock<false>::BY;
     const int bz = is3 ? ResidBlock<true>::BZ : ResidBlock<false>::BZ;
     const int nxb = (a.mxp + kBlkX - 1) / kBlkX, nyb = (a.my + by - 1) / by, nzb = (a.mz + bz - 1) / bz;
-    const int nres = (nxb * nyb * nzb + 7) / 8 * 8;
-    constexpr int QC = 32;   // time rows per workgroup (6 history rows re-read per chunk)
-    const int nq = (a.N + QC - 1) / QC;
+    const int nblk = nxb * nyb * nzb;
+    const int nvirt = is3 ? nxb * ((nyb + kRegY - 1) / kRegY * kRegY) * ((nzb + kRegZ - 1) / kRegZ * kRegZ) : nblk;
+    const int nres = (nvirt + 7) / 8 * 8;
+    // time rows per workgroup: each chunk re-reads the k history rows before it,
+    // so the longest chunk (up to 128) that still leaves >= 2048 workgroups
+    int qc = 32;
+    while (qc < 128 && (long long)nblk * ((a.N + 2 * qc - 1) / (2 * qc)) >= 2048) qc *= 2;
+    const int nq = (a.N + qc - 1) / qc;
     if (is3)
-        PINT_LAUNCH((k_resid<R, true>), dim3(nres, nq), dim3(kResidNT), 0, st, a, QC, nxb, nyb, nzb);
+        PINT_LAUNCH((k_resid<R, true>), dim3(nres, nq), dim3(kResidNT), 0, st, a, qc, nxb, nyb, nzb);
     else
-        PINT_LAUNCH((k_resid<R, false>), dim3(nres, nq), dim3(kResidNT), 0, st, a, QC, nxb, nyb, nzb);
+        PINT_LAUNCH((k_resid<R, false>), dim3(nres, nq), dim3(kResidNT), 0, st, a, qc, nxb, nyb, nzb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // 128-byte row segments where the N x W tile fits 64 KB of LDS
