@@ -562,36 +562,63 @@ __global__ __launch_bounds__(NT, TAB ? 1 : 2) void k_fwd_wide(FwdArgs a, int nco
 //   H_p = Sg_p + sum_{n=1..k} kappa^{(n-1)/N} c_n e^{-2 pi i (n-1) p/N},
 //   c_n = kappa tau^{-1} sum_{j=n..k} w_j U^{N+n-j},
 // which replaces the forward kernel of a direct sweep (no FFT, U read only in
-// its last k rows).  One lane per spectrum slot and a chunk of frequencies.
+// its last k rows).  One lane per spectrum slot and a chunk of frequencies,
+// read in batches of 8 so that a lane keeps 8 loads in flight (the next batch
+// is issued before the current one is combined and stored).
+constexpr int kInjectBatch = 8;
 template <typename R>
 __global__ __launch_bounds__(256) void k_inject(FwdArgs a, const void* Sg, int pchunk) {
     using T = cx<R>;
+    constexpr int PB = kInjectBatch;
     const int P0 = blockIdx.y * pchunk, P1 = min(a.N / 2 + 1, P0 + pchunk);
     const int slot = blockIdx.x * 256 + threadIdx.x;
     if (slot >= a.Mp) return;
     const int d = slot_dof(slot, a.mx, a.mxp, a.Mp);
+    // the last k rows of U, then c_n = kappa tau^{-1} kappa^{(n-1)/N} sum_{j=n..k} w_j U^{N+n-j}
+    double ul[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ul[i] = (d >= 0 && i < a.k) ? a.U[(size_t)(a.N - 1 - i) * a.M + d] : 0.0;
     double c[6];
 #pragma unroll
     for (int n = 1; n <= 6; ++n) {
         double acc = 0.0;
-        if (d >= 0 && n <= a.k)
-            for (int j = n; j <= a.k; ++j) acc += a.wk[j] * a.U[(size_t)(a.N + n - j - 1) * a.M + d];
+#pragma unroll
+        for (int j = n; j <= 6; ++j)
+            if (j <= a.k) acc += a.wk[j] * ul[j - n];   // U^{N+n-j} is row N+n-j-1 = N-1-(j-n)
         c[n - 1] = n <= a.k ? a.kappa * a.ta * acc * a.scale[n - 1] : 0.0;
     }
     const T* src = reinterpret_cast<const T*>(Sg);
     T* dst = reinterpret_cast<T*>(a.S);
     const T* tw = reinterpret_cast<const T*>(a.tw);
-    for (int p = P0; p < P1; ++p) {
-        const T g = src[(size_t)p * a.ldS + slot];
-        double hr = (double)g.x, hi = (double)g.y;
+    const unsigned so = (unsigned)slot * (unsigned)sizeof(T);   // within one frequency row
+    auto load = [&](int p0, T (&g)[PB]) {
 #pragma unroll
-        for (int n = 1; n <= 6; ++n) {
-            if (n > a.k) break;
-            const T w = tw[((n - 1) * p) & (a.N - 1)];
-            hr += c[n - 1] * (double)w.x;
-            hi += c[n - 1] * (double)w.y;
+        for (int i = 0; i < PB; ++i) {
+            const int p = p0 + i;   // a row of its own (the spectrum may exceed 4 GB)
+            const auto rs = buf_rsrc(src + (size_t)min(p, P1 - 1) * a.ldS, (size_t)a.ldS * sizeof(T));
+            g[i] = buf_ld(rs, p < P1 ? so : kNoLane, mk<T>(0, 0));
         }
-        dst[(size_t)p * a.ldS + slot] = mk<T>((R)hr, (R)hi);
+    };
+    T g[PB], gn[PB];
+    load(P0, g);
+    for (int p0 = P0; p0 < P1; p0 += PB) {
+        if (p0 + PB < P1) load(p0 + PB, gn);
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int p = p0 + i;
+            if (p >= P1) break;
+            double hr = (double)g[i].x, hi = (double)g[i].y;
+#pragma unroll
+            for (int n = 1; n <= 6; ++n) {
+                if (n > a.k) break;
+                const T w = tw[((n - 1) * p) & (a.N - 1)];
+                hr += c[n - 1] * (double)w.x;
+                hi += c[n - 1] * (double)w.y;
+            }
+            dst[(size_t)p * a.ldS + slot] = mk<T>((R)hr, (R)hi);
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) g[i] = gn[i];
     }
 }
 
@@ -1367,7 +1394,7 @@ hipError_t launch_forward(const FwdArgs& a, bool mixed, bool cq, int* nb, hipStr
 }
 
 hipError_t launch_inject(const FwdArgs& a, const void* Sg, bool mixed, hipStream_t st) {
-    const int pchunk = 16;
+    const int pchunk = 4 * kInjectBatch;
     const dim3 grid((unsigned)((a.Mp + 255) / 256), (unsigned)((a.N / 2 + 1 + pchunk - 1) / pchunk));
     if (mixed)
         PINT_LAUNCH(k_inject<float>, grid, dim3(256), 0, st, a, Sg, pchunk);
