@@ -1146,11 +1146,12 @@ __global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc, int nxb, 
             if (store[e]) out[(size_t)q * a.Mp + slot[e]] = valid[e] ? (RT)(res * sc) : (RT)0;
         }
     };
-    // history rows q0-6..q0-1 (absent rows stay zero); hist[0] holds the row before q0
+    // history rows q0-k..q0-1 (absent rows, and lags beyond k whose weights are
+    // zero, stay zero); hist[0] holds the row before q0
 #pragma unroll
     for (int j = 6; j >= 1; --j) {
         const int qh = q0 - j;
-        if (qh >= 0) {
+        if (qh >= 0 && j <= a.k) {
             const unsigned rq = (unsigned)qh * (unsigned)M * 8u;
 #pragma unroll
             for (int e = 0; e < PT; ++e) {
@@ -1209,7 +1210,7 @@ hipError_t fwd_split(const FwdArgs& a, int* nb, hipStream_t st) {
     const int nblk = nxb * nyb * nzb;
     const int nvirt = is3 ? nxb * ((nyb + kRegY - 1) / kRegY * kRegY) * ((nzb + kRegZ - 1) / kRegZ * kRegZ) : nblk;
     const int nres = (nvirt + 7) / 8 * 8;
-    // time rows per workgroup: each chunk re-reads the k history rows before it,
+    // time rows per workgroup: each chunk re-reads the k rows before it,
     // so the longest chunk (up to 128) that still leaves >= 2048 workgroups
     int qc = 32;
     while (qc < 128 && (long long)nblk * ((a.N + 2 * qc - 1) / (2 * qc)) >= 2048) qc *= 2;
