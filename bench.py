@@ -364,6 +364,78 @@ def bench_batch(count=256):
 # CPU leg: the FP64 oracle (test infrastructure) timed on a bounded sample of the
 # headline workload, and the oracle's values that time-to-tolerance is measured against
 
+def wall_ms(fn, reps=3):
+    """Median wall-clock time (ms) of fn() over reps runs after one warm-up run,
+    each bracketed by device synchronisation (the solves run their host stop
+    tests, so wall time is what a caller sees); returns (ms, last result)."""
+    import torch
+    out = fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return sorted(ts)[len(ts) // 2], out
+
+
+def bench_next():
+    """The rows beyond the single linear sweep, each at the paper's size and at a
+    larger one: Algorithm 3 (Allen-Cahn, Sec. 4 Example 4), P1 elements (Example 1's
+    problem with the paper's elements, against the same problem with finite
+    differences) and windowed solves (2D heat in 4 windows against one solve)."""
+    import torch
+    from paper_2007_13125_amd import binding as B
+    from paper_2007_13125_amd import workloads as wl
+    out = {}
+    rows = []
+    for M, N in ((999, 100), (2047, 1024)):
+        w, c3, c1 = wl.example4(2, 0.75, M=M, N=N)
+        plan = B.Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-12, max_sweeps=40)
+        U = torch.empty((w.N, w.M), dtype=torch.float64, device="cuda")
+        v, f, fd = to_dev(w.v), to_dev(w.f), to_dev(w.fder)
+        ms, (st, inner, upd) = wall_ms(lambda: B.pint_nonlinear_solve(plan.h, c3, c1, v, f, fd, U, 3))
+        plan.close()
+        rows.append({"problem": f"Allen-Cahn, eps=1, kappa=0.1, T=0.4, m={M}, N={N}, BDF2, alpha=0.75, 3 Newton steps",
+                     "status": st, "ms": ms, "inner_sweeps": inner,
+                     "unknown_updates_per_s": w.N * w.M * sum(inner) / (ms * 1e-3)})
+    out["algorithm3"] = rows
+    rows = []
+    for label, wf, wd in (("Example 1 (Table 2's problem), m=999, N=100, BDF6", wl.example1_fem(6), wl.example1(6)),
+                          ("1D heat line m=2047, N=2048, BDF2",
+                           wl.fem1d(m=2047, N=2048, k=2), wl.heat1d(seed=61, m=2047, N=2048, k=2))):
+        rec = {"problem": label}
+        for space, w in (("fem", wf), ("fd", wd)):
+            plan = B.Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-12, max_sweeps=40, space=space)
+            U = torch.empty((w.N, w.M), dtype=torch.float64, device="cuda")
+            v, f, fd = to_dev(w.v), to_dev(w.f), to_dev(w.fder)
+            ms, (_, info) = wall_ms(lambda: plan.solve(v, f, fd, U))
+            plan.close()
+            rec[space] = {"ms_to_1e-12": ms, "sweeps": info["sweeps"], "status": info["status"]}
+        rows.append(rec)
+    out["fem_p1"] = rows
+    w = wl.heat2d(k=2)
+    nwin = 4
+    v, f = to_dev(w.v), to_dev(w.f)
+    plan = B.Plan(w.m, w.k, w.alpha, w.T / nwin, w.N // nwin, w.kappa, tol=1e-12, max_sweeps=40)
+    U = torch.empty((w.N, w.M), dtype=torch.float64, device="cuda")
+    ms_w, (st, _, sw) = wall_ms(lambda: B.pint_solve_windows(plan.h, nwin, v, f, None, U, 40))
+    ws_w = B.pint_plan_workspace_bytes(plan.h)
+    plan.close()
+    plan = B.Plan(w.m, w.k, w.alpha, w.T, w.N, w.kappa, tol=1e-12, max_sweeps=40)
+    ms_1, (_, info) = wall_ms(lambda: plan.solve(v, f, None, U))
+    ws_1 = B.pint_plan_workspace_bytes(plan.h)
+    plan.close()
+    out["windows"] = {"problem": "2D heat 255^2, N=512, BDF2, kappa=1e-5, tol 1e-12: 4 windows of 128 steps "
+                                 "against one solve of 512",
+                      "windows": {"ms": ms_w, "sweeps_per_window": sw, "status": st, "workspace_bytes": ws_w},
+                      "one_solve": {"ms": ms_1, "sweeps": info["sweeps"], "workspace_bytes": ws_1}}
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -645,6 +717,8 @@ def main():
     if not args.only:
         print("[bench] batch", file=sys.stderr, flush=True)
         res["workloads"]["batch"] = bench_batch()
+        print("[bench] algorithm 3, P1 elements, windows", file=sys.stderr, flush=True)
+        res["workloads"]["next_rows"] = bench_next()
     res["variant_knobs"] = ["forward kernel", "x pass rows", "y/z pass columns", "1D solver"]
     print(json.dumps(res), flush=True)
     if args.copy_calibration:

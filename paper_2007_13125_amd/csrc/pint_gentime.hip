@@ -303,12 +303,13 @@ __device__ __forceinline__ void gn_dft_body(const GenArgs& a, int g0, int gstrid
     }
 }
 
-template <typename R, int LOGP, int B, bool INV>
+template <typename R, int LOGP, int B, bool INV, bool BLUE>
 __global__ __launch_bounds__(kGenNT) void k_gn_dft(GenArgs a) {
     __shared__ cx<R> sm[(1 << LOGP) * B];
     __shared__ double red[2][kGenNT / 64];
     double mx = 0.0, s2 = 0.0;
-    gn_dft_body<R, LOGP, B, INV>(a, blockIdx.x, gridDim.x, sm, red, mx, s2);
+    gn_dft_body<R, LOGP, B, INV, BLUE>(a, blockIdx.x, gridDim.x, sm, red, mx, s2,
+                                       reinterpret_cast<const cx<R>*>(a.twN));
     if (INV && threadIdx.x == 0) {
         a.partial[2 * blockIdx.x] = mx;
         a.partial[2 * blockIdx.x + 1] = s2;
@@ -321,21 +322,35 @@ template <typename R, int LOGP> constexpr int gn_slots() {
     return b > 16 ? 16 : (b < 1 ? 1 : b);
 }
 
-template <typename R, int LOGP, bool INV>
+// LOGP: log2 of the transform length (Bluestein's P, or N itself when !BLUE).
+template <typename R, int LOGP, bool INV, bool BLUE = true>
 hipError_t gn_dft_one(const GenArgs& a, int* nb, hipStream_t st) {
     constexpr int B = gn_slots<R, LOGP>();
-    const void* fn = reinterpret_cast<const void*>(&k_gn_dft<R, LOGP, B, INV>);
+    const void* fn = reinterpret_cast<const void*>(&k_gn_dft<R, LOGP, B, INV, BLUE>);
     const long long ntiles = ((long long)a.Mp + B - 1) / B;
     long long grid = std::min<long long>(ntiles, persistent_blocks(fn, kGenNT));
     if (INV) grid = std::min<long long>(grid, a.max_partials);
     if (grid < 1) grid = 1;
-    PINT_LAUNCH((k_gn_dft<R, LOGP, B, INV>), dim3((unsigned)grid), dim3(kGenNT), 0, st, a);
+    PINT_LAUNCH((k_gn_dft<R, LOGP, B, INV, BLUE>), dim3((unsigned)grid), dim3(kGenNT), 0, st, a);
     if (nb) *nb = (int)grid;
     return hipGetLastError();
 }
 
 template <typename R, bool INV>
 hipError_t gn_dft_dispatch(const GenArgs& a, int* nb, hipStream_t st) {
+    if (a.pow2) {
+        switch (a.logP - 1) {   // N = P/2
+            case 4: return gn_dft_one<R, 4, INV, false>(a, nb, st);
+            case 5: return gn_dft_one<R, 5, INV, false>(a, nb, st);
+            case 6: return gn_dft_one<R, 6, INV, false>(a, nb, st);
+            case 7: return gn_dft_one<R, 7, INV, false>(a, nb, st);
+            case 8: return gn_dft_one<R, 8, INV, false>(a, nb, st);
+            case 9: return gn_dft_one<R, 9, INV, false>(a, nb, st);
+            case 10: return gn_dft_one<R, 10, INV, false>(a, nb, st);
+            case 11: return gn_dft_one<R, 11, INV, false>(a, nb, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (a.logP) {
         case 2: return gn_dft_one<R, 2, INV>(a, nb, st);
         case 3: return gn_dft_one<R, 3, INV>(a, nb, st);

@@ -512,8 +512,7 @@ pint_status build_plan(pint_plan* P, const pint_grid* g, const pint_params* p, h
             if ((rc = upload(P, &P->d_mass, mt.data(), m)) != PINT_OK) return rc;
         }
         const long long L = 2LL * (m + 1);
-        // (P1 elements: the sine solve with the mass divide is the Bluestein pass)
-        if (is_pow2(L) && L <= (1LL << pint::kMaxLogL) && (g->dim == 1 || L >= 8) && !P->fem) {
+        if (is_pow2(L) && L <= (1LL << pint::kMaxLogL) && (g->dim == 1 || L >= 8)) {
             if ((rc = upload_tw(P, &P->d_twL[i], L, P->mixed)) != PINT_OK) return rc;
         } else {
             if ((rc = upload_bluestein(P, i, m)) != PINT_OK) return rc;
@@ -720,6 +719,8 @@ GenArgs gen_args(const pint_plan* P, double* U) {
     ga.ncorr = P->p.k > 1 ? P->p.k - 1 : 0;
     ga.an = P->d_an;
     ga.fem = P->fem ? 1 : 0;
+    ga.pow2 = batch_pow2(P) ? 1 : 0;
+    ga.twN = P->d_twN;
     if (ga.form == 0) {
         ga.wh = P->d_whT;
         ga.twh = P->d_twhT;

@@ -97,6 +97,10 @@ struct GenArgs {
     // 1D P1 elements: the scaled mass matrix tridiag(1, 4, 1)/6 multiplies the
     // time-derivative terms (history sums and the s_n v term)
     int fem;
+    // N a power of two >= 16 (then P = 2N): the time DFTs are plain length-N
+    // FFTs with the twiddles twN = e^{-2 pi i j/N} (spectrum precision)
+    int pow2;
+    const void* twN;
 };
 
 // One 1D problem of a batched sweep (every pass one launch over all active

@@ -111,7 +111,8 @@ __global__ __launch_bounds__(NT) void k_tri1d(SpaceArgs a) {
 // workgroup, layout [ROWS][L] in LDS.  Applying it twice multiplies by
 // -2(m+1), which the divide pass folds in.
 // With SOLVE (1D problems), the transformed row of frequency p is divided by
-// (sigma_p + mu_x) times the raw-transform factor and transformed back.
+// (sigma_p + mu_x) times the raw-transform factor (sigma_p mass_x + mu_x for P1
+// elements) and transformed back.
 template <typename R, int LOGL, int ROWS, int NT, bool SOLVE>
 __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) {
     using T = cx<R>;
@@ -211,9 +212,11 @@ __global__ __launch_bounds__(NT) void k_dst_rows(SpaceArgs a, long long nlines) 
                     continue;
                 }
                 const double2 sg = a.sigma[(unsigned)g / (unsigned)lpp];
-                const double dre = sg.x + a.mu[0][t - 1];
-                const double inv = a.inv_factor / (dre * dre + sg.y * sg.y);
-                const T c = mk<T>((R)(dre * inv), (R)(-sg.y * inv));
+                // P1 elements (1D): sigma_p mass_t + mu_t
+                const double mm = a.mass ? a.mass[t - 1] : 1.0;
+                const double dre = sg.x * mm + a.mu[0][t - 1], dim = sg.y * mm;
+                const double inv = a.inv_factor / (dre * dre + dim * dim);
+                const T c = mk<T>((R)(dre * inv), (R)(-dim * inv));
                 const T z = cmul(sm[ix(b, t)], c);
                 sm[ix(b, t)] = z;
                 sm[ix(b, L - t)] = mk<T>(-z.x, -z.y);
@@ -1040,11 +1043,11 @@ hipError_t cols_dispatch(const SpaceArgs& a, int axis, hipStream_t st) {
 //   3D: DST-x, DST-y, DST-z + divide + inverse, DST-y, DST-x.
 int pass_count(const SpaceArgs& a) { return a.dim == 1 ? 1 : (a.dim == 2 ? 3 : 5); }
 
-// 1D: the power-of-two sine solve (P1 elements, whose divide carries the mass
-// eigenvalues, take the Bluestein pass whatever the length).
+// 1D: the power-of-two sine solve (for P1 elements its divide carries the mass
+// eigenvalues).
 bool dst1d(const SpaceArgs& a) {
     const unsigned L = 2u * (unsigned)(a.mx + 1);
-    return (L & (L - 1)) == 0 && L <= (1u << kMaxLogL) && !a.mass;
+    return (L & (L - 1)) == 0 && L <= (1u << kMaxLogL);
 }
 
 bool tri1d(const SpaceArgs& a) {

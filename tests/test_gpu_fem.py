@@ -20,7 +20,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # (m, N, k, alpha, kappa)
 CASES = [
     (7, 16, 2, 1.0, 1e-2),
-    (63, 64, 3, 1.0, 1e-3),      # sine length 128 (a power of two; P1 takes the Bluestein pass)
+    (63, 64, 3, 1.0, 1e-3),      # sine length 128 (the power-of-two sine solve with the mass divide)
     (100, 32, 4, 0.5, 1e-3),
     (255, 100, 6, 1.0, 1e-3),    # time axis of 100 levels
     (40, 6, 5, 1.0, 0.1),
