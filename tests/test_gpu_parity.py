@@ -151,6 +151,35 @@ def test_each_sweep_matches_dense_dft_sweep(dim, m, N, k, alpha, kappa, form, in
         assert abs(norms[s - 1, 0] - upd) <= bound * max(upd, np.max(np.abs(ref[s]))) + 1e-300
 
 
+@pytest.mark.parametrize("dim,m,N,k,alpha,kappa", [c for c in SMALL if np.prod(c[1]) * c[2] <= 70000])
+def test_mixed_sweeps_track_dense_dft_sweep(dim, m, N, k, alpha, kappa):
+    # Mixed precision, sweeps 1..3 against the FP64 Algorithm 1/2 iterates.  Sweep s
+    # adds the FP32 rounding of its own transforms and solves (depth D = log2 N plus
+    # log2 2(m_i + 1) per axis, relative to the transformed residual and amplified by
+    # up to 1/kappa by the unscaling, so bounded by c eps32 D / kappa |Delta_s|, Delta_s
+    # the sweep's update) to the error of sweep s-1 carried through the sweep's
+    # contraction (at most kappa/(1 - kappa), or the iterates' own ratio |Delta_s| /
+    # |Delta_{s-1}|), plus the FP64 terms of the FP64 bar.  The residual itself is
+    # FP64: formed in FP32 its rounding (eps32 |A_h U|) would not contract with Delta_s.
+    w = _case(dim, m, N, k, alpha, kappa)
+    got, _ = gpu_iterates(w, 3, precision="mixed")
+    ref = oracle_iterates(w, 3)
+    e32 = float(np.finfo(np.float32).eps)
+    depth = np.log2(N) + sum(np.log2(2 * (mi + 1)) for mi in m)
+    mu = [(4.0 * (mi + 1) ** 2) * np.sin(np.pi * np.array([1, mi]) / (2.0 * (mi + 1))) ** 2 for mi in m]
+    cond = sum(x[1] for x in mu) / sum(x[0] for x in mu)
+    bound, prev = 0.0, None
+    for s in range(1, 4):
+        delta = np.max(np.abs(ref[s] - ref[s - 1]))
+        rho = 1.0 if prev is None else 10 * max(kappa / (1 - kappa), delta / max(prev, 1e-300))
+        f64 = max(1e-12, 10 * EPS * np.log2(N) / kappa, EPS * cond) * np.max(np.abs(ref[s]))
+        bound = rho * bound + 10 * e32 * depth / kappa * delta + f64
+        err = np.max(np.abs(got[s] - ref[s]))
+        print(f"mixed sweep {s}: max error {err:.3g}, bound {bound:.3g}, |Delta| {delta:.3g}", flush=True)
+        assert err <= bound, (s, err, bound)
+        prev = delta
+
+
 def test_heat1d_workload_full():
     # the 1D heat workload (m = 63, N = 64, BDF2, kappa = 1e-3) to the stated tolerance 1e-12
     w = wl.heat1d()
