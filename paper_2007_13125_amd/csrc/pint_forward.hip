@@ -1366,6 +1366,19 @@ hipError_t fwd_one(const FwdArgs& a, bool cq, int* nb, hipStream_t st) {
     if (kind == 1) return fwd_march<R, LOGN, W, NTM, false>(a, nb, st);
     if (kind == 5) return fwd_split<R, LOGN>(a, nb, st);
     const int ntiles = (a.Mp + W - 1) / W;
+    if constexpr (W >= 16) {
+        // small grids (fewer tiles than a tenth of the CUs' worth): tiles of W/8 slots,
+        // so the work spreads over 8 times as many workgroups (each one's chain of
+        // loads, barriers and FFT stages is what a launch this small waits for)
+        constexpr int WS = W / 8;
+        constexpr int NTS = N_OF(LOGN) * WS >= kNT ? kNT : 64;
+        if (ntiles < 32) {
+            const int grid = (((a.Mp + WS - 1) / WS + 7) / 8) * 8;
+            if (nb) *nb = grid;
+            PINT_LAUNCH((k_fwd_heat<R, LOGN, WS, NTS>), dim3(grid), dim3(NTS), 0, st, a);
+            return hipGetLastError();
+        }
+    }
     const int grid = ((ntiles + 7) / 8) * 8;
     if (nb) *nb = grid;
     PINT_LAUNCH((k_fwd_heat<R, LOGN, W, NT>), dim3(grid), dim3(NT), 0, st, a);

@@ -212,6 +212,18 @@ template <typename R, int LOGN>
 hipError_t inv_one(const InvArgs& a, int* nb, hipStream_t st) {
     constexpr int W = time_tile<R>(LOGN);
     const int ntiles = (a.Mp + W - 1) / W;
+    if constexpr (W >= 8) {
+        // small grids: tiles of W/4 slots (4 times as many workgroups)
+        constexpr int WS = W / 4;
+        constexpr int E = N_OF(LOGN) * WS;
+        constexpr int NTS = E >= PINT_INV_NT ? PINT_INV_NT : (E >= kNT ? kNT : 64);
+        if (ntiles < 32) {
+            const int grid = (((a.Mp + WS - 1) / WS + 7) / 8) * 8;
+            if (nb) *nb = grid;
+            PINT_LAUNCH((k_inv<R, LOGN, WS, NTS>), dim3(grid), dim3(NTS), 0, st, a);
+            return hipGetLastError();
+        }
+    }
     const int grid = ((ntiles + 7) / 8) * 8;
     if (nb) *nb = grid;
     constexpr int NT = (N_OF(LOGN) * W >= PINT_INV_NT) ? PINT_INV_NT : kNT;
