@@ -988,6 +988,13 @@ hipError_t cols_run(const SpaceArgs& a, int axis, hipStream_t st) {
 
 template <typename R, int LOGL, bool SOLVE>
 hipError_t rows_one(const SpaceArgs& a, hipStream_t st) {
+    constexpr int RD = rows_default<R, SOLVE>(LOGL);
+    if constexpr (RD >= 8) {
+        // small grids (fewer than 32 row groups): groups of RD/8 rows, so the lines
+        // spread over 8 times as many workgroups
+        const long long nlines = (long long)a.nP * a.my * a.mz;
+        if (a.var_rows == 0 && (nlines + RD - 1) / RD < 32) return rows_run<R, LOGL, RD / 8, SOLVE>(a, st);
+    }
     if (a.var_rows == 1 && rows_alt<R, SOLVE>(LOGL) != rows_default<R, SOLVE>(LOGL))
         return rows_run<R, LOGL, rows_alt<R, SOLVE>(LOGL), SOLVE>(a, st);
     return rows_run<R, LOGL, rows_default<R, SOLVE>(LOGL), SOLVE>(a, st);
