@@ -728,7 +728,26 @@ GenArgs gen_args(const pint_plan* P, double* U) {
     return ga;
 }
 
-// One sweep of a plan whose time axis is not a power of two >= 8.
+InvArgs inv_args(const pint_plan* P, double* U, int form) {
+    InvArgs ia{};
+    ia.U = U;
+    ia.S = P->S;
+    ia.unscale = P->d_unscale;
+    ia.tw = P->d_twN;
+    ia.partial = P->partial;
+    ia.M = P->M;
+    ia.N = P->N;
+    ia.ldS = P->ldS;
+    ia.mx = P->mx;
+    ia.mxp = P->mxp;
+    ia.Mp = P->Mp;
+    ia.form = form;
+    return ia;
+}
+
+// One sweep of a plan on the general-length kernels (time axis not a power of
+// two >= 8, or P1 elements).  With N a power of two >= 16 the inverse is the
+// power-of-two kernel (same spectrum layout, same update and norm partials).
 pint_status one_sweep_gn(pint_plan* P, double* U, double* norms_out, Profiler* prof) {
     const GenArgs ga = gen_args(P, U);
     PROF_BEGIN(prof, "residual_rhs");
@@ -745,7 +764,10 @@ pint_status one_sweep_gn(pint_plan* P, double* U, double* norms_out, Profiler* p
     }
     int nb = 0;
     PROF_BEGIN(prof, "inverse_tdft_update");
-    HIP_TRY(pint::launch_gn_inverse(ga, P->mixed, &nb, P->st));
+    if (ga.pow2)
+        HIP_TRY(pint::launch_inverse(inv_args(P, U, ga.form), P->mixed, &nb, P->st));
+    else
+        HIP_TRY(pint::launch_gn_inverse(ga, P->mixed, &nb, P->st));
     PROF_END(prof);
     PROF_BEGIN(prof, "norm_reduce");
     HIP_TRY(pint::launch_norm_reduce(P->partial, nb, P->hd, norms_out, P->st));
@@ -775,22 +797,9 @@ pint_status one_sweep(pint_plan* P, double* U, double* norms_out, Profiler* prof
         PROF_END(prof);
     }
 
-    InvArgs ia{};
-    ia.U = U;
-    ia.S = P->S;
-    ia.unscale = P->d_unscale;
-    ia.tw = P->d_twN;
-    ia.partial = P->partial;
-    ia.M = P->M;
-    ia.N = P->N;
-    ia.ldS = P->ldS;
-    ia.mx = P->mx;
-    ia.mxp = P->mxp;
-    ia.Mp = P->Mp;
-    ia.form = fa.form;
     int nb = 0;
     PROF_BEGIN(prof, "inverse_tfft_update");
-    HIP_TRY(pint::launch_inverse(ia, P->mixed, &nb, P->st));
+    HIP_TRY(pint::launch_inverse(inv_args(P, U, fa.form), P->mixed, &nb, P->st));
     PROF_END(prof);
     PROF_BEGIN(prof, "norm_reduce");
     HIP_TRY(pint::launch_norm_reduce(P->partial, nb, P->hd, norms_out, P->st));
