@@ -977,7 +977,7 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 
 // ---------------------------------------------------------------------------
 // Forward pass in two kernels (BDF-k residual form, 2D/3D).
-// k_resid: each workgroup owns a block of 64 x slots by 4 x 4 grid lines (3D;
+// k_resid: each workgroup owns a block of 64 x slots by 8 x 4 grid lines (3D;
 // 64 x 8 lines in 2D) and marches along time, q = 0..N-1, writing the kappa^{q/N}-scaled
 // residual
 //   r~_q = kappa^{q/N} (f(t_{q+1}) + corrections + tau^{-1} s_q v
@@ -986,7 +986,7 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 // time stencil's earlier rows stay in registers.  Row q of the block is staged
 // in LDS with its halo faces, so every space stencil neighbour is an LDS read:
 // the loads per element are U, f (and the correction rows while q < k - 1) plus
-// about one halo value in 3D (0.3 in 2D), instead of one per neighbour (the
+// 0.8 halo values in 3D (0.3 in 2D), instead of one per neighbour (the
 // kernel is bound by the rate at which the texture addresser takes load
 // instructions, and neighbour lines of other workgroups mostly come from HBM).
 // The loads of row q+1 are in flight while row q is combined.  Two LDS buffers
@@ -994,29 +994,31 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 // reads.
 // k_tfft: the time FFT of Rb, a tile of W slots x N rows in LDS, stored as the
 // half spectrum.
-constexpr int kResidNT = 256;
 constexpr int kBlkX = 64;   // x slots of a block (one wave's lanes)
-// Block of a workgroup: 64 x slots by BY grid lines by BZ planes (BY BZ / 4
-// lines per lane), and the halo values it stages per row: the y and z faces (64
-// values each line) and the x neighbours of its lines.
-// 64 x 4 x 4 in 3D, 64 x 8 in 2D (measured against 64 x 4 x 2, 64 x 8 x 1 and
-// 64 x 16: the 3D shapes tie, the 2D block of 8 lines is 7% faster than 16).
+// Block of a workgroup: 64 x slots by BY grid lines by BZ planes (BY BZ / NW
+// lines per lane, NW waves), and the halo values it stages per row: the y and z
+// faces (64 values each line) and the x neighbours of its lines.
+// 3D: 64 x 8 x 4 points, 512 lanes (measured against 64 x 4 x 4 / 256 lanes, 5%
+// slower, 64 x 4 x 8 and 64 x 16 x 2 / 512 lanes, and 64 x 8 x 8 at 512 or 1024
+// lanes, which spill); 2D: 64 x 8, 256 lanes (7% faster than 64 x 16).
 template <bool IS3> struct ResidBlock {
-    static constexpr int BY = IS3 ? 4 : 8, BZ = IS3 ? 4 : 1;
+    static constexpr int BY = 8, BZ = IS3 ? 4 : 1;
+    static constexpr int NT = IS3 ? 512 : 256, NW = NT / 64;   // lanes, waves
     static constexpr int NH = 2 * BZ * kBlkX + (IS3 ? 2 * BY * kBlkX : 0) + 2 * BY * BZ;
-    static constexpr int HPL = (NH + kResidNT - 1) / kResidNT;   // halo values per lane
+    static constexpr int HPL = (NH + NT - 1) / NT;   // halo values per lane
     static constexpr int LZ = IS3 ? BZ + 2 : 1;                  // LDS planes (z halo in 3D)
     static constexpr int LY = BY + 2, LX = kBlkX + 2;
 };
-// 3D block order: regions of nxb x kRegY x kRegZ blocks (whole x rows, 8 y by 4 z
+// 3D block order: regions of nxb x kRegY x kRegZ blocks (whole x rows, 2 y by 8 z
 // blocks: about the workgroups an XCD holds at once) one after another, so the
 // y and z halo faces of most blocks are rows that co-resident workgroups of the
 // same XCD load, and come from its L2.
-constexpr int kRegY = 8, kRegZ = 4;
+constexpr int kRegY = 2, kRegZ = 8;
 template <typename RT, bool IS3>
-__global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc, int nxb, int nyb, int nzb) {
+__global__ __launch_bounds__(ResidBlock<IS3>::NT) void k_resid(FwdArgs a, int qc, int nxb, int nyb, int nzb) {
     using BL = ResidBlock<IS3>;
-    constexpr int BY = BL::BY, BZ = BL::BZ, LZ = BL::LZ, LY = BL::LY, LX = BL::LX, PT = BY * BZ / 4;
+    constexpr int BY = BL::BY, BZ = BL::BZ, LZ = BL::LZ, LY = BL::LY, LX = BL::LX, NW = BL::NW, PT = BY * BZ / NW;
+    static_assert(PT * NW == BY * BZ, "whole lines per lane");
     __shared__ double su[2][LZ * LY * LX];   // [buffer][(z + zo) LY + y + 1][x + 1], zo = 1 in 3D
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     int xb, yb, zb;
@@ -1058,7 +1060,7 @@ __global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc, int nxb, 
     long long slot[PT];
 #pragma unroll
     for (int e = 0; e < PT; ++e) {
-        const int l = wv + 4 * e, yl = l % BY, zl = l / BY;
+        const int l = wv + NW * e, yl = l % BY, zl = l / BY;
         const int y = y0 + yl, z = z0 + zl;
         lu[e] = gofs(z, y, x);
         valid[e] = lu[e] != kNoLane;
@@ -1076,7 +1078,7 @@ __global__ __launch_bounds__(kResidNT) void k_resid(FwdArgs a, int qc, int nxb, 
     int hl[BL::HPL];
 #pragma unroll
     for (int i = 0; i < BL::HPL; ++i) {
-        int h = tid + kResidNT * i;
+        int h = tid + BL::NT * i;
         ho[i] = kNoLane;
         hl[i] = -1;
         if (h < 2 * BZ * kBlkX) {
@@ -1216,9 +1218,9 @@ hipError_t fwd_split(const FwdArgs& a, int* nb, hipStream_t st) {
     while (qc < 128 && (long long)nblk * ((a.N + 2 * qc - 1) / (2 * qc)) >= 2048) qc *= 2;
     const int nq = (a.N + qc - 1) / qc;
     if (is3)
-        PINT_LAUNCH((k_resid<R, true>), dim3(nres, nq), dim3(kResidNT), 0, st, a, qc, nxb, nyb, nzb);
+        PINT_LAUNCH((k_resid<R, true>), dim3(nres, nq), dim3(ResidBlock<true>::NT), 0, st, a, qc, nxb, nyb, nzb);
     else
-        PINT_LAUNCH((k_resid<R, false>), dim3(nres, nq), dim3(kResidNT), 0, st, a, qc, nxb, nyb, nzb);
+        PINT_LAUNCH((k_resid<R, false>), dim3(nres, nq), dim3(ResidBlock<false>::NT), 0, st, a, qc, nxb, nyb, nzb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // 128-byte row segments where the N x W tile fits 64 KB of LDS
