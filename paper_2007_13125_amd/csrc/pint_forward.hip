@@ -978,7 +978,7 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 // ---------------------------------------------------------------------------
 // Forward pass in two kernels (BDF-k residual form, 2D/3D).
 // k_resid: each workgroup owns a block of 64 x slots by 8 x 4 grid lines (3D;
-// 64 x 8 lines in 2D) and marches along time, q = 0..N-1, writing the kappa^{q/N}-scaled
+// 64 x 16 lines in 2D) and marches along time, q = 0..N-1, writing the kappa^{q/N}-scaled
 // residual
 //   r~_q = kappa^{q/N} (f(t_{q+1}) + corrections + tau^{-1} s_q v
 //                       - tau^{-1} sum_{j<=min(q,k)} w_j U_{q-j} - A_h U_q)
@@ -986,7 +986,7 @@ __global__ __launch_bounds__(NT, 1) void k_fwd_cqm(FwdArgs a, int ncol, int nchu
 // time stencil's earlier rows stay in registers.  Row q of the block is staged
 // in LDS with its halo faces, so every space stencil neighbour is an LDS read:
 // the loads per element are U, f (and the correction rows while q < k - 1) plus
-// 0.8 halo values in 3D (0.3 in 2D), instead of one per neighbour (the
+// 0.8 halo values in 3D (0.16 in 2D), instead of one per neighbour (the
 // kernel is bound by the rate at which the texture addresser takes load
 // instructions, and neighbour lines of other workgroups mostly come from HBM).
 // The loads of row q+1 are in flight while row q is combined.  Two LDS buffers
@@ -1000,10 +1000,11 @@ constexpr int kBlkX = 64;   // x slots of a block (one wave's lanes)
 // faces (64 values each line) and the x neighbours of its lines.
 // 3D: 64 x 8 x 4 points, 512 lanes (measured against 64 x 4 x 4 / 256 lanes, 5%
 // slower, 64 x 4 x 8 and 64 x 16 x 2 / 512 lanes, and 64 x 8 x 8 at 512 or 1024
-// lanes, which spill); 2D: 64 x 8, 256 lanes (7% faster than 64 x 16).
+// lanes, which spill); 2D: 64 x 16, 512 lanes (3% faster than 64 x 8 or 64 x 32
+// with 512 lanes, 64 x 8 with 256, and 10% faster than 64 x 16 with 256).
 template <bool IS3> struct ResidBlock {
-    static constexpr int BY = 8, BZ = IS3 ? 4 : 1;
-    static constexpr int NT = IS3 ? 512 : 256, NW = NT / 64;   // lanes, waves
+    static constexpr int BY = IS3 ? 8 : 16, BZ = IS3 ? 4 : 1;
+    static constexpr int NT = 512, NW = NT / 64;   // lanes, waves
     static constexpr int NH = 2 * BZ * kBlkX + (IS3 ? 2 * BY * kBlkX : 0) + 2 * BY * BZ;
     static constexpr int HPL = (NH + NT - 1) / NT;   // halo values per lane
     static constexpr int LZ = IS3 ? BZ + 2 : 1;                  // LDS planes (z halo in 3D)
