@@ -1053,7 +1053,7 @@ __global__ __launch_bounds__(ResidBlock<IS3>::NT) void k_resid(FwdArgs a, int qc
         const bool in = xx >= 0 && xx < a.mx && yy >= 0 && yy < a.my && zz >= 0 && zz < a.mz;
         return in ? (((unsigned)zz * (unsigned)a.my + (unsigned)yy) * (unsigned)a.mx + (unsigned)xx) * 8u : kNoLane;
     };
-    // the lane's lines (line l = wv + 4 e of the block: y = l % BY, z = l / BY)
+    // the lane's lines (line l = wv + NW e of the block: y = l % BY, z = l / BY)
     unsigned lu[PT];
     int li[PT];
     double vt[PT], hist[7][PT];
