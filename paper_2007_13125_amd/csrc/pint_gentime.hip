@@ -102,6 +102,32 @@ __global__ __launch_bounds__(kGenNT) void k_gn_resid(GenArgs a, int W) {
     gn_resid_body(a, W, blockIdx.x, gridDim.x, gl);
 }
 
+// Residual form with a short history (BDF-k: w_j = 0 beyond j = k <= 6): one lane
+// per dof and a chunk of kGnQC rows, the k levels before the chunk and then each
+// row's level held in registers (no LDS; consecutive lanes read consecutive
+// dofs).  Same sums, in the same order, as the tile kernel below.
+constexpr int kGnQC = 32;
+__global__ __launch_bounds__(kGenNT) void k_gn_resid_short(GenArgs a) {
+    const int d = blockIdx.x * kGenNT + threadIdx.x;
+    if (d >= a.M) return;
+    const int q0 = blockIdx.y * kGnQC, q1 = min(a.N, q0 + kGnQC);
+    double w[7], hist[7];   // hist[j]: the history input at row q - j (zero before row 0)
+#pragma unroll
+    for (int j = 0; j < 7; ++j) w[j] = j <= a.jmax ? a.w[j] : 0.0;
+    hist[0] = 0.0;
+#pragma unroll
+    for (int j = 1; j < 7; ++j) hist[j] = (j <= a.jmax && q0 - j >= 0) ? hist_input(a, q0 - j, d) : 0.0;
+    for (int q = q0; q < q1; ++q) {
+        hist[0] = hist_input(a, q, d);
+        double h = 0.0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) h += w[j] * hist[j];
+        gn_resid_point(a, q, d, a.fem ? a.U[(size_t)q * a.M + d] : hist[0], h);
+#pragma unroll
+        for (int j = 6; j > 0; --j) hist[j] = hist[j - 1];
+    }
+}
+
 // Dofs per tile of the direct-sum residual: the N weights and the N x W tile of
 // levels within 64 KB of LDS.
 __host__ __device__ inline int gn_resid_width(int N) {
@@ -712,6 +738,13 @@ hipError_t launch_nl_axpy(double* U, const double* W, double* partial, int N, in
 
 hipError_t launch_gn_resid(const GenArgs& a, hipStream_t st) {
     if (a.wh && a.form == 0) return gn_resid_fft_dispatch(a, st);
+    // short histories on grids of >= 128 such workgroups (fewer: the tile kernel,
+    // whose lanes share the rows of a tile, is faster; the paper's 999 x 100 runs 16)
+    const dim3 sgrid((unsigned)((a.M + kGenNT - 1) / kGenNT), (unsigned)((a.N + kGnQC - 1) / kGnQC));
+    if (a.form == 0 && a.jmax <= 6 && (long long)sgrid.x * sgrid.y >= 128) {
+        PINT_LAUNCH(k_gn_resid_short, sgrid, dim3(kGenNT), 0, st, a);
+        return hipGetLastError();
+    }
     // dofs per workgroup: the N x W tile and the N weights within 64 KB of LDS
     const int W = gn_resid_width(a.N);
     const size_t lds = (size_t)a.N * (W + 1) * sizeof(double);

@@ -28,6 +28,7 @@ CASES = [
     (1000, 64, 2, 0.7, 1e-3),
     (127, 1024, 3, 0.5, 1e-3),   # CQ history by the 2048-point convolution
     (9, 48, 1, 0.3, 1e-2),
+    (2047, 2048, 2, 1.0, 1e-3),  # the largest line: one lane per dof in the residual
 ]
 
 

@@ -103,6 +103,9 @@ SMALL = [
     (2, (20, 13), 98, 6, 1.0, 1e-3),
     (3, (7, 5, 3), 12, 3, 1.0, 1e-3),
     (3, (6, 9, 5), 20, 2, 0.7, 1e-3),
+    # a large grid with a time axis that is not a power of two (BDF residual with
+    # one lane per dof and 32-row chunks)
+    (2, (255, 255), 100, 2, 1.0, 1e-3),
 ]
 
 
