@@ -637,14 +637,34 @@ hipError_t batch_pass_dispatch(const BatchLaunch& L, hipStream_t st) {
 }
 
 // g'(Ubar) with Ubar[x] the mean of U over the N time levels (fixed order).
-__global__ __launch_bounds__(kGenNT) void k_nl_mean_dg(const double* __restrict__ U, double* __restrict__ dg, int N,
-                                                       int M, double c3, double c1) {
-    const int d = blockIdx.x * kGenNT + threadIdx.x;
-    if (d >= M) return;
+// A workgroup of 16 waves per 64 dofs: wave w sums rows w, w + 16, ... (eight
+// loads in flight per lane), then the 16 partial sums combine in wave order.
+constexpr int kMeanWaves = 16;
+__global__ __launch_bounds__(64 * kMeanWaves) void k_nl_mean_dg(const double* __restrict__ U, double* __restrict__ dg,
+                                                               int N, int M, double c3, double c1) {
+    __shared__ double part[kMeanWaves][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int d = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int n = 0; n < N; ++n) s += U[(size_t)n * M + d];
-    const double ub = s / N;
-    dg[d] = 3.0 * c3 * ub * ub + c1;
+    if (d < M) {
+        int n = wv;
+        for (; n + 7 * kMeanWaves < N; n += 8 * kMeanWaves) {
+            double v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = U[(size_t)(n + i * kMeanWaves) * M + d];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s += v[i];
+        }
+        for (; n < N; n += kMeanWaves) s += U[(size_t)n * M + d];
+    }
+    part[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && d < M) {
+        double t = part[0][lane];
+        for (int i = 1; i < kMeanWaves; ++i) t += part[i][lane];
+        const double ub = t / N;
+        dg[d] = 3.0 * c3 * ub * ub + c1;
+    }
 }
 
 // U += W over [N][M], with per-workgroup partials (max |W|, sum of W^2 on the
@@ -722,7 +742,7 @@ hipError_t launch_batch_thomas(const Batch1D* descs, const int* bstart, int n, i
 }
 
 hipError_t launch_nl_mean_dg(const double* U, double* dg, int N, int M, double c3, double c1, hipStream_t st) {
-    PINT_LAUNCH(k_nl_mean_dg, dim3((M + kGenNT - 1) / kGenNT), dim3(kGenNT), 0, st, U, dg, N, M, c3, c1);
+    PINT_LAUNCH(k_nl_mean_dg, dim3((M + 63) / 64), dim3(64 * kMeanWaves), 0, st, U, dg, N, M, c3, c1);
     return hipGetLastError();
 }
 
