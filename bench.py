@@ -683,8 +683,9 @@ def main():
         summarize(args.summarize, args.only or HEADLINE)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): this build runs on a single "
-              f"GPU; the sharded multi-GPU design is described in DESIGN.md and is not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library runs a sweep on one "
+              f"GPU; sharding the dofs for the time FFTs and the frequencies for the spatial solves over several "
+              f"GPUs is a design, not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
