@@ -1214,9 +1214,9 @@ hipError_t fwd_split(const FwdArgs& a, int* nb, hipStream_t st) {
     const int nvirt = is3 ? nxb * ((nyb + kRegY - 1) / kRegY * kRegY) * ((nzb + kRegZ - 1) / kRegZ * kRegZ) : nblk;
     const int nres = (nvirt + 7) / 8 * 8;
     // time rows per workgroup: each chunk re-reads the k rows before it,
-    // so the longest chunk (up to 128) that still leaves >= 2048 workgroups
+    // so the longest chunk (up to 256) that still leaves >= 1024 workgroups
     int qc = 32;
-    while (qc < 128 && (long long)nblk * ((a.N + 2 * qc - 1) / (2 * qc)) >= 2048) qc *= 2;
+    while (qc < 256 && (long long)nblk * ((a.N + 2 * qc - 1) / (2 * qc)) >= 1024) qc *= 2;
     const int nq = (a.N + qc - 1) / qc;
     if (is3)
         PINT_LAUNCH((k_resid<R, true>), dim3(nres, nq), dim3(ResidBlock<true>::NT), 0, st, a, qc, nxb, nyb, nzb);
@@ -1228,7 +1228,9 @@ hipError_t fwd_split(const FwdArgs& a, int* nb, hipStream_t st) {
     constexpr int WL = 65536 / (N_OF(LOGN) * (int)sizeof(R));
     constexpr int W0 = sizeof(R) == 8 ? 16 : 32;
     constexpr int W = WL < W0 ? (WL < 2 ? 2 : WL) : W0;
-    constexpr int NT = N_OF(LOGN) * W >= 512 ? 512 : N_OF(LOGN) * W;
+    // lanes: 256 for N <= 256, else 512 (each measured ~1% ahead of the other there)
+    constexpr int NTC = LOGN <= 8 ? 256 : 512;
+    constexpr int NT = N_OF(LOGN) * W >= NTC ? NTC : N_OF(LOGN) * W;
     const int ntiles = ((a.Mp + W - 1) / W + 7) / 8 * 8;
     if (nb) *nb = ntiles;
     PINT_LAUNCH((k_tfft<R, LOGN, W, NT>), dim3(ntiles), dim3(NT), 0, st, a);
